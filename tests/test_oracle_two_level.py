@@ -1,0 +1,157 @@
+"""Pins for the oracle's two-level solve (paper Alg. 1, Alg. 2, eq. factor2).
+
+* The two-level result equals the direct solve of the global collocation
+  system of eq. Aentries (an algebraic identity; the brute-force system uses
+  no Schur complements).
+* Polynomials of per-axis degree <= p-1 are reproduced exactly at kappa = 0.
+* Manufactured plane waves converge spectrally in p (paper Sec. 4.1 reports
+  the same behaviour and a floor near 1e-13 for Poisson).
+* One box with all faces on the boundary reduces to a dense interior solve.
+* Planted mistakes in the oracle make at least one of these fail.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import brute, interface, leaf
+
+
+def _interior_coords(res):
+    return np.concatenate([bd.xi for bd in res.boxes])
+
+
+def test_face_numbering_counts():
+    bf, fb = interface.face_numbering((3, 2, 4))
+    n1, n2, n3 = 3, 2, 4
+    assert fb.shape[0] == (n1 - 1) * n2 * n3 + n1 * (n2 - 1) * n3 + n1 * n2 * (n3 - 1)
+    # every internal face is seen by exactly two boxes, on opposite sides
+    for F, (lo, hi) in enumerate(fb):
+        a_lo = list(bf[lo]).index(F)
+        a_hi = list(bf[hi]).index(F)
+        assert a_lo % 2 == 1 and a_hi == a_lo - 1
+    # boundary faces: 2*(n2 n3 + n1 n3 + n1 n2)
+    assert (bf < 0).sum() == 2 * (n2 * n3 + n1 * n3 + n1 * n2)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.config1(),
+    lambda: W.single_bump((2, 2, 2), 6, 7.0, 2),
+    lambda: W.multi_bump((2, 1, 2), 7, 9.0, 3, gaussian_source=True),
+    lambda: W.multi_bump((2, 2, 2), 8, 5.0, 5, gaussian_source=True),
+])
+def test_two_level_equals_global_solve(maker):
+    prob = maker()
+    res = interface.solve(prob)
+    u_int, u_face, _ = brute.solve_global(prob)
+    assert interface.rel_l2(res.u_i, u_int) < 1e-12
+    assert interface.rel_l2(res.u_face, u_face) < 1e-12
+
+
+@pytest.mark.parametrize("p", [5, 7])
+def test_polynomial_exactness(p):
+    prob = W.polynomial((2, 2, 1), p)
+    res = interface.solve(prob)
+    assert interface.rel_l2(res.u_i.ravel(), prob.u_exact(_interior_coords(res))) < 1e-12
+    mm = (p - 2) ** 2
+    # interface values too: the face nodes of the lower box of every internal face
+    for F, (lo, _) in enumerate(res.face_boxes):
+        a = list(res.box_faces[lo]).index(F)
+        xb = res.boxes[lo].xb[a * mm:(a + 1) * mm]
+        np.testing.assert_allclose(res.u_face[F * mm:(F + 1) * mm], prob.u_exact(xb),
+                                   atol=1e-11 * np.abs(prob.u_exact(xb)).max())
+
+
+def test_spectral_convergence_plane_wave():
+    errs = []
+    for p in (6, 8, 10, 12):
+        prob = W.plane_wave_sine((2, 2, 2), p, 2.0, 1)
+        res = interface.solve(prob)
+        errs.append(interface.rel_l2(res.u_i.ravel(), prob.u_exact(_interior_coords(res))))
+    assert errs[0] < 1e-5 and errs[-1] < 1e-13
+    for a, b in zip(errs, errs[1:]):
+        assert b < a * 1e-2  # each +2 in p gains at least two digits until the floor
+
+
+def test_helmholtz_greens_function_accuracy():
+    # Paper Sec. 4.1 problem (kappa = 16 on [-1.1,0.1]x[1,2]x[1.2,2.2]).  The
+    # paper reports floors near 1e-11; at 2x2x2 boxes and p = 12 the error is
+    # still discretisation-limited, so only a loose bound is pinned.
+    prob = W.helmholtz_greens((2, 2, 2), 12, 16.0)
+    res = interface.solve(prob)
+    err = interface.rel_l2(res.u_i.ravel(), prob.u_exact(_interior_coords(res)))
+    assert err < 1e-4
+
+
+def test_single_box_is_dense_solve():
+    prob = W.multi_bump((1, 1, 1), 7, 6.0, 9, gaussian_source=True)
+    res = interface.solve(prob)
+    bd = res.boxes[0]
+    ub = prob.g(bd.xb)
+    ui = np.linalg.solve(bd.blocks.A_ii, bd.f_int - bd.blocks.A_ib @ ub)
+    np.testing.assert_allclose(res.u_i[0], ui, rtol=0, atol=1e-12 * np.abs(ui).max())
+    assert res.T_ff.shape == (0, 0)
+
+
+# ---- planted mistakes: each must be caught by one of the pins above -------------
+
+def _caught(monkeypatch, target, name, bad):
+    monkeypatch.setattr(target, name, bad)
+    prob = W.multi_bump((2, 2, 2), 6, 5.0, 5, gaussian_source=True)
+    res = interface.solve(prob)
+    u_int, _, _ = brute.solve_global(prob)
+    return interface.rel_l2(res.u_i, u_int) > 1e-8
+
+
+def test_planted_dropped_abb_is_caught(monkeypatch):
+    orig = leaf.leaf_reduce
+
+    def bad(blk, f):
+        r = orig(blk, f)
+        r.T = r.T - blk.A_bb   # Alg. 1 as printed, without A_bb
+        return r
+
+    assert _caught(monkeypatch, leaf, "leaf_reduce", bad)
+
+
+def test_planted_wrong_load_sign_is_caught(monkeypatch):
+    orig = leaf.leaf_reduce
+
+    def bad(blk, f):
+        r = orig(blk, f)
+        r.g = -r.g
+        return r
+
+    assert _caught(monkeypatch, leaf, "leaf_reduce", bad)
+
+
+def test_planted_transposed_face_is_caught(monkeypatch):
+    orig = interface.face_values
+
+    def bad(prob, boxes, box_faces, u_face):
+        m = prob.p - 2
+        ub = orig(prob, boxes, box_faces, u_face)
+        f0 = ub[:, :m * m].reshape(-1, m, m).transpose(0, 2, 1).reshape(-1, m * m)
+        ub[:, :m * m] = f0
+        return ub
+
+    assert _caught(monkeypatch, interface, "face_values", bad)
+
+
+def test_planted_neumann_sign_is_caught():
+    # a wrong outward sign on one face breaks the flux of a linear function
+    p = 6
+    h = (0.5,) * 3
+    N = leaf.neumann_rows(p, h)
+    xi, xb = leaf.box_node_coords((0, 0, 0), h, p)
+    a = np.array([1.0, 2.0, 3.0])
+    ii, fb = leaf.interior_full_index(p), leaf.face_full_index(p)
+    full = np.zeros((p ** 3, 3))
+    full[ii], full[fb] = xi, xb
+    good = N[:, np.r_[ii, fb]] @ np.r_[xi @ a, xb @ a]
+    Nbad = N.copy()
+    mm = (p - 2) ** 2
+    Nbad[:mm] *= -1
+    bad = Nbad[:, np.r_[ii, fb]] @ np.r_[xi @ a, xb @ a]
+    normals = np.repeat(np.array([[-1, 0, 0], [1, 0, 0], [0, -1, 0], [0, 1, 0], [0, 0, -1], [0, 0, 1]]), mm, 0)
+    assert np.allclose(good, normals @ a)
+    assert not np.allclose(bad, normals @ a)
