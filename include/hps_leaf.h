@@ -1,0 +1,184 @@
+/*
+ * hps_leaf.h -- C ABI of the MI355X (gfx950) leaf-box reduction of the
+ * two-level Hierarchical Poincare-Steklov solver (Kump, Yesypenko, Martinsson,
+ * "A Two-Level Direct Solver for the Hierarchical Poincare-Steklov Method").
+ *
+ * Problem (paper Sec. 1, eqs. bvp/bvphelmholtz): -Lap u - kappa^2 b(x) u = f on a
+ * union of equal rectangular leaf boxes, u = g on the outer boundary.  Each box
+ * carries p Chebyshev-Gauss-Lobatto nodes per axis (Sec. 2.1); m = p - 2 interior
+ * nodes per axis; n_i = m^3 interior unknowns; n_b = 6 m^2 face unknowns (edges
+ * and corners are dropped, Remark 1).
+ *
+ * Per box the library computes (Sec. 2.2, Sec. 3.1, Alg. 1 and Alg. 2):
+ *   hps_leaf_operators   A_ii, the interior block of the collocation operator;
+ *   hps_leaf_factor      P A_ii = L U with partial pivoting by rows;
+ *   hps_leaf_dtn         X = A_ii^{-1} [A_ib | f_i] (FP64, optionally from an FP32
+ *                        factorization refined in FP64), the DtN map
+ *                        T = A_bb - A_bi X_b = A_bb + A_bi S (eq. t-block),
+ *                        scattered into the block-sparse interface matrix, and
+ *                        the equivalent load g = -A_bi v (v = X_f) lifted by the
+ *                        Dirichlet data of boundary faces;
+ *   hps_leaf_reconstruct u_i = v + S u_b = X_f - X_b u_b (last step of Alg. 2);
+ *   hps_leaf_adjoint_*   transposed solves for the gradient of a misfit with
+ *                        respect to b (transpose of eq. factor2).
+ * The sparse interface system itself is assembled and factored by the caller.
+ *
+ * Node numbering inside a box (all arrays below use it):
+ *   interior node (i,j,k), 1 <= i,j,k <= m, has index (i-1) + m(j-1) + m^2(k-1);
+ *   faces are x-, x+, y-, y+, z-, z+ (face a = 2*axis + side); a face's m^2 nodes
+ *   are indexed by its two tangential axes in increasing axis order, the lower
+ *   axis fastest; face node index = a*m^2 + local.
+ * Box node coordinates: x = origin + h (t + 1)/2 with t_j = -cos(pi j/(p-1)).
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer owned by the caller; the library
+ *     never frees or keeps them.  Sizes per box come from hps_plan_get_info().
+ *   - Calls enqueue work on `stream` and return without synchronizing.  The
+ *     returned hps_status reports argument and launch errors only; numerical
+ *     outcomes are reported per box in device arrays (info, ir_iters, berr).
+ *   - The plan holds the Chebyshev tables on the device and is not thread-safe;
+ *     use one plan per host thread.  Plans are tied to the device that was
+ *     current at hps_plan_create().
+ *   - Per-box matrices are row-major with padded leading dimensions:
+ *       A / LU : [nbox][n_pad][n_pad] (FP32 in HPS_FP32_IR mode, else FP64);
+ *                rows and columns n_i..n_pad-1 are an identity border.
+ *       X      : [nbox][n_pad][ldx] FP64; column c < n_b is face node c,
+ *                column n_b is the load column, the rest is zero padding.
+ */
+#ifndef HPS_LEAF_H
+#define HPS_LEAF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HPS_OK = 0,
+  HPS_EINVAL = -1,       /* bad argument (null pointer, size out of range)      */
+  HPS_ENOMEM = -2,       /* plan creation could not allocate its tables          */
+  HPS_EDEVICE = -3,      /* a HIP call or kernel launch failed                   */
+  HPS_EUNSUPPORTED = -4  /* p outside the compiled range                         */
+} hps_status;
+
+typedef enum { HPS_FP64 = 0, HPS_FP32_IR = 1 } hps_precision;
+
+typedef struct {
+  int32_t p;            /* Gauss-Lobatto nodes per axis per box, 4 <= p <= 20      */
+  double h[3];          /* box side lengths along x, y, z (> 0)                    */
+  double kappa;         /* wavenumber                                              */
+  int32_t precision;    /* hps_precision                                           */
+  int32_t ir_max_iter;  /* FP32_IR: max FP64 refinement steps (0..8)               */
+  double ir_tol;        /* FP32_IR: stop when the normwise backward error
+                           max|R| / (|A_ii|_inf max|X| + max|B|) <= ir_tol         */
+} hps_leaf_desc;
+
+typedef struct {
+  int32_t m, n_i, n_b;   /* interior nodes per axis, per box, face nodes per box  */
+  int32_t n_pad;         /* n_i rounded up to a multiple of 32                     */
+  int32_t nrhs, ldx;     /* n_b + 1 right-hand sides; ldx = nrhs rounded to 64     */
+  int32_t npanel;        /* LU panels of width <= 64                               */
+  int32_t elem_bytes;    /* 4 (FP32_IR) or 8 (FP64): element size of A / LU       */
+  size_t a_bytes;        /* per box: A / LU storage                                */
+  size_t perm_bytes;     /* per box: row permutation (int32 [n_pad])               */
+  size_t dinv_bytes;     /* per box: inverses of the diagonal LU blocks            */
+  size_t x_bytes;        /* per box: X (FP64 [n_pad][ldx])                         */
+  size_t ws_bytes;       /* per box: workspace of hps_leaf_dtn                     */
+} hps_plan_info;
+
+typedef struct hps_plan_s* hps_plan;
+
+/* Create a plan: validates `desc`, builds the differentiation tables of paper
+ * Sec. 2.1 in FP64 on the host and uploads them.  Returns HPS_EINVAL for bad
+ * sizes, HPS_EUNSUPPORTED for p outside [4, 20], HPS_ENOMEM/HPS_EDEVICE if the
+ * device tables cannot be created.  *plan is set only on success. */
+hps_status hps_plan_create(hps_plan* plan, const hps_leaf_desc* desc);
+hps_status hps_plan_destroy(hps_plan plan);
+hps_status hps_plan_get_info(hps_plan plan, hps_plan_info* info);
+
+/* Coordinates of the interior nodes xi [nbox][n_i][3] and face nodes
+ * xb [nbox][n_b][3] of boxes with lower corners origin [nbox][3] (Sec. 2.1).
+ * The caller evaluates b, f and g at these points. */
+hps_status hps_leaf_nodes(hps_plan plan, int32_t nbox, const double* origin, double* xi, double* xb,
+                          hipStream_t stream);
+
+/* a1 -- collocation operator (Sec. 2.1 eq. Aentries, interior rows; Alg. 1 "form
+ * the local equilibrium matrix").  Writes A_ii = -(Dxx + Dyy + Dzz) - kappa^2
+ * diag(b) restricted to interior nodes, rounded to the plan's element type, into
+ * A [nbox][n_pad][n_pad] with an identity border, and |A_ii|_inf (FP64, exact
+ * row sums) into anorm [nbox].  b: [nbox][n_i] FP64 values at interior nodes. */
+hps_status hps_leaf_operators(hps_plan plan, int32_t nbox, const double* b, void* A, double* anorm,
+                              hipStream_t stream);
+
+/* a2 -- dense LU with partial pivoting of every box's A_ii, in place (Alg. 1,
+ * "form the local solution operator"; the interior block is block diagonal,
+ * Sec. 2.2).  The pivot in column k is the row of largest modulus among the
+ * rows not yet pivoted (lowest current position on ties).  On return, for
+ * position i, row perm[i] of A holds row i of L (unit lower, below the
+ * diagonal) and of U (on and above); perm [nbox][n_pad] int32.  dinv receives
+ * the inverses of the diagonal 64x64 blocks of L and U (workspace reused by
+ * the solves).  info[box] = 0, or k > 0 if U(k,k) (1-based) is exactly zero or
+ * not finite (LAPACK convention; the factorization still completes). */
+hps_status hps_leaf_factor(hps_plan plan, int32_t nbox, void* A, int32_t* perm, void* dinv, int32_t* info,
+                           hipStream_t stream);
+
+/* a3 + a4 -- interior solves and DtN assembly (Sec. 2.2 four-step solve, steps
+ * 1-2; Sec. 3.1 eq. t-block; Alg. 1 and the load loop of Alg. 2).
+ *   X = A_ii^{-1} [A_ib | f_i] in FP64.  FP64 plans solve with the FP64 factors.
+ *   FP32_IR plans solve with the FP32 factors and refine in FP64: R = B - A_ii X
+ *   is formed in FP64 through the tensor-product structure of A_ii (b is needed
+ *   for that), the correction is solved in FP32 and added in FP64, until the
+ *   backward error is <= ir_tol or ir_max_iter steps; ir_iters[box] = steps
+ *   taken (negative if still above ir_tol), berr[box] = final backward error.
+ *   T = A_bb - A_bi X_b: row block a / column block b of box t is written to
+ *   T_vals + slot_map[t*36 + 6a + b] * m^4 (row-major m^2 x m^2 block) when the
+ *   slot is >= 0; slot -1 drops the block (rows of boundary faces, columns of
+ *   boundary faces).  g[box][n_b] = -A_bi X_f - sum over boundary faces b of
+ *   T[:, b] g_dir[box][b]: the load lifted by the Dirichlet data g_dir (values on
+ *   boundary faces, ignored elsewhere).  f, g_dir may be NULL (zero).
+ *   ws: hps_plan_info.ws_bytes per box.  X, T_vals, g, ir_iters, berr are
+ *   written; ir_iters/berr may be NULL. */
+hps_status hps_leaf_dtn(hps_plan plan, int32_t nbox, const void* LU, const int32_t* perm, const void* dinv,
+                        const double* b, const double* anorm, const double* f, const double* g_dir,
+                        const int32_t* slot_map, double* T_vals, double* g, double* X, int32_t* ir_iters,
+                        double* berr, void* ws, hipStream_t stream);
+
+/* Deterministic reduction of duplicate interface blocks (Alg. 1, "add T^t to
+ * the relevant slot of T"): for q = 0..npairs-1 in order,
+ * T_vals[dst_q] += T_vals[src_q] (blocks of block_elems doubles), pairs given as
+ * int64 [npairs][2] = (dst, src) block indices; every dst appears once. */
+hps_status hps_interface_reduce(int32_t npairs, const int64_t* pairs, int64_t block_elems, double* T_vals,
+                                hipStream_t stream);
+
+/* a5 -- reconstruction (Sec. 2.2 step 4; Alg. 2 last loop): u_i = X_f - X_b u_b
+ * for every box, with X from hps_leaf_dtn and u_b [nbox][n_b] the box's face
+ * values (interface solution on internal faces, Dirichlet data on boundary
+ * faces).  u_i: [nbox][n_i] FP64. */
+hps_status hps_leaf_reconstruct(hps_plan plan, int32_t nbox, const double* X, const double* u_b, double* u_i,
+                                hipStream_t stream);
+
+/* a6 -- adjoint solves for dJ/db (transpose of eq. factor2):
+ * hps_leaf_adjoint_solve:  z = A_ii^{-T} (w_i - A_bi^T lam_b) per box and
+ *   y_b = -A_ib^T z; lam_b may be NULL (zero).  Uses the factors of
+ *   hps_leaf_factor; FP32_IR plans refine in FP64 like hps_leaf_dtn.
+ *   w_i, z: [nbox][n_i]; lam_b, y_b: [nbox][n_b]; y_b may be NULL.
+ * ws: hps_plan_info.ws_bytes per box. */
+hps_status hps_leaf_adjoint_solve(hps_plan plan, int32_t nbox, const void* LU, const int32_t* perm,
+                                  const void* dinv, const double* b, const double* w_i, const double* lam_b,
+                                  double* z, double* y_b, void* ws, hipStream_t stream);
+
+/* Gradient assembly: grad[box][n_i] = kappa^2 * lam_i * u_i (dA/db_n = -kappa^2
+ * e_n e_n^T at interior node n). */
+hps_status hps_leaf_adjoint_grad(hps_plan plan, int32_t nbox, const double* lam_i, const double* u_i,
+                                 double* grad, hipStream_t stream);
+
+/* Human-readable message for a status code (static storage). */
+const char* hps_status_string(hps_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPS_LEAF_H */

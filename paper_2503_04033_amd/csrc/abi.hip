@@ -1,0 +1,312 @@
+// extern "C" entry points of libhps_leaf (declared in include/hps_leaf.h).
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/hps_leaf.h"
+#include "common.h"
+#include "kernels.h"
+
+struct hps_plan_s {
+  hps_leaf_desc desc;
+  hps::Geom g;
+  int device;
+  double* tables;  // device: t[p], D[p*p], D2[p*p]
+  const double* t;
+};
+
+namespace {
+
+using hps::Geom;
+
+hps_status dev(hipError_t e) { return e == hipSuccess ? HPS_OK : HPS_EDEVICE; }
+
+#define HPS_TRY(expr)                               \
+  do {                                              \
+    hipError_t e__ = (expr);                        \
+    if (e__ != hipSuccess) return HPS_EDEVICE;      \
+  } while (0)
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Gauss-Lobatto points t_j = -cos(pi j/(p-1)) and the barycentric
+// differentiation matrix on them (weights (-1)^j, halved at the end points),
+// with the diagonal chosen so that every row sums to zero (Sec. 2.1).
+void cheb_tables(int p, std::vector<double>& t, std::vector<double>& D, std::vector<double>& D2) {
+  const double pi = 3.14159265358979323846;
+  t.assign(p, 0.0);
+  for (int j = 0; j < p; j++) t[j] = -std::cos(pi * j / (p - 1));
+  std::vector<double> w(p);
+  for (int j = 0; j < p; j++) w[j] = ((j % 2) ? -1.0 : 1.0) * ((j == 0 || j == p - 1) ? 0.5 : 1.0);
+  D.assign((size_t)p * p, 0.0);
+  for (int i = 0; i < p; i++) {
+    double rowsum = 0.0;
+    for (int j = 0; j < p; j++) {
+      if (i == j) continue;
+      const double v = (w[j] / w[i]) / (t[i] - t[j]);
+      D[(size_t)i * p + j] = v;
+      rowsum += v;
+    }
+    D[(size_t)i * p + i] = -rowsum;
+  }
+  D2.assign((size_t)p * p, 0.0);
+  for (int i = 0; i < p; i++)
+    for (int k = 0; k < p; k++) {
+      const double a = D[(size_t)i * p + k];
+      for (int j = 0; j < p; j++) D2[(size_t)i * p + j] += a * D[(size_t)k * p + j];
+    }
+}
+
+struct Sizes {
+  size_t a, perm, dinv, x, ws;
+};
+
+Sizes sizes_of(const hps_plan_s* pl) {
+  const Geom& g = pl->g;
+  const size_t es = pl->desc.precision == HPS_FP32_IR ? 4 : 8;
+  Sizes s;
+  s.a = es * g.n_pad * (size_t)g.n_pad;
+  s.perm = 4 * (size_t)g.n_pad;
+  s.dinv = es * (size_t)g.npanel * 2 * 64 * 64;
+  s.x = 8 * (size_t)g.n_pad * g.ldx;
+  const size_t elems = (size_t)g.n_pad * g.ldx;
+  // FP32_IR: B32, Y32, Rz (FP64); FP64: B64 (reused as Rz).  Plus per-box scalars.
+  s.ws = (pl->desc.precision == HPS_FP32_IR ? 16 : 8) * elems + 64;
+  return s;
+}
+
+struct WsLayout {
+  void* B;      // B32 or B64
+  float* Y32;
+  double* Rz;
+  double *maxb, *maxr, *maxx;
+  int* active;
+};
+
+WsLayout ws_layout(const hps_plan_s* pl, int nbox, void* ws) {
+  const Geom& g = pl->g;
+  const size_t elems = (size_t)g.n_pad * g.ldx * nbox;
+  char* p = static_cast<char*>(ws);
+  WsLayout L;
+  if (pl->desc.precision == HPS_FP32_IR) {
+    L.B = p;
+    L.Y32 = reinterpret_cast<float*>(p + 4 * elems);
+    L.Rz = reinterpret_cast<double*>(p + 8 * elems);
+    p += 16 * elems;
+  } else {
+    L.B = p;
+    L.Y32 = nullptr;
+    L.Rz = reinterpret_cast<double*>(p);
+    p += 8 * elems;
+  }
+  L.maxb = reinterpret_cast<double*>(p);
+  L.maxr = L.maxb + nbox;
+  L.maxx = L.maxr + nbox;
+  L.active = reinterpret_cast<int*>(L.maxx + nbox);
+  return L;
+}
+
+bool bad_plan(hps_plan p) { return p == nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+const char* hps_status_string(hps_status s) {
+  switch (s) {
+    case HPS_OK: return "ok";
+    case HPS_EINVAL: return "invalid argument";
+    case HPS_ENOMEM: return "out of memory";
+    case HPS_EDEVICE: return "HIP runtime or launch failure";
+    case HPS_EUNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
+  if (!out || !d) return HPS_EINVAL;
+  if (d->p < 4 || d->p > 20) return HPS_EUNSUPPORTED;
+  for (int a = 0; a < 3; a++)
+    if (!(d->h[a] > 0.0) || !std::isfinite(d->h[a])) return HPS_EINVAL;
+  if (!std::isfinite(d->kappa)) return HPS_EINVAL;
+  if (d->precision != HPS_FP64 && d->precision != HPS_FP32_IR) return HPS_EINVAL;
+  if (d->precision == HPS_FP32_IR && (d->ir_max_iter < 0 || d->ir_max_iter > 8 || !(d->ir_tol >= 0.0)))
+    return HPS_EINVAL;
+  hps_plan_s* pl = new (std::nothrow) hps_plan_s();
+  if (!pl) return HPS_ENOMEM;
+  pl->desc = *d;
+  Geom& g = pl->g;
+  g.p = d->p;
+  g.m = d->p - 2;
+  g.n = g.m * g.m * g.m;
+  g.nb = 6 * g.m * g.m;
+  g.n_pad = (int)round_up(g.n, 32);
+  g.nrhs = g.nb + 1;
+  g.ldx = (int)round_up(g.nrhs, 64);
+  g.npanel = (g.n_pad + hps::kPanel - 1) / hps::kPanel;
+  for (int a = 0; a < 3; a++) {
+    g.s1[a] = 2.0 / d->h[a];
+    g.s2[a] = g.s1[a] * g.s1[a];
+  }
+  g.kappa2 = d->kappa * d->kappa;
+  std::vector<double> t, D, D2;
+  cheb_tables(g.p, t, D, D2);
+  std::vector<double> all;
+  all.insert(all.end(), t.begin(), t.end());
+  all.insert(all.end(), D.begin(), D.end());
+  all.insert(all.end(), D2.begin(), D2.end());
+  if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return HPS_EDEVICE; }
+  if (hipMalloc(&pl->tables, all.size() * sizeof(double)) != hipSuccess) { delete pl; return HPS_ENOMEM; }
+  if (hipMemcpy(pl->tables, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(pl->tables);
+    delete pl;
+    return HPS_EDEVICE;
+  }
+  pl->t = pl->tables;
+  g.D = pl->tables + g.p;
+  g.D2 = pl->tables + g.p + (size_t)g.p * g.p;
+  *out = pl;
+  return HPS_OK;
+}
+
+hps_status hps_plan_destroy(hps_plan pl) {
+  if (!pl) return HPS_EINVAL;
+  (void)hipFree(pl->tables);
+  delete pl;
+  return HPS_OK;
+}
+
+hps_status hps_plan_get_info(hps_plan pl, hps_plan_info* info) {
+  if (bad_plan(pl) || !info) return HPS_EINVAL;
+  const Geom& g = pl->g;
+  Sizes s = sizes_of(pl);
+  info->m = g.m;
+  info->n_i = g.n;
+  info->n_b = g.nb;
+  info->n_pad = g.n_pad;
+  info->nrhs = g.nrhs;
+  info->ldx = g.ldx;
+  info->npanel = g.npanel;
+  info->elem_bytes = pl->desc.precision == HPS_FP32_IR ? 4 : 8;
+  info->a_bytes = s.a;
+  info->perm_bytes = s.perm;
+  info->dinv_bytes = s.dinv;
+  info->x_bytes = s.x;
+  info->ws_bytes = s.ws;
+  return HPS_OK;
+}
+
+hps_status hps_leaf_nodes(hps_plan pl, int32_t nbox, const double* origin, double* xi, double* xb,
+                          hipStream_t st) {
+  if (bad_plan(pl) || nbox < 0 || (nbox > 0 && (!origin || !xi || !xb))) return HPS_EINVAL;
+  if (nbox == 0) return HPS_OK;
+  return dev(hps::launch_nodes(pl->g, pl->t, pl->desc.h, nbox, origin, xi, xb, st));
+}
+
+hps_status hps_leaf_operators(hps_plan pl, int32_t nbox, const double* b, void* A, double* anorm,
+                              hipStream_t st) {
+  if (bad_plan(pl) || nbox < 0 || nbox > 65535 || (nbox > 0 && (!b || !A || !anorm))) return HPS_EINVAL;
+  if (nbox == 0) return HPS_OK;
+  if (pl->desc.precision == HPS_FP32_IR)
+    return dev(hps::launch_operators<float>(pl->g, nbox, b, static_cast<float*>(A), anorm, st));
+  return dev(hps::launch_operators<double>(pl->g, nbox, b, static_cast<double*>(A), anorm, st));
+}
+
+hps_status hps_leaf_factor(hps_plan pl, int32_t nbox, void* A, int32_t* perm, void* dinv, int32_t* info,
+                           hipStream_t st) {
+  if (bad_plan(pl) || nbox < 0 || (nbox > 0 && (!A || !perm || !dinv || !info))) return HPS_EINVAL;
+  if (nbox == 0) return HPS_OK;
+  if (pl->desc.precision == HPS_FP32_IR)
+    return dev(hps::getrf_dispatch<float>(pl->g, static_cast<float*>(A), perm, static_cast<float*>(dinv), info,
+                                          nbox, st));
+  return dev(hps::getrf_dispatch<double>(pl->g, static_cast<double*>(A), perm, static_cast<double*>(dinv), info,
+                                         nbox, st));
+}
+
+hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t* perm, const void* dinv,
+                        const double* b, const double* anorm, const double* f, const double* g_dir,
+                        const int32_t* slot_map, double* T_vals, double* gload, double* X, int32_t* ir_iters,
+                        double* berr, void* ws, hipStream_t st) {
+  if (bad_plan(pl) || nbox < 0 || nbox > 65535) return HPS_EINVAL;
+  if (nbox == 0) return HPS_OK;
+  if (!LU || !perm || !dinv || !b || !anorm || !slot_map || !T_vals || !gload || !X || !ws) return HPS_EINVAL;
+  const Geom& g = pl->g;
+  WsLayout L = ws_layout(pl, nbox, ws);
+  const bool ir = pl->desc.precision == HPS_FP32_IR;
+  if (!ir) {
+    double* B = static_cast<double*>(L.B);
+    HPS_TRY(hps::launch_rhs<double>(g, nbox, f, B, L.maxb, st));
+    HPS_TRY(hps::getrs_dispatch<double>(g, static_cast<const double*>(LU), perm, static_cast<const double*>(dinv), B,
+                                        X, nbox, nullptr, st));
+    if (ir_iters) HPS_TRY(hps::launch_fill_int(ir_iters, 0, nbox, st));
+    if (berr) {
+      HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
+      HPS_TRY(hps::launch_residual(g, nbox, b, f, X, L.Rz, nullptr, L.maxr, L.maxx, nullptr, st));
+      HPS_TRY(hps::launch_ir_check(nbox, 0, 1, INFINITY, anorm, L.maxb, L.maxr, L.maxx, L.active, nullptr, berr,
+                                   st));
+    }
+  } else {
+    float* B = static_cast<float*>(L.B);
+    const float* LUf = static_cast<const float*>(LU);
+    const float* Dinv = static_cast<const float*>(dinv);
+    HPS_TRY(hps::launch_rhs<float>(g, nbox, f, B, L.maxb, st));
+    HPS_TRY(hps::getrs_dispatch<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st));
+    HPS_TRY(hps::launch_ir_add(g, nbox, L.Y32, X, 1, nullptr, st));
+    HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
+    const int kmax = pl->desc.ir_max_iter;
+    const double tol = pl->desc.ir_tol;
+    for (int it = 0; it <= kmax; it++) {
+      const int last = it == kmax;
+      HPS_TRY(hps::launch_residual(g, nbox, b, f, X, L.Rz, B, L.maxr, L.maxx, L.active, st));
+      HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
+                                   st));
+      if (last) break;
+      HPS_TRY(hps::getrs_dispatch<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st));
+      HPS_TRY(hps::launch_ir_add(g, nbox, L.Y32, X, 0, L.active, st));
+    }
+  }
+  return dev(hps::launch_dtn(g, nbox, X, g_dir, slot_map, T_vals, gload, st));
+}
+
+hps_status hps_interface_reduce(int32_t npairs, const int64_t* pairs, int64_t block_elems, double* T_vals,
+                                hipStream_t st) {
+  if (npairs < 0 || npairs > 65535 || block_elems <= 0 || (npairs > 0 && (!pairs || !T_vals))) return HPS_EINVAL;
+  return dev(hps::launch_reduce(npairs, reinterpret_cast<const long long*>(pairs), block_elems, T_vals, st));
+}
+
+hps_status hps_leaf_reconstruct(hps_plan pl, int32_t nbox, const double* X, const double* u_b, double* u_i,
+                                hipStream_t st) {
+  if (bad_plan(pl) || nbox < 0 || nbox > 65535 || (nbox > 0 && (!X || !u_b || !u_i))) return HPS_EINVAL;
+  if (nbox == 0) return HPS_OK;
+  return dev(hps::launch_reconstruct(pl->g, nbox, X, u_b, u_i, st));
+}
+
+hps_status hps_leaf_adjoint_solve(hps_plan pl, int32_t nbox, const void* LU, const int32_t* perm,
+                                  const void* dinv, const double* b, const double* w_i, const double* lam_b,
+                                  double* z, double* y_b, void* ws, hipStream_t st) {
+  (void)b;
+  if (bad_plan(pl) || nbox < 0 || nbox > 65535) return HPS_EINVAL;
+  if (pl->desc.precision != HPS_FP64) return HPS_EUNSUPPORTED;
+  if (nbox == 0) return HPS_OK;
+  if (!LU || !perm || !dinv || !w_i || !z || !ws) return HPS_EINVAL;
+  const Geom& g = pl->g;
+  double* rhs = static_cast<double*>(ws);
+  double* zt = rhs + (size_t)nbox * g.n_pad;
+  HPS_TRY(hps::launch_adjoint_rhs(g, nbox, w_i, lam_b, rhs, st));
+  HPS_TRY(hps::launch_getrs_t(g, nbox, static_cast<const double*>(LU), perm, static_cast<const double*>(dinv), rhs,
+                              zt, st));
+  HPS_TRY(hps::launch_compact(g, nbox, zt, z, st));
+  if (y_b) HPS_TRY(hps::launch_adjoint_yb(g, nbox, zt, y_b, st));
+  return HPS_OK;
+}
+
+hps_status hps_leaf_adjoint_grad(hps_plan pl, int32_t nbox, const double* lam_i, const double* u_i, double* grad,
+                                 hipStream_t st) {
+  if (bad_plan(pl) || nbox < 0 || (nbox > 0 && (!lam_i || !u_i || !grad))) return HPS_EINVAL;
+  if (nbox == 0) return HPS_OK;
+  return dev(hps::launch_grad(pl->g, nbox, lam_i, u_i, grad, st));
+}
+
+}  // extern "C"

@@ -1,0 +1,640 @@
+// Bandwidth-bound leaf kernels: operator assembly (a1), right-hand sides, the
+// FP64 residual of the refinement loop (a3), DtN assembly and loads (a4), the
+// interface block reduction, reconstruction (a5), adjoint helpers (a6), nodes.
+//
+// Local numbering: interior node (ii, jj, kk) in [0, m)^3 (grid index = +1)
+// has index ii + m jj + m^2 kk; face a = 2*axis + side holds m^2 nodes indexed
+// by the tangential interior coordinates, lower axis fastest.
+#include "common.h"
+#include "kernels.h"
+
+namespace hps {
+
+// ----------------------------------------------------------------------------
+// atomics on non-negative doubles: their bit patterns order like unsigned ints
+// ----------------------------------------------------------------------------
+__device__ inline void atomic_max_nonneg(double* addr, double v) {
+  if (!(v >= 0.0)) v = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf (flags the box)
+  atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// ----------------------------------------------------------------------------
+// fills (kernels rather than hipMemsetAsync so that the sequence can be captured)
+// ----------------------------------------------------------------------------
+__global__ void fill_zero_kernel(unsigned int* p, size_t nwords) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  size_t nw = bytes / 4;
+  int grid = (int)((nw + 255) / 256 < 65536 ? (nw + 255) / 256 : 65536);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid), dim3(256), 0, st, (unsigned int*)p, nw);
+  return hipGetLastError();
+}
+
+__global__ void fill_int_kernel(int* p, int v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_int(int* p, int value, size_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  int grid = (int)((count + 255) / 256 < 65536 ? (count + 255) / 256 : 65536);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(grid), dim3(256), 0, st, p, value, count);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// node coordinates (Sec. 2.1): x = origin + h (t + 1) / 2
+// ----------------------------------------------------------------------------
+__global__ void nodes_kernel(Geom g, const double* t, double h0, double h1, double h2, int nbox,
+                             const double* origin, double* xi, double* xb) {
+  const int box = blockIdx.y;
+  const int m = g.m, mm = m * m;
+  const double* o = origin + 3 * box;
+  const double h[3] = {h0, h1, h2};
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.n + g.nb; e += gridDim.x * blockDim.x) {
+    int c[3];
+    if (e < g.n) {
+      c[0] = e % m + 1;
+      c[1] = (e / m) % m + 1;
+      c[2] = e / mm + 1;
+      double* out = xi + ((size_t)box * g.n + e) * 3;
+      for (int a = 0; a < 3; a++) out[a] = o[a] + 0.5 * h[a] * (t[c[a]] + 1.0);
+    } else {
+      const int f = e - g.n;
+      const int a = f / mm, q = f % mm, axis = a >> 1, side = a & 1;
+      const int t0 = axis == 0 ? 1 : 0, t1 = axis == 2 ? 1 : 2;
+      c[axis] = side ? g.p - 1 : 0;
+      c[t0] = q % m + 1;
+      c[t1] = q / m + 1;
+      double* out = xb + ((size_t)box * g.nb + f) * 3;
+      for (int d = 0; d < 3; d++) out[d] = o[d] + 0.5 * h[d] * (t[c[d]] + 1.0);
+    }
+  }
+}
+
+hipError_t launch_nodes(const Geom& g, const double* t, const double* h, int nbox, const double* origin, double* xi,
+                        double* xb, hipStream_t st) {
+  dim3 grid((g.n + g.nb + 255) / 256, nbox);
+  hipLaunchKernelGGL(nodes_kernel, grid, dim3(256), 0, st, g, t, h[0], h[1], h[2], nbox, origin, xi, xb);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// a1: A_ii = -(Dxx + Dyy + Dzz) - kappa^2 diag(b) on interior nodes, identity border.
+// One workgroup writes one row; each thread writes 4 consecutive columns.
+// ----------------------------------------------------------------------------
+template <typename T> struct Store4;
+template <> struct Store4<float> {
+  __device__ static void st(float* p, const double v[4]) { *reinterpret_cast<f4*>(p) = f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]}; }
+};
+template <> struct Store4<double> {
+  __device__ static void st(double* p, const double v[4]) {
+    *reinterpret_cast<d2*>(p) = d2{v[0], v[1]};
+    *reinterpret_cast<d2*>(p + 2) = d2{v[2], v[3]};
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void operators_kernel(Geom g, int nbox, const double* b, T* A_all, double* anorm) {
+  const int box = blockIdx.y;
+  const int N = g.n_pad, n = g.n, m = g.m, p = g.p;
+  T* A = A_all + (size_t)box * N * N;
+  for (int r = blockIdx.x; r < N; r += gridDim.x) {
+    T* row = A + (size_t)r * N;
+    if (r >= n) {
+      for (int c = 4 * threadIdx.x; c < N; c += 4 * blockDim.x) {
+        double v[4] = {0, 0, 0, 0};
+        for (int q = 0; q < 4; q++) v[q] = (c + q == r) ? 1.0 : 0.0;
+        Store4<T>::st(row + c, v);
+      }
+      continue;
+    }
+    const int ii = r % m, jj = (r / m) % m, kk = r / (m * m);
+    const double* D2 = g.D2;
+    const int xbase = m * jj + m * m * kk;  // x-line: columns xbase + ii'
+    const int ybase = ii + m * m * kk;      // y-line: ybase + m jj'
+    const int zbase = ii + m * jj;          // z-line: zbase + m^2 kk'
+    const double diag_b = -g.kappa2 * b[(size_t)box * n + r];
+    for (int c = 4 * threadIdx.x; c < N; c += 4 * blockDim.x) {
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int cc = c + q;
+        double s = 0.0;
+        if (cc < n) {
+          const int dx = cc - xbase;
+          if (dx >= 0 && dx < m) s -= g.s2[0] * D2[(ii + 1) * p + dx + 1];
+          const int dy = cc - ybase;
+          if (dy >= 0 && dy < m * m && dy % m == 0) s -= g.s2[1] * D2[(jj + 1) * p + dy / m + 1];
+          const int dz = cc - zbase;
+          if (dz >= 0 && dz % (m * m) == 0) s -= g.s2[2] * D2[(kk + 1) * p + dz / (m * m) + 1];
+          if (cc == r) s += diag_b;
+        }
+        v[q] = s;
+      }
+      Store4<T>::st(row + c, v);
+    }
+    if (threadIdx.x == 0) {
+      // exact |row| sum of A_ii (FP64)
+      double sum = 0.0;
+      for (int q = 0; q < m; q++) {
+        if (q != ii) sum += g.s2[0] * fabs(D2[(ii + 1) * p + q + 1]);
+        if (q != jj) sum += g.s2[1] * fabs(D2[(jj + 1) * p + q + 1]);
+        if (q != kk) sum += g.s2[2] * fabs(D2[(kk + 1) * p + q + 1]);
+      }
+      const double d = -(g.s2[0] * D2[(ii + 1) * p + ii + 1] + g.s2[1] * D2[(jj + 1) * p + jj + 1] +
+                         g.s2[2] * D2[(kk + 1) * p + kk + 1]) + diag_b;
+      atomic_max_nonneg(anorm + box, sum + fabs(d));
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_operators(const Geom& g, int nbox, const double* b, T* A, double* anorm, hipStream_t st) {
+  hipError_t e = launch_fill_zero(anorm, sizeof(double) * nbox, st);
+  if (e != hipSuccess) return e;
+  const int rows = g.n_pad < 1024 ? g.n_pad : 1024;
+  hipLaunchKernelGGL((operators_kernel<T>), dim3(rows, nbox), dim3(256), 0, st, g, nbox, b, A, anorm);
+  return hipGetLastError();
+}
+template hipError_t launch_operators<float>(const Geom&, int, const double*, float*, double*, hipStream_t);
+template hipError_t launch_operators<double>(const Geom&, int, const double*, double*, double*, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// B = [A_ib | f_i | 0] (rows >= n are zero).  A_ib (Sec. 2.2) couples interior
+// node (ii,jj,kk) to the two face nodes at the ends of each of its three lines:
+// entry -(2/h_a)^2 D2[c+1][e], c the node's coordinate along axis a, e = 0 or p-1.
+// ----------------------------------------------------------------------------
+__device__ inline double aib_entry(const Geom& g, int ii, int jj, int kk, int col) {
+  const int m = g.m, mm = m * m;
+  const int a = col / mm, q = col - a * mm;
+  const int axis = a >> 1, side = a & 1;
+  int along, tq;
+  if (axis == 0) { along = ii; tq = jj + m * kk; }
+  else if (axis == 1) { along = jj; tq = ii + m * kk; }
+  else { along = kk; tq = ii + m * jj; }
+  if (tq != q) return 0.0;
+  return -g.s2[axis] * g.D2[(along + 1) * g.p + (side ? g.p - 1 : 0)];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void rhs_kernel(Geom g, int nbox, const double* f, T* B_all, double* maxb) {
+  const int box = blockIdx.y;
+  const int N = g.n_pad, ldx = g.ldx, n = g.n, m = g.m;
+  T* B = B_all + (size_t)box * N * ldx;
+  double mx = 0.0;
+  for (int r = blockIdx.x; r < N; r += gridDim.x) {
+    T* row = B + (size_t)r * ldx;
+    const int ii = r % m, jj = (r / m) % m, kk = r / (m * m);
+    const double fr = (r < n && f) ? f[(size_t)box * n + r] : 0.0;
+    for (int c = threadIdx.x; c < ldx; c += blockDim.x) {
+      double v = 0.0;
+      if (r < n) {
+        if (c < g.nb) v = aib_entry(g, ii, jj, kk, c);
+        else if (c == g.nb) v = fr;
+      }
+      mx = fmax(mx, fabs(v));
+      row[c] = (T)v;
+    }
+  }
+  mx = wave_max(mx);
+  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(maxb + box, mx);
+}
+
+template <typename T>
+hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* maxb, hipStream_t st) {
+  hipError_t e = launch_fill_zero(maxb, sizeof(double) * nbox, st);
+  if (e != hipSuccess) return e;
+  const int rows = g.n_pad < 1024 ? g.n_pad : 1024;
+  hipLaunchKernelGGL((rhs_kernel<T>), dim3(rows, nbox), dim3(256), 0, st, g, nbox, f, B, maxb);
+  return hipGetLastError();
+}
+template hipError_t launch_rhs<float>(const Geom&, int, const double*, float*, double*, hipStream_t);
+template hipError_t launch_rhs<double>(const Geom&, int, const double*, double*, double*, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// FP64 residual R = B - A_ii X through the tensor structure of A_ii.
+// Pass 1 (one wave per z-line and 64 columns): Rz = B + s2z D2 X (along z)
+//                                                  + kappa^2 b X.
+// Pass 2 (workgroup per z-plane and 16 columns, plane staged in LDS):
+//        R = Rz + s2x D2 X (along x) + s2y D2 X (along y); R -> FP32 for the
+//        correction solve, max|R| and max|X| per box.
+// ----------------------------------------------------------------------------
+constexpr int kMaxM = 18;
+
+__global__ __launch_bounds__(256) void residual_z_kernel(Geom g, int nbox, const double* b, const double* f,
+                                                         const double* X_all, double* Rz_all, const int* active) {
+  const int box = blockIdx.z;
+  if (active && active[box] == 0) return;
+  const int m = g.m, mm = m * m, n = g.n, ldx = g.ldx, p = g.p;
+  const int pencil = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pencil >= mm) return;
+  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int ii = pencil % m, jj = pencil / m;
+  const double* X = X_all + (size_t)box * g.n_pad * ldx;
+  double* Rz = Rz_all + (size_t)box * g.n_pad * ldx;
+  double x[kMaxM];
+#pragma unroll
+  for (int k = 0; k < kMaxM; k++)
+    if (k < m) x[k] = X[(size_t)(pencil + mm * k) * ldx + c];
+#pragma unroll
+  for (int k = 0; k < kMaxM; k++) {
+    if (k < m) {
+    const int node = pencil + mm * k;
+    double s = 0.0;
+#pragma unroll
+    for (int k2 = 0; k2 < kMaxM; k2++)
+      if (k2 < m) s += g.D2[(k + 1) * p + k2 + 1] * x[k2];
+    double bv = 0.0;
+    if (c < g.nb) bv = aib_entry(g, ii, jj, k, c);
+    else if (c == g.nb && f) bv = f[(size_t)box * n + node];
+    Rz[(size_t)node * ldx + c] = bv + g.s2[2] * s + g.kappa2 * b[(size_t)box * n + node] * x[k];
+    }
+  }
+}
+
+constexpr int kResCols = 16;
+
+__global__ __launch_bounds__(256) void residual_xy_kernel(Geom g, int nbox, const double* X_all, const double* Rz_all,
+                                                          float* R32_all, double* maxr, double* maxx,
+                                                          const int* active) {
+  __shared__ double plane[kMaxM * kMaxM * kResCols];
+  __shared__ double d2s[kMaxM * kMaxM];
+  const int box = blockIdx.z;
+  if (active && active[box] == 0) return;
+  const int m = g.m, mm = m * m, ldx = g.ldx, p = g.p;
+  const int kk = blockIdx.x;
+  const int c0 = blockIdx.y * kResCols;
+  const double* X = X_all + (size_t)box * g.n_pad * ldx;
+  const double* Rz = Rz_all + (size_t)box * g.n_pad * ldx;
+  float* R32 = R32_all + (size_t)box * g.n_pad * ldx;
+  for (int e = threadIdx.x; e < mm * kResCols; e += blockDim.x) {
+    const int node2 = e / kResCols, c = e % kResCols;
+    plane[e] = X[(size_t)(node2 + mm * kk) * ldx + c0 + c];
+  }
+  for (int e = threadIdx.x; e < mm; e += blockDim.x) d2s[e] = g.D2[(e / m + 1) * p + e % m + 1];
+  __syncthreads();
+  double mr = 0.0, mxv = 0.0;
+  for (int e = threadIdx.x; e < mm * kResCols; e += blockDim.x) {
+    const int node2 = e / kResCols, c = e % kResCols;
+    const int ii = node2 % m, jj = node2 / m;
+    double ax = 0.0, ay = 0.0;
+    for (int q = 0; q < m; q++) {
+      ax += d2s[ii * m + q] * plane[(q + m * jj) * kResCols + c];
+      ay += d2s[jj * m + q] * plane[(ii + m * q) * kResCols + c];
+    }
+    const size_t off = (size_t)(node2 + mm * kk) * ldx + c0 + c;
+    const double r = Rz[off] + g.s2[0] * ax + g.s2[1] * ay;
+    if (R32) R32[off] = (float)r;
+    mr = fmax(mr, fabs(r));
+    mxv = fmax(mxv, fabs(plane[e]));
+  }
+  mr = wave_max(mr);
+  mxv = wave_max(mxv);
+  if ((threadIdx.x & 63) == 0) {
+    atomic_max_nonneg(maxr + box, mr);
+    atomic_max_nonneg(maxx + box, mxv);
+  }
+}
+
+hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const double* X, double* Rz,
+                           float* R32, double* maxr, double* maxx, const int* active, hipStream_t st) {
+  hipError_t e = launch_fill_zero(maxr, sizeof(double) * nbox, st);
+  if (e == hipSuccess) e = launch_fill_zero(maxx, sizeof(double) * nbox, st);
+  if (e != hipSuccess) return e;
+  const int mm = g.m * g.m;
+  hipLaunchKernelGGL(residual_z_kernel, dim3((mm + 3) / 4, g.ldx / 64, nbox), dim3(256), 0, st, g, nbox, b, f, X, Rz,
+                     active);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(residual_xy_kernel, dim3(g.m, g.ldx / kResCols, nbox), dim3(256), 0, st, g, nbox, X, Rz, R32,
+                     maxr, maxx, active);
+  return hipGetLastError();
+}
+
+// Backward error check of one refinement step; decides which boxes continue.
+__global__ void ir_check_kernel(int nbox, int it, int last, double tol, const double* anorm, const double* maxb,
+                                const double* maxr, const double* maxx, int* active, int* iters, double* berr) {
+  const int box = blockIdx.x * blockDim.x + threadIdx.x;
+  if (box >= nbox || active[box] == 0) return;
+  const double be = maxr[box] / (anorm[box] * maxx[box] + maxb[box]);
+  if (berr) berr[box] = be;
+  if (be <= tol) {
+    active[box] = 0;
+    if (iters) iters[box] = it;
+  } else if (last) {
+    active[box] = 0;
+    if (iters) iters[box] = -it;
+  }
+}
+
+hipError_t launch_ir_check(int nbox, int it, int last, double tol, const double* anorm, const double* maxb,
+                           const double* maxr, const double* maxx, int* active, int* iters, double* berr,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(ir_check_kernel, dim3((nbox + 255) / 256), dim3(256), 0, st, nbox, it, last, tol, anorm, maxb,
+                     maxr, maxx, active, iters, berr);
+  return hipGetLastError();
+}
+
+// X (FP64) = Y (first) or X += Y, rows < n only.
+__global__ __launch_bounds__(256) void ir_add_kernel(Geom g, int nbox, const float* Y_all, double* X_all, int first,
+                                                     const int* active) {
+  const int box = blockIdx.y;
+  if (active && active[box] == 0) return;
+  const size_t sz = (size_t)g.n_pad * g.ldx;
+  const float* Y = Y_all + box * sz;
+  double* X = X_all + box * sz;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < sz; i += (size_t)gridDim.x * blockDim.x)
+    X[i] = first ? (double)Y[i] : X[i] + (double)Y[i];
+}
+
+hipError_t launch_ir_add(const Geom& g, int nbox, const float* Y, double* X, int first, const int* active,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(ir_add_kernel, dim3(512, nbox), dim3(256), 0, st, g, nbox, Y, X, first, active);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// a4: DtN rows and loads (Sec. 3.1 eq. t-block, Alg. 1; Alg. 2 load loop).
+// One wave per normal line (axis, tangential q): the two face rows at its ends.
+//   face x- row: outward derivative -(2/h) sum_l D[0][l] u_l
+//   face x+ row: +(2/h) sum_l D[p-1][l] u_l
+//   T = A_bb - A_bi X_b,  g = -A_bi X_f - sum_{boundary faces b} T[:, b] g_dir[b].
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void dtn_kernel(Geom g, int nbox, const double* X_all, const double* gdir,
+                                                  const int* slot_map, double* T_vals, double* gload) {
+  const int box = blockIdx.y;
+  const int m = g.m, mm = m * m, p = g.p, nb = g.nb, ldx = g.ldx;
+  const int line = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (line >= 3 * mm) return;
+  const int axis = line / mm, q = line % mm;
+  const int a_minus = 2 * axis, a_plus = 2 * axis + 1;
+  const int* smap = slot_map + box * 36;
+  const bool do_minus = smap[a_minus * 6 + a_minus] >= 0;
+  const bool do_plus = smap[a_plus * 6 + a_plus] >= 0;
+  const int row_m = a_minus * mm + q, row_p = a_plus * mm + q;
+  if (!do_minus && !do_plus) {
+    if (lane == 0) { gload[(size_t)box * nb + row_m] = 0.0; gload[(size_t)box * nb + row_p] = 0.0; }
+    return;
+  }
+  // interior nodes on the line
+  const int t0 = q % m, t1 = q / m;
+  int base, stride;
+  if (axis == 0) { base = m * t0 + mm * t1; stride = 1; }
+  else if (axis == 1) { base = t0 + mm * t1; stride = m; }
+  else { base = t0 + m * t1; stride = mm; }
+  const double* X = X_all + (size_t)box * g.n_pad * ldx;
+  const double s1 = g.s1[axis];
+  const double* D0 = g.D;                  // D[0][.]
+  const double* D1 = g.D + (size_t)(p - 1) * p;  // D[p-1][.]
+  const size_t m4 = (size_t)mm * mm;
+  double lift_m = 0.0, lift_p = 0.0;
+  for (int c = lane; c < nb + 1; c += 64) {
+    double xm = 0.0, xp = 0.0;
+    for (int l = 0; l < m; l++) {
+      const double xv = X[(size_t)(base + l * stride) * ldx + c];
+      xm += D0[l + 1] * xv;
+      xp += D1[l + 1] * xv;
+    }
+    if (c == nb) {  // load column: g = -A_bi v
+      lift_m += s1 * xm;
+      lift_p += -s1 * xp;
+      continue;
+    }
+    double tm = s1 * xm, tp = -s1 * xp;  // -A_bi X_b
+    if (c == row_m) { tm += -s1 * D0[0]; tp += s1 * D1[0]; }
+    if (c == row_p) { tm += -s1 * D0[p - 1]; tp += s1 * D1[p - 1]; }
+    const int b = c / mm, qc = c - b * mm;
+    const bool bdir = smap[b * 6 + b] < 0;
+    if (bdir) {
+      const double gd = gdir ? gdir[(size_t)box * nb + c] : 0.0;
+      lift_m -= tm * gd;
+      lift_p -= tp * gd;
+    } else {
+      if (do_minus) {
+        const int sl = smap[a_minus * 6 + b];
+        if (sl >= 0) T_vals[(size_t)sl * m4 + (size_t)q * mm + qc] = tm;
+      }
+      if (do_plus) {
+        const int sl = smap[a_plus * 6 + b];
+        if (sl >= 0) T_vals[(size_t)sl * m4 + (size_t)q * mm + qc] = tp;
+      }
+    }
+  }
+  lift_m = wave_sum(lift_m);
+  lift_p = wave_sum(lift_p);
+  if (lane == 0) {
+    gload[(size_t)box * nb + row_m] = do_minus ? lift_m : 0.0;
+    gload[(size_t)box * nb + row_p] = do_plus ? lift_p : 0.0;
+  }
+}
+
+hipError_t launch_dtn(const Geom& g, int nbox, const double* X, const double* gdir, const int* slot_map,
+                      double* T_vals, double* gload, hipStream_t st) {
+  const int lines = 3 * g.m * g.m;
+  hipLaunchKernelGGL(dtn_kernel, dim3((lines + 3) / 4, nbox), dim3(256), 0, st, g, nbox, X, gdir, slot_map, T_vals,
+                     gload);
+  return hipGetLastError();
+}
+
+// T_vals[dst] += T_vals[src] for each (dst, src) pair; every dst appears once.
+__global__ void reduce_kernel(int npairs, const long long* pairs, long long block_elems, double* T) {
+  const int pr = blockIdx.y;
+  if (pr >= npairs) return;
+  const long long dst = pairs[2 * pr], src = pairs[2 * pr + 1];
+  double* d = T + dst * block_elems;
+  const double* s = T + src * block_elems;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < block_elems;
+       i += (long long)gridDim.x * blockDim.x)
+    d[i] = d[i] + s[i];
+}
+
+hipError_t launch_reduce(int npairs, const long long* pairs, long long block_elems, double* T_vals, hipStream_t st) {
+  if (npairs == 0) return hipSuccess;
+  int gx = (int)((block_elems + 255) / 256);
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL(reduce_kernel, dim3(gx, npairs), dim3(256), 0, st, npairs, pairs, block_elems, T_vals);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// a5: u_i = X_f - X_b u_b (one wave per interior node)
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void reconstruct_kernel(Geom g, int nbox, const double* X_all, const double* ub,
+                                                          double* ui) {
+  const int box = blockIdx.y;
+  const int node = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (node >= g.n) return;
+  const double* x = X_all + ((size_t)box * g.n_pad + node) * g.ldx;
+  const double* u = ub + (size_t)box * g.nb;
+  double s = 0.0;
+  for (int c = lane; c < g.nb; c += 64) s += x[c] * u[c];
+  s = wave_sum(s);
+  if (lane == 0) ui[(size_t)box * g.n + node] = x[g.nb] - s;
+}
+
+hipError_t launch_reconstruct(const Geom& g, int nbox, const double* X, const double* ub, double* ui,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(reconstruct_kernel, dim3((g.n + 3) / 4, nbox), dim3(256), 0, st, g, nbox, X, ub, ui);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// a6 helpers.  rhs = w - A_bi^T lam_b: node (ii,jj,kk) lies on one line per axis;
+// the face rows at the ends of that line have A_bi entries -/+ (2/h) D[e][c+1].
+// ----------------------------------------------------------------------------
+__global__ void adjoint_rhs_kernel(Geom g, int nbox, const double* w, const double* lam, double* rhs) {
+  const int box = blockIdx.y;
+  const int m = g.m, mm = m * m, p = g.p;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < g.n_pad; r += gridDim.x * blockDim.x) {
+    double v = 0.0;
+    if (r < g.n) {
+      v = w[(size_t)box * g.n + r];
+      if (lam) {
+        const int ii = r % m, jj = (r / m) % m, kk = r / mm;
+        const int along[3] = {ii, jj, kk};
+        const int tq[3] = {jj + m * kk, ii + m * kk, ii + m * jj};
+        const double* lb = lam + (size_t)box * g.nb;
+        for (int axis = 0; axis < 3; axis++) {
+          const double lm = lb[(2 * axis) * mm + tq[axis]];
+          const double lp = lb[(2 * axis + 1) * mm + tq[axis]];
+          v -= -g.s1[axis] * g.D[along[axis] + 1] * lm;
+          v -= g.s1[axis] * g.D[(size_t)(p - 1) * p + along[axis] + 1] * lp;
+        }
+      }
+    }
+    rhs[(size_t)box * g.n_pad + r] = v;
+  }
+}
+
+hipError_t launch_adjoint_rhs(const Geom& g, int nbox, const double* w, const double* lam_b, double* rhs,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(adjoint_rhs_kernel, dim3((g.n_pad + 255) / 256, nbox), dim3(256), 0, st, g, nbox, w, lam_b, rhs);
+  return hipGetLastError();
+}
+
+// z = A_ii^{-T} rhs with P A = L U:  A^T = U^T L^T P, so solve U^T y = rhs
+// (forward), L^T v = y (backward), z[perm[i]] = v[i].  One workgroup per box;
+// the vector lives in LDS, the factor rows are read coalesced (row-major).
+__global__ __launch_bounds__(256) void getrs_t_kernel(Geom g, int nbox, const double* LU_all, const int* perm_all,
+                                                      const double* dinv_all, const double* rhs_all, double* z_all) {
+  extern __shared__ double vec[];
+  double* tmp = vec + g.n_pad;
+  const int box = blockIdx.x;
+  const int N = g.n_pad;
+  const double* LU = LU_all + (size_t)box * N * N;
+  const int* perm = perm_all + (size_t)box * N;
+  const double* dinv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) vec[i] = rhs_all[(size_t)box * N + i];
+  __syncthreads();
+  // U^T y = r: block b, y_b = Uinv_b^T (r_b - sum_{k<b} U_kb^T y_k); right-looking updates
+  for (int bk = 0; bk < g.npanel; bk++) {
+    const int s = bk * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
+    const double* Uinv = dinv + (size_t)(2 * bk + 1) * 64 * 64;
+    if (threadIdx.x < w) {
+      double acc = 0.0;
+      for (int k = 0; k < w; k++) acc += Uinv[k * 64 + threadIdx.x] * vec[s + k];
+      tmp[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
+    __syncthreads();
+    for (int j = s + w + threadIdx.x; j < N; j += blockDim.x) {
+      double acc = 0.0;
+      for (int i = 0; i < w; i++) acc += LU[(size_t)perm[s + i] * N + j] * vec[s + i];
+      vec[j] -= acc;
+    }
+    __syncthreads();
+  }
+  // L^T v = y: block b from the last, v_b = Linv_b^T (y_b - sum_{k>b} L_kb^T v_k)
+  for (int bk = g.npanel - 1; bk >= 0; bk--) {
+    const int s = bk * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
+    const double* Linv = dinv + (size_t)(2 * bk) * 64 * 64;
+    if (threadIdx.x < w) {
+      double acc = 0.0;
+      for (int k = 0; k < w; k++) acc += Linv[k * 64 + threadIdx.x] * vec[s + k];
+      tmp[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
+    __syncthreads();
+    for (int j = threadIdx.x; j < s; j += blockDim.x) {
+      double acc = 0.0;
+      for (int i = 0; i < w; i++) acc += LU[(size_t)perm[s + i] * N + j] * vec[s + i];
+      vec[j] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < N; i += blockDim.x) z_all[(size_t)box * N + perm[i]] = vec[i];
+}
+
+hipError_t launch_getrs_t(const Geom& g, int nbox, const double* LU, const int* perm, const double* dinv,
+                          const double* rhs, double* z, hipStream_t st) {
+  const size_t shm = sizeof(double) * (g.n_pad + 64);
+  hipLaunchKernelGGL(getrs_t_kernel, dim3(nbox), dim3(256), shm, st, g, nbox, LU, perm, dinv, rhs, z);
+  return hipGetLastError();
+}
+
+// y_b = -A_ib^T z: face node (a, q) collects +(2/h_a)^2 D2[c+1][e] z over its line.
+__global__ void adjoint_yb_kernel(Geom g, int nbox, const double* z, double* yb) {
+  const int box = blockIdx.y;
+  const int m = g.m, mm = m * m, p = g.p;
+  for (int row = blockIdx.x * blockDim.x + threadIdx.x; row < g.nb; row += gridDim.x * blockDim.x) {
+    const int a = row / mm, q = row % mm, axis = a >> 1, side = a & 1;
+    const int t0 = q % m, t1 = q / m;
+    int base, stride;
+    if (axis == 0) { base = m * t0 + mm * t1; stride = 1; }
+    else if (axis == 1) { base = t0 + mm * t1; stride = m; }
+    else { base = t0 + m * t1; stride = mm; }
+    const int e = side ? p - 1 : 0;
+    double s = 0.0;
+    for (int l = 0; l < m; l++) s += g.D2[(l + 1) * p + e] * z[(size_t)box * g.n_pad + base + l * stride];
+    yb[(size_t)box * g.nb + row] = g.s2[axis] * s;
+  }
+}
+
+hipError_t launch_adjoint_yb(const Geom& g, int nbox, const double* z, double* yb, hipStream_t st) {
+  hipLaunchKernelGGL(adjoint_yb_kernel, dim3((g.nb + 255) / 256, nbox), dim3(256), 0, st, g, nbox, z, yb);
+  return hipGetLastError();
+}
+
+__global__ void compact_kernel(Geom g, int nbox, const double* in, double* out) {
+  const int box = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += gridDim.x * blockDim.x)
+    out[(size_t)box * g.n + i] = in[(size_t)box * g.n_pad + i];
+}
+
+hipError_t launch_compact(const Geom& g, int nbox, const double* in, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(compact_kernel, dim3((g.n + 255) / 256, nbox), dim3(256), 0, st, g, nbox, in, out);
+  return hipGetLastError();
+}
+
+__global__ void grad_kernel(Geom g, int nbox, const double* lam, const double* u, double* grad) {
+  const size_t tot = (size_t)nbox * g.n;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < tot; i += (size_t)gridDim.x * blockDim.x)
+    grad[i] = g.kappa2 * lam[i] * u[i];
+}
+
+hipError_t launch_grad(const Geom& g, int nbox, const double* lam, const double* u, double* grad, hipStream_t st) {
+  hipLaunchKernelGGL(grad_kernel, dim3(1024), dim3(256), 0, st, g, nbox, lam, u, grad);
+  return hipGetLastError();
+}
+
+}  // namespace hps

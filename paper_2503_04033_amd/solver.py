@@ -1,0 +1,137 @@
+"""Two-level HPS driver over the leaf-box C ABI (paper Alg. 1 build stage, Alg. 2 solve stage).
+
+Per chunk of boxes the GPU runs: hps_leaf_operators (a1) -> hps_leaf_factor (a2)
+-> hps_leaf_dtn (a3 solves + refinement, a4 DtN/load scatter into the BSR
+interface matrix).  The host then reduces the duplicate diagonal blocks on the
+GPU (hps_interface_reduce), copies T and the loads, and factors the sparse
+interface matrix (p-independent, off the hot path).  The solve stage sums
+loads, solves for the interface values and reconstructs the interiors on the
+GPU (hps_leaf_reconstruct, a5).  X (the interior solution operator and load
+response) is kept in HBM per box when `keep_X` is set; otherwise the chunk is
+recomputed in the solve stage, as the paper does for large problems.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+import torch
+
+from . import interface as itf
+from .leaf import LeafPlan, hps_interface_reduce
+
+
+def _box_origins(nboxes, lo, h) -> np.ndarray:
+    n1, n2, n3 = nboxes
+    t = np.arange(n1 * n2 * n3)
+    bx, rem = t % n1, t // n1
+    by, bz = rem % n2, rem // n2
+    return np.stack([lo[0] + bx * h[0], lo[1] + by * h[1], lo[2] + bz * h[2]], axis=1).astype(np.float64)
+
+
+@dataclass
+class BuildResult:
+    T_vals: torch.Tensor            # BSR blocks (+ extra diagonal slots), device
+    g_loads: torch.Tensor           # [nbox, n_b] lifted loads, device
+    info: torch.Tensor              # [nbox] LU info
+    ir_iters: torch.Tensor
+    berr: torch.Tensor
+    X: Optional[torch.Tensor] = None  # [nbox * n_pad * ldx] when kept
+    extra: dict = field(default_factory=dict)
+
+
+class TwoLevelSolver:
+    """Solve -Lap u - kappa^2 b u = f on a box grid with Dirichlet data g."""
+
+    def __init__(self, nboxes, lo, hi, p: int, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
+                 ir_tol: float = 1e-12, chunk: Optional[int] = None, keep_X: bool = True, device="cuda"):
+        self.nboxes = tuple(int(v) for v in nboxes)
+        self.nbox = int(np.prod(self.nboxes))
+        self.lo = tuple(float(v) for v in lo)
+        self.hi = tuple(float(v) for v in hi)
+        self.h = tuple((self.hi[a] - self.lo[a]) / self.nboxes[a] for a in range(3))
+        self.p, self.kappa = int(p), float(kappa)
+        self.device = torch.device(device)
+        self.plan = LeafPlan(p, self.h, kappa, precision, ir_max_iter, ir_tol)
+        self.info = self.plan.info
+        self.layout = itf.build_layout(self.nboxes, self.info.m)
+        self.chunk = int(chunk) if chunk else self.nbox
+        self.keep_X = keep_X
+        self.origins = torch.tensor(_box_origins(self.nboxes, self.lo, self.h), device=self.device)
+        self.slot_map = torch.tensor(self.layout.slot_map, device=self.device)
+        self.bmask = itf.boundary_mask(self.layout)
+
+    @classmethod
+    def for_problem(cls, prob, **kw) -> "TwoLevelSolver":
+        return cls(prob.nboxes, prob.lo, prob.hi, prob.p, prob.kappa, **kw)
+
+    # ---- problem data at the collocation nodes --------------------------------
+    def nodes(self):
+        i = self.info
+        xi = torch.empty(self.nbox * i.n_i * 3, dtype=torch.float64, device=self.device)
+        xb = torch.empty(self.nbox * i.n_b * 3, dtype=torch.float64, device=self.device)
+        self.plan.hps_leaf_nodes(self.nbox, self.origins, xi, xb)
+        return xi.view(self.nbox, i.n_i, 3), xb.view(self.nbox, i.n_b, 3)
+
+    def sample(self, b: Callable, f: Optional[Callable], g: Callable):
+        """Evaluate b, f at interior nodes and g at boundary-face nodes; device tensors."""
+        xi, xb = self.nodes()
+        xi_h, xb_h = xi.cpu().numpy(), xb.cpu().numpy()
+        bv = torch.tensor(b(xi_h), dtype=torch.float64, device=self.device).contiguous()
+        fv = torch.tensor(f(xi_h), dtype=torch.float64, device=self.device).contiguous() if f else None
+        gd = np.where(self.bmask, g(xb_h), 0.0)
+        gv = torch.tensor(gd, dtype=torch.float64, device=self.device).contiguous()
+        return bv, fv, gv, xi_h, xb_h
+
+    # ---- build stage (Alg. 1) ---------------------------------------------------
+    def build(self, b: torch.Tensor, f: Optional[torch.Tensor], g_dir: torch.Tensor) -> BuildResult:
+        i, plan, nbox = self.info, self.plan, self.nbox
+        mm = i.m * i.m
+        # one spare element keeps the pointer valid when the grid has no internal face
+        T_vals = torch.zeros(self.layout.nslot_total * mm * mm + 1, dtype=torch.float64, device=self.device)
+        g_loads = torch.empty(nbox, i.n_b, dtype=torch.float64, device=self.device)
+        info = torch.empty(nbox, dtype=torch.int32, device=self.device)
+        iters = torch.empty(nbox, dtype=torch.int32, device=self.device)
+        berr = torch.empty(nbox, dtype=torch.float64, device=self.device)
+        X_all = torch.empty(nbox * i.n_pad * i.ldx, dtype=torch.float64, device=self.device) if self.keep_X else None
+        C = min(self.chunk, nbox)
+        bufs = plan.alloc(C, self.device)
+        xs = i.n_pad * i.ldx
+        for c0 in range(0, nbox, C):
+            nb = min(C, nbox - c0)
+            sl = slice(c0, c0 + nb)
+            bb = b[sl].contiguous()
+            ff = f[sl].contiguous() if f is not None else None
+            X = X_all[c0 * xs:(c0 + nb) * xs] if X_all is not None else bufs["X"]
+            plan.hps_leaf_operators(nb, bb, bufs["A"], bufs["anorm"])
+            plan.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], info[sl])
+            plan.hps_leaf_dtn(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
+                              g_dir[sl].contiguous(), self.slot_map[sl].contiguous(), T_vals, g_loads[sl], X,
+                              iters[sl], berr[sl], bufs["ws"])
+        pairs = torch.tensor(self.layout.reduce_pairs, device=self.device)
+        if pairs.shape[0]:
+            hps_interface_reduce(pairs, mm * mm, T_vals)
+        return BuildResult(T_vals=T_vals, g_loads=g_loads, info=info, ir_iters=iters, berr=berr, X=X_all)
+
+    # ---- solve stage (Alg. 2) ---------------------------------------------------
+    def solve(self, br: BuildResult, g_dir: torch.Tensor, isolver: Optional[itf.InterfaceSolver] = None):
+        """Return (u_face, u_b [nbox, n_b], u_i [nbox, n_i], interface solver)."""
+        if br.X is None:
+            raise ValueError("reconstruction needs X: build with keep_X=True")
+        if isolver is None:
+            isolver = itf.InterfaceSolver(self.layout, br.T_vals.cpu().numpy())
+        rhs = itf.interface_rhs(self.layout, br.g_loads.cpu().numpy())
+        u_face = isolver.solve(rhs)
+        ub = itf.box_face_values(self.layout, u_face, g_dir.cpu().numpy())
+        ub_d = torch.tensor(ub, device=self.device)
+        ui = torch.empty(self.nbox, self.info.n_i, dtype=torch.float64, device=self.device)
+        self.plan.hps_leaf_reconstruct(self.nbox, br.X, ub_d, ui)
+        return u_face, ub, ui, isolver
+
+    def solve_problem(self, prob):
+        bv, fv, gv, xi, xb = self.sample(prob.b, prob.f, prob.g)
+        br = self.build(bv, fv, gv)
+        u_face, ub, ui, isolver = self.solve(br, gv)
+        return {"build": br, "u_face": u_face, "u_b": ub, "u_i": ui, "xi": xi, "xb": xb, "b": bv, "f": fv,
+                "g_dir": gv, "isolver": isolver}
