@@ -1,0 +1,243 @@
+"""Benchmark of the batched leaf-box reduction (two-level HPS, a1..a4) on one MI355X.
+
+Workload: 16 x 16 x 16 leaf boxes on [0,1]^3, p = 16 (2744 interior nodes per
+box), kappa = 40, b = 1 + 0.3 * (8 seeded Gaussian bumps), plane-wave Dirichlet
+data, f = 0 (seeded synthetic inputs, workloads.config3).  One step = the whole
+hot path over all 4096 boxes: operator assembly, LU, solves with FP64
+refinement, DtN/load assembly into the BSR interface matrix, and the diagonal
+block reduction.  Inputs (b, g) are resident in HBM before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--nbox N] [--no-fp64] [--no-cpu]
+
+Prints one JSON line.  value = leaf boxes/s of the FP32+IR path.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "leaf boxes/s + % MFMA peak at p=16; FP32+IR vs FP64 path at <=1e-9 rel err"
+PEAK_FP32_MFMA = 157.3e12
+PEAK_FP64_MFMA = 78.6e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flops_per_box(n_i: int, n_b: int, passes: int) -> dict:
+    """Algorithmic flops of one box: LU 2/3 n^3, each solve pass 2 n^2 (n_b + 1)."""
+    return {"lu": 2.0 / 3.0 * n_i ** 3, "solve": passes * 2.0 * n_i ** 2 * (n_b + 1)}
+
+
+class Runner:
+    """Buffers and the per-chunk ABI call sequence for one precision."""
+
+    def __init__(self, prob, precision, nbox, chunk, ir_max_iter=3, ir_tol=1e-11):
+        import torch
+        from paper_2503_04033_amd import interface as itf
+        from paper_2503_04033_amd.leaf import LeafPlan
+        self.torch = torch
+        self.prob = prob
+        self.nbox = nbox
+        self.plan = LeafPlan(prob.p, prob.h, prob.kappa, precision, ir_max_iter, ir_tol)
+        self.info = self.plan.info
+        self.layout = itf.build_layout(prob.nboxes, self.info.m)
+        self.chunk = min(chunk, nbox)
+        dev = torch.device("cuda")
+        i = self.info
+        mm = i.m * i.m
+        self.T_vals = torch.zeros(self.layout.nslot_total * mm * mm + 1, dtype=torch.float64, device=dev)
+        self.g_loads = torch.zeros(nbox, i.n_b, dtype=torch.float64, device=dev)
+        self.infov = torch.zeros(nbox, dtype=torch.int32, device=dev)
+        self.iters = torch.zeros(nbox, dtype=torch.int32, device=dev)
+        self.berr = torch.zeros(nbox, dtype=torch.float64, device=dev)
+        self.bufs = self.plan.alloc(self.chunk, dev)
+        self.slot_map = torch.tensor(self.layout.slot_map[:nbox], device=dev).contiguous()
+        self.pairs = torch.tensor(self.layout.reduce_pairs, device=dev)
+        self.ev = {k: [] for k in ("operators", "factor", "dtn")}
+
+    def step(self, b, g_dir, record=False):
+        torch = self.torch
+        plan, B, C = self.plan, self.bufs, self.chunk
+        for c0 in range(0, self.nbox, C):
+            nb = min(C, self.nbox - c0)
+            sl = slice(c0, c0 + nb)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+            if record:
+                e[0].record()
+            plan.hps_leaf_operators(nb, b[sl], B["A"], B["anorm"])
+            if record:
+                e[1].record()
+            plan.hps_leaf_factor(nb, B["A"], B["perm"], B["dinv"], self.infov[sl])
+            if record:
+                e[2].record()
+            plan.hps_leaf_dtn(nb, B["A"], B["perm"], B["dinv"], b[sl], B["anorm"], None, g_dir[sl],
+                              self.slot_map[sl], self.T_vals, self.g_loads[sl], B["X"], self.iters[sl],
+                              self.berr[sl], B["ws"])
+            if record:
+                e[3].record()
+                self.ev["operators"].append((e[0], e[1], nb))
+                self.ev["factor"].append((e[1], e[2], nb))
+                self.ev["dtn"].append((e[2], e[3], nb))
+        if self.pairs.shape[0] and self.nbox == self.prob.nbox:
+            from paper_2503_04033_amd.leaf import hps_interface_reduce
+            mm = self.info.m ** 2
+            hps_interface_reduce(self.pairs, mm * mm, self.T_vals)
+
+    def phase_ms(self):
+        out = {}
+        for k, lst in self.ev.items():
+            tot = sum(a.elapsed_time(b) for a, b, _ in lst)
+            out[k] = {"ms_total": tot, "launches": len(lst), "boxes": sum(n for _, _, n in lst)}
+        return out
+
+
+def cpu_baseline(prob, nsample: int, seed: int = 0) -> dict:
+    """The oracle (plain FP64 NumPy/SciPy) on a bounded sample of boxes of the same workload."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import leaf as ol
+    rng = np.random.default_rng(seed)
+    ids = rng.choice(prob.nbox, size=nsample, replace=False)
+    org = prob.box_origins()
+    t0 = time.perf_counter()
+    for t in ids:
+        xi, _ = ol.box_node_coords(org[t], prob.h, prob.p)
+        blk = ol.local_blocks(prob.p, prob.h, prob.kappa, prob.b(xi))
+        ol.leaf_reduce(blk, prob.f(xi))
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": nsample / dt, "unit": "boxes/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{nsample} seeded boxes of the same 16^3 p=16 workload (operator + dense LU + "
+                      f"{prob.p - 2}^3-row solve with {6 * (prob.p - 2) ** 2 + 1} right-hand sides + DtN), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nbox", type=int, default=0, help="time only the first N boxes (profiling)")
+    ap.add_argument("--chunk", type=int, default=1024)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=24)
+    ap.add_argument("--ir-max-iter", type=int, default=3)
+    ap.add_argument("--ir-tol", type=float, default=1e-11)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the leaf reduction shards by boxes with no exchange, and this "
+              "build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import workloads as W
+    prob = W.config3()
+    nbox = a.nbox if a.nbox else prob.nbox
+    dev = torch.device("cuda")
+    log(f"workload {prob.name}: nbox={nbox} p={prob.p} kappa={prob.kappa}")
+    # ---- inputs resident in HBM ----
+    fp32 = Runner(prob, "fp32_ir", nbox, a.chunk, a.ir_max_iter, a.ir_tol)
+    from paper_2503_04033_amd.solver import TwoLevelSolver  # noqa: F401  (import check of the package)
+    i = fp32.info
+    xi = torch.empty(nbox * i.n_i * 3, dtype=torch.float64, device=dev)
+    xb = torch.empty(nbox * i.n_b * 3, dtype=torch.float64, device=dev)
+    org = torch.tensor(prob.box_origins()[:nbox], device=dev)
+    fp32.plan.hps_leaf_nodes(nbox, org, xi, xb)
+    xi_h = xi.view(nbox, i.n_i, 3).cpu().numpy()
+    xb_h = xb.view(nbox, i.n_b, 3).cpu().numpy()
+    from paper_2503_04033_amd import interface as itf
+    bmask = itf.boundary_mask(fp32.layout)[:nbox]
+    b = torch.tensor(prob.b(xi_h), device=dev).contiguous()
+    g_dir = torch.tensor(np.where(bmask, prob.g(xb_h), 0.0), device=dev).contiguous()
+    torch.cuda.synchronize()
+    # ---- FP32 + IR (headline) ----
+    for _ in range(a.warmup):
+        fp32.step(b, g_dir)
+    torch.cuda.synchronize()
+    fp32.ev = {k: [] for k in fp32.ev}
+    t0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(a.steps):
+        fp32.step(b, g_dir, record=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / a.steps
+    boxes_s = nbox / (ms / 1e3)
+    phases = fp32.phase_ms()
+    iters = fp32.iters.cpu().numpy()
+    berr = fp32.berr.cpu().numpy()
+    info_bad = int((fp32.infov.cpu().numpy() != 0).sum())
+    log(f"fp32_ir: {ms:.1f} ms/step, {boxes_s:.1f} boxes/s (wall {wall:.1f} s); phases {phases}")
+    passes = 1 + float(np.mean(np.abs(iters)))
+    fl = flops_per_box(i.n_i, i.n_b, passes)
+    lu_ms_per_box = phases["factor"]["ms_total"] / phases["factor"]["boxes"]
+    lu_tflops = fl["lu"] / (lu_ms_per_box / 1e3) / 1e12
+    n_launch = phases["factor"]["launches"]
+    avg_launch_ms = phases["factor"]["ms_total"] / n_launch
+    boxes_per_launch = phases["factor"]["boxes"] / n_launch
+    achieved = fl["lu"] * boxes_per_launch / (avg_launch_ms / 1e3)
+    tot_flops = nbox * (fl["lu"] + fl["solve"])
+    result = {
+        "metric": METRIC, "value": round(boxes_s, 2), "unit": "boxes/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 MFMA LU/solves + f64 refinement and DtN", "data": "synthetic",
+        "config": {"workload": "16x16x16 leaf boxes, p=16 (2744 interior nodes/box), kappa=40, "
+                               "b=1+0.3*sum of 8 seeded Gaussian bumps (width 0.1), plane-wave g, f=0",
+                   "nbox": nbox, "p": prob.p, "n_i": i.n_i, "n_b": i.n_b, "chunk": fp32.chunk,
+                   "ir_tol": a.ir_tol, "ir_max_iter": a.ir_max_iter},
+        "mfma_frac_lu_solve": round(tot_flops / (ms / 1e3) / PEAK_FP32_MFMA, 4),
+        "ir": {"iters_hist": {int(k): int(v) for k, v in zip(*np.unique(iters, return_counts=True))},
+               "berr_max": float(berr.max()), "lu_info_nonzero": info_bad},
+        "phase_ms_per_step": {k: round(v["ms_total"] / a.steps, 3) for k, v in phases.items()},
+        "roofline": {"kernel": "getrf_kernel<float> (hps_leaf_factor)", "bound": "mfma",
+                     "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": None,
+                     "per_launch": {"boxes": boxes_per_launch, "algorithmic_flops": fl["lu"] * boxes_per_launch,
+                                    "avg_ms": round(avg_launch_ms, 3)}},
+    }
+    log(f"LU: {lu_tflops:.2f} TFLOP/s per box-average; whole path {tot_flops / (ms / 1e3) / 1e12:.2f} TFLOP/s")
+    # ---- FP64 path beside it ----
+    if not a.no_fp64:
+        T32 = fp32.T_vals.clone()
+        g32 = fp32.g_loads.clone()
+        del fp32
+        torch.cuda.empty_cache()
+        fp64 = Runner(prob, "fp64", nbox, a.chunk)
+        fp64.step(b, g_dir)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fp64.step(b, g_dir, record=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms64 = e0.elapsed_time(e1)
+        dT = float(torch.linalg.norm(T32 - fp64.T_vals) / torch.linalg.norm(fp64.T_vals))
+        dg = float(torch.linalg.norm(g32 - fp64.g_loads) / torch.linalg.norm(fp64.g_loads))
+        result["fp64_path"] = {"boxes_per_s": round(nbox / (ms64 / 1e3), 2), "ms_per_step": round(ms64, 3),
+                               "speedup_fp32ir_over_fp64": round(ms64 / ms, 3),
+                               "rel_err_T_fp32ir_vs_fp64": dT, "rel_err_g_fp32ir_vs_fp64": dg,
+                               "phase_ms": {k: round(v["ms_total"], 3) for k, v in fp64.phase_ms().items()}}
+        log(f"fp64: {ms64:.1f} ms/step; dT {dT:.2e} dg {dg:.2e}")
+        del fp64
+        torch.cuda.empty_cache()
+    if not a.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(prob, a.cpu_sample)
+        log(f"cpu baseline {result['cpu_baseline']}")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
