@@ -14,6 +14,7 @@ struct hps_plan_s {
   hps::Geom g;
   int device;
   double* tables;  // device: t[p], D[p*p], D2[p*p]
+  std::vector<int> lu_ops, fwd_ops, bwd_ops;  // schedules (records of 8 ints)
   const double* t;
 };
 
@@ -57,6 +58,48 @@ void cheb_tables(int p, std::vector<double>& t, std::vector<double>& D, std::vec
       const double a = D[(size_t)i * p + k];
       for (int j = 0; j < p; j++) D2[(size_t)i * p + j] += a * D[(size_t)k * p + j];
     }
+}
+
+// Recursive column-split LU unrolled into records (see lu.hip):
+//   lu(c0, c1): panel if c1 - c0 <= 64, else lu(c0, mid); trsm(c0, mid | mid, c1);
+//               gemm(rows [mid, N), cols [mid, c1), k [c0, mid)); lu(mid, c1)
+//   trsm(r0, r1 | cA, cB): leaf if r1 - r0 <= 64, else trsm(r0, mid); gemm(rows [mid, r1),
+//               cols [cA, cB), k [r0, mid)); trsm(mid, r1)
+// Split points are multiples of 64 so that leaves coincide with 64-wide panels.
+void sched_trsm(std::vector<int>& ops, int r0, int r1, int cA, int cB) {
+  if (r1 - r0 <= 64) {
+    ops.insert(ops.end(), {hps::kOpLeaf, r0, r1 - r0, cA, cB, 0, 0, 0});
+    return;
+  }
+  const int mid = r0 + (int)round_up((r1 - r0) / 2, 64);
+  sched_trsm(ops, r0, mid, cA, cB);
+  ops.insert(ops.end(), {hps::kOpGemm, mid, r1, cA, cB, r0, mid, 0});
+  sched_trsm(ops, mid, r1, cA, cB);
+}
+
+// Backward substitution with U: trsm_up(r0, r1): leaf if small, else trsm_up(mid, r1);
+// gemm(rows [r0, mid), cols, k [mid, r1)); trsm_up(r0, mid).
+void sched_trsm_up(std::vector<int>& ops, int r0, int r1, int cA, int cB) {
+  if (r1 - r0 <= 64) {
+    ops.insert(ops.end(), {hps::kOpLeaf, r0, r1 - r0, cA, cB, 0, 0, 0});
+    return;
+  }
+  const int mid = r0 + (int)round_up((r1 - r0) / 2, 64);
+  sched_trsm_up(ops, mid, r1, cA, cB);
+  ops.insert(ops.end(), {hps::kOpGemm, r0, mid, cA, cB, mid, r1, 0});
+  sched_trsm_up(ops, r0, mid, cA, cB);
+}
+
+void sched_lu(std::vector<int>& ops, int c0, int c1, int N) {
+  if (c1 - c0 <= 64) {
+    ops.insert(ops.end(), {hps::kOpPanel, c0, c1 - c0, 0, 0, 0, 0, 0});
+    return;
+  }
+  const int mid = c0 + (int)round_up((c1 - c0) / 2, 64);
+  sched_lu(ops, c0, mid, N);
+  sched_trsm(ops, c0, mid, mid, c1);
+  ops.insert(ops.end(), {hps::kOpGemm, mid, N, mid, c1, c0, mid, 0});
+  sched_lu(ops, mid, c1, N);
 }
 
 struct Sizes {
@@ -167,6 +210,9 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
   pl->t = pl->tables;
   g.D = pl->tables + g.p;
   g.D2 = pl->tables + g.p + (size_t)g.p * g.p;
+  sched_lu(pl->lu_ops, 0, g.n_pad, g.n_pad);
+  sched_trsm(pl->fwd_ops, 0, g.n_pad, 0, g.ldx);
+  sched_trsm_up(pl->bwd_ops, 0, g.n_pad, 0, g.ldx);
   *out = pl;
   return HPS_OK;
 }
@@ -219,10 +265,10 @@ hps_status hps_leaf_factor(hps_plan pl, int32_t nbox, void* A, int32_t* perm, vo
   if (bad_plan(pl) || nbox < 0 || (nbox > 0 && (!A || !perm || !dinv || !info))) return HPS_EINVAL;
   if (nbox == 0) return HPS_OK;
   if (pl->desc.precision == HPS_FP32_IR)
-    return dev(hps::getrf_dispatch<float>(pl->g, static_cast<float*>(A), perm, static_cast<float*>(dinv), info,
-                                          nbox, st));
-  return dev(hps::getrf_dispatch<double>(pl->g, static_cast<double*>(A), perm, static_cast<double*>(dinv), info,
-                                         nbox, st));
+    return dev(hps::getrf_run<float>(pl->g, pl->lu_ops, static_cast<float*>(A), perm, static_cast<float*>(dinv),
+                                     info, nbox, st));
+  return dev(hps::getrf_run<double>(pl->g, pl->lu_ops, static_cast<double*>(A), perm, static_cast<double*>(dinv),
+                                    info, nbox, st));
 }
 
 hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t* perm, const void* dinv,
@@ -238,8 +284,8 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
   if (!ir) {
     double* B = static_cast<double*>(L.B);
     HPS_TRY(hps::launch_rhs<double>(g, nbox, f, B, L.maxb, st));
-    HPS_TRY(hps::getrs_dispatch<double>(g, static_cast<const double*>(LU), perm, static_cast<const double*>(dinv), B,
-                                        X, nbox, nullptr, st));
+    HPS_TRY(hps::getrs_run<double>(g, pl->fwd_ops, pl->bwd_ops, static_cast<const double*>(LU), perm,
+                                   static_cast<const double*>(dinv), B, X, nbox, nullptr, st));
     if (ir_iters) HPS_TRY(hps::launch_fill_int(ir_iters, 0, nbox, st));
     if (berr) {
       HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
@@ -252,7 +298,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     const float* LUf = static_cast<const float*>(LU);
     const float* Dinv = static_cast<const float*>(dinv);
     HPS_TRY(hps::launch_rhs<float>(g, nbox, f, B, L.maxb, st));
-    HPS_TRY(hps::getrs_dispatch<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st));
+    HPS_TRY(hps::getrs_run<float>(g, pl->fwd_ops, pl->bwd_ops, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st));
     HPS_TRY(hps::launch_ir_add(g, nbox, L.Y32, X, 1, nullptr, st));
     HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
     const int kmax = pl->desc.ir_max_iter;
@@ -263,7 +309,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
       HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
                                    st));
       if (last) break;
-      HPS_TRY(hps::getrs_dispatch<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st));
+      HPS_TRY(hps::getrs_run<float>(g, pl->fwd_ops, pl->bwd_ops, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st));
       HPS_TRY(hps::launch_ir_add(g, nbox, L.Y32, X, 0, L.active, st));
     }
   }

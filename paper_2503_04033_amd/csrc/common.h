@@ -74,6 +74,13 @@ struct Geom {
   const double* D2;    // [p][p] D*D
 };
 
+// Schedule record kinds for the recursive LU and solves (record = {kind, a1..a7}):
+//   kOpPanel {c0, w}                 factor columns [c0, c0+w) (w <= 64)
+//   kOpLeaf  {r0, w, cA, cB}          rows [r0, r0+w) := Inv * rows on columns [cA, cB),
+//                                     Inv the stored inverse of the L (or U) diagonal block
+//   kOpGemm  {m0, m1, n0, n1, k0, k1} rows [m0,m1) x cols [n0,n1) -= F[., k0:k1] X[k0:k1, .]
+constexpr int kOpPanel = 0, kOpLeaf = 1, kOpGemm = 2;
+
 __device__ inline int panel_start(int r) { return r * kPanel; }
 __device__ inline int panel_width(const Geom& g, int r) {
   int s = r * kPanel;
@@ -135,6 +142,126 @@ __device__ inline void wg_gemm_sub(typename Mfma<T>::acc (&acc)[RT][CT], ARow ar
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// Pipelined workgroup tile GEMM:  acc -= A[rows, k0:k1) * B[k0:k1, tile cols)
+//
+// GM x GN waves; wave (wm, wn) owns rows [wm*WRT*16, +WRT*16) and columns
+// [wn*WCT*16, +WCT*16) of the MT x NT tile.  Both operands are staged through
+// double-buffered LDS in chunks of KC: while the MFMAs of chunk c read LDS, the
+// 16-byte global loads of chunk c+1 sit in a few staging registers and are
+// written to the other buffer afterwards, so each chunk costs one barrier and
+// the global latency overlaps the math.  A fragments are read as 4 consecutive
+// k values per lane (the MFMA k slot g = lane/16 stands for k = 4g + t, t the
+// step); B fragments are the matching rows.
+//   arow(r): pointer to A row r of the tile (r in [0, MT)), nullptr -> zeros;
+//   brow(k): pointer to B[k][tile col 0]; bcols: valid tile columns (rest zero).
+//   (k1 - k0) % KC == 0.  smem: SMEM elements.
+// ---------------------------------------------------------------------------
+template <typename T, int WRT, int WCT, int GM, int GN, int KC>
+struct TileGemm {
+  static constexpr int MT = GM * WRT * 16;
+  static constexpr int NT = GN * WCT * 16;
+  static constexpr int NTHR = GM * GN * 64;
+  static constexpr int VEC = 16 / sizeof(T);  // elements per 16-byte load
+  static constexpr int LDA = KC + VEC;        // padded LDS row lengths
+  static constexpr int LDB = NT + VEC;
+  static constexpr int ABUF = MT * LDA, BBUF = KC * LDB;
+  static constexpr int SMEM = 2 * (ABUF + BBUF);
+  static constexpr int ALOADS = MT * KC / (NTHR * VEC);
+  static constexpr int BLOADS = KC * NT / (NTHR * VEC);
+  static_assert(ALOADS >= 1 && MT * KC == ALOADS * NTHR * VEC, "A chunk must split evenly");
+  static_assert(BLOADS >= 1 && KC * NT == BLOADS * NTHR * VEC, "B chunk must split evenly");
+  typedef typename Mfma<T>::acc acc_t;
+  typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+
+  template <typename ARow, typename BRow>
+  __device__ static void run(acc_t (&acc)[WRT][WCT], ARow arow, BRow brow, int bcols, int k0, int k1, T* smem) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave % GM, wn = wave / GM;
+    const int g = lane >> 4, c16 = lane & 15;
+    const int nchunk = (k1 - k0) / KC;
+    if (nchunk <= 0) return;
+    // per-thread A staging rows (fixed over the k loop)
+    const T* asrc[ALOADS];
+#pragma unroll
+    for (int q = 0; q < ALOADS; q++) {
+      const int e = (tid + q * NTHR) * VEC;
+      asrc[q] = arow(e / KC);
+      if (asrc[q]) asrc[q] += e % KC;
+    }
+    vec_t ast[ALOADS], bst[BLOADS];
+    auto gload = [&](int kb) {
+#pragma unroll
+      for (int q = 0; q < ALOADS; q++) {
+        if (asrc[q]) {
+          ast[q] = *reinterpret_cast<const vec_t*>(asrc[q] + kb);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; v++) ast[q][v] = T(0);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < BLOADS; q++) {
+        const int e = (tid + q * NTHR) * VEC;
+        const int kk = e / NT, c = e - kk * NT;
+        if (c < bcols) {
+          bst[q] = *reinterpret_cast<const vec_t*>(brow(kb + kk) + c);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; v++) bst[q][v] = T(0);
+        }
+      }
+    };
+    auto lstore = [&](T* buf) {
+#pragma unroll
+      for (int q = 0; q < ALOADS; q++) {
+        const int e = (tid + q * NTHR) * VEC;
+        *reinterpret_cast<vec_t*>(buf + (e / KC) * LDA + e % KC) = ast[q];
+      }
+      T* bb = buf + ABUF;
+#pragma unroll
+      for (int q = 0; q < BLOADS; q++) {
+        const int e = (tid + q * NTHR) * VEC;
+        const int kk = e / NT, c = e - kk * NT;
+        *reinterpret_cast<vec_t*>(bb + kk * LDB + c) = bst[q];
+      }
+    };
+    auto compute = [&](const T* buf) {
+      const T* as = buf;
+      const T* bs = buf + ABUF;
+#pragma unroll
+      for (int s = 0; s < KC / 16; s++) {
+        T a[WRT][4];
+#pragma unroll
+        for (int rt = 0; rt < WRT; rt++) Vec4<T>::load(as + ((wm * WRT + rt) * 16 + c16) * LDA + 16 * s + 4 * g, a[rt]);
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          T bv[WCT];
+#pragma unroll
+          for (int ct = 0; ct < WCT; ct++) bv[ct] = bs[(16 * s + 4 * g + t) * LDB + (wn * WCT + ct) * 16 + c16];
+#pragma unroll
+          for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+            for (int ct = 0; ct < WCT; ct++) acc[rt][ct] = Mfma<T>::op(-a[rt][t], bv[ct], acc[rt][ct]);
+        }
+      }
+    };
+    gload(k0);
+    __syncthreads();  // previous users of smem are done
+    lstore(smem);
+    for (int c = 0; c < nchunk; c++) {
+      T* cur = smem + (c & 1) * (ABUF + BBUF);
+      T* nxt = smem + ((c + 1) & 1) * (ABUF + BBUF);
+      __syncthreads();
+      if (c + 1 < nchunk) gload(k0 + (c + 1) * KC);
+      compute(cur);
+      if (c + 1 < nchunk) lstore(nxt);
+    }
+  }
+};
 
 // acc += A[rows, 0:K) * C[0:K, col0 + cols) with A rows from global memory
 // (row pointer per lane as in wg_gemm_sub) and C already resident in LDS.

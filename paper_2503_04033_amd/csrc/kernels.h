@@ -3,16 +3,19 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "common.h"
 
 namespace hps {
 
+// lu.hip: one kernel launch per schedule record (records of 8 ints, see common.h)
 template <typename T>
-hipError_t getrf_dispatch(const Geom& g, T* A, int* perm, T* dinv, int* info, int nbox, hipStream_t st);
-
+hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
+                     hipStream_t st);
 template <typename T>
-hipError_t getrs_dispatch(const Geom& g, const T* LU, const int* perm, const T* dinv, const T* B, T* X, int nbox,
-                          const int* active, hipStream_t st);
+hipError_t getrs_run(const Geom& g, const std::vector<int>& fwd, const std::vector<int>& bwd, const T* F,
+                     const int* perm, const T* dinv, const T* B, T* Y, int nbox, const int* active, hipStream_t st);
 
 // leafops.hip
 hipError_t launch_nodes(const Geom& g, const double* t, const double* h, int nbox, const double* origin, double* xi,

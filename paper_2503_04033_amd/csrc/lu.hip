@@ -1,0 +1,572 @@
+// a2 + a3 -- batched dense LU with partial pivoting of the interior blocks A_ii
+// and the triangular solves X = U^{-1} L^{-1} P B with its factors.
+//
+// The paper factors every box's interior block A_ii and solves with it (Alg. 1
+// "form the local solution operator", Alg. 2 "form u = A_ii^{-1} f"; A_ii is
+// block diagonal over boxes, Sec. 2.2).  Both run as a recursive column split:
+//
+//   lu(c0, c1):  if c1 - c0 <= 64: pivoted panel factorization
+//                else: lu(c0, mid); U12 = L11^{-1} A12 (recursive triangular
+//                solve); A22 -= L21 U12 (tile GEMM on MFMA); lu(mid, c1)
+//   solve:       Y = P B; Y = L^{-1} Y and X = U^{-1} Y, each a recursive
+//                triangular solve (leaves: 64 x 64 stored inverses, the rest
+//                tile GEMMs)
+//
+// so nearly all flops are large MFMA tile GEMMs.  The recursion depends only on
+// the matrix size, so the host unrolls it into an op list once per plan and
+// launches one kernel per op over all boxes of a chunk: a GEMM kernel (many
+// workgroups per box, each one output tile, XCD-aware placement so a box's
+// tiles share one L2), a leaf kernel, and a panel kernel (one workgroup per box,
+// sub-panels in registers, workgroup-wide pivot search).  Each kernel gets its
+// own register budget and occupancy.
+//
+// Rows are never moved: perm[pos] names the physical row at position pos (a
+// row gather in row-major storage is a contiguous read).  Pivot rule: largest
+// modulus among the rows not yet pivoted, ties to the lowest current position;
+// after each sub-panel the chosen pivots take the next positions in order and
+// the remaining rows keep their relative order.
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace hps {
+
+constexpr int kLuThreads = 512;
+constexpr int kLuWaves = kLuThreads / 64;
+constexpr int kLdsLd = 64 + 8;  // padded row length of LDS tiles
+
+// LDS of the panel kernel.  M = L11^{-1} and Nn = U11^{-1} of the panel's
+// growing diagonal block (positions [j0, j0+npv)), kept up to date after every
+// sub-panel, so the U part of a new sub-panel is one parallel product and the
+// diagonal-block inverses needed by the solves come out at the end for free.
+template <typename T>
+struct LuSmem {
+  T M[64 * 65];
+  T Nn[64 * 65];
+  T ub[64 * 8];          // U part of the current sub-panel (npv x SP)
+  T stg[64 * 8];         // staging of A[earlier pivots][sub-panel cols]; later Z = Nn * ub
+  T lq[8 * 64];          // new pivot rows' L values in the earlier panel columns (SP x npv)
+  T t1[8 * 64];          // lq * M
+  T uq[8 * 8];           // inverse of the new pivots' SP x SP upper block
+  T PR[8 * 8];           // new pivot rows in the sub-panel columns (SP x SP)
+  T wrow[2][kLuWaves][8];
+  T wval[2][kLuWaves];
+  int wslot[2][kLuWaves];
+  int cnt[32 * kLuWaves];
+};
+
+// Pivoted factorization of panel columns [j0, j0+W) for positions >= j0, in
+// sub-panels of SP columns.  Per sub-panel (columns [c0, c0+SP), npv = c0-j0
+// pivots already chosen in this panel):
+//   (a) U rows of the earlier pivots: ub = M * A[pivots, c0:c0+SP)
+//   (b) candidates (positions >= c0, one register row per slot): subtract
+//       L[row, j0:c0) * ub
+//   (c) SP pivot columns: per-wave best candidate (modulus, lowest slot on ties)
+//       and its row go to LDS, one barrier, every thread picks the winner
+//   (d) write back, (e) new position order: pivots first, the rest keep their
+//       relative order
+//   (f) extend M and Nn with the new pivots (block triangular inverses)
+// After the last sub-panel M and Nn are written to dinv_panel as Linv / Uinv.
+template <typename T, int ROWS, int SP, int W>
+__device__ __attribute__((noinline)) void lu_panel(const Geom& g, T* A, int* perm, int j0, LuSmem<T>& sm, int& info,
+                                                   T* dinv_panel) {
+  const int N = g.n_pad, lda = N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int q = 0; q < W / SP; q++) {
+    const int c0 = j0 + q * SP;
+    const int npv = c0 - j0;
+    // (a)
+    if (npv > 0) {
+      for (int e = tid; e < npv * SP; e += kLuThreads) {
+        const int i = e / SP, c = e - i * SP;
+        sm.stg[e] = A[(size_t)perm[j0 + i] * lda + c0 + c];
+      }
+      __syncthreads();
+      for (int e = tid; e < npv * SP; e += kLuThreads) {
+        const int i = e / SP, c = e - i * SP;
+        T s = T(0);
+        for (int k = 0; k <= i; k++) s += sm.M[i * 65 + k] * sm.stg[k * SP + c];
+        sm.ub[e] = s;
+        A[(size_t)perm[j0 + i] * lda + c0 + c] = s;
+      }
+      __syncthreads();
+    }
+    // (b)
+    const int nrem = N - c0;
+    T v[ROWS][SP];
+    int phys[ROWS];
+    bool done[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+      const int s = tid + kLuThreads * r;
+      done[r] = s >= nrem;
+      phys[r] = done[r] ? 0 : perm[c0 + s];
+      const T* row = A + (size_t)phys[r] * lda;
+#pragma unroll
+      for (int c = 0; c < SP; c += 4) {
+        T t4[4];
+        if (!done[r]) Vec4<T>::load(row + c0 + c, t4);
+        else t4[0] = t4[1] = t4[2] = t4[3] = T(0);
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[r][c + u] = t4[u];
+      }
+    }
+    for (int k0 = 0; k0 < npv; k0 += SP) {  // npv is a multiple of SP
+      T lb[ROWS][SP];
+#pragma unroll
+      for (int r = 0; r < ROWS; r++) {
+        const T* row = A + (size_t)phys[r] * lda + j0 + k0;
+#pragma unroll
+        for (int u = 0; u < SP; u += 4) {
+          if (!done[r]) Vec4<T>::load(row + u, lb[r] + u);
+          else lb[r][u] = lb[r][u + 1] = lb[r][u + 2] = lb[r][u + 3] = T(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SP; u++) {
+        T ubr[SP];
+#pragma unroll
+        for (int c = 0; c < SP; c++) ubr[c] = sm.ub[(k0 + u) * SP + c];
+#pragma unroll
+        for (int r = 0; r < ROWS; r++)
+#pragma unroll
+          for (int c = 0; c < SP; c++) v[r][c] -= lb[r][u] * ubr[c];
+      }
+    }
+    // (c)
+    int pivslot[SP];
+#pragma unroll
+    for (int c = 0; c < SP; c++) {
+      T best = T(-1);
+      int bslot = 0x7fffffff;
+#pragma unroll
+      for (int r = 0; r < ROWS; r++) {
+        if (!done[r]) {
+          T a = fabs(v[r][c]);
+          if (a != a) a = T(INFINITY);  // a NaN is taken as the pivot and flagged below
+          const int s = tid + kLuThreads * r;
+          if (a > best || (a == best && s < bslot)) { best = a; bslot = s; }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const T ob = __shfl_xor(best, off);
+        const int os = __shfl_xor(bslot, off);
+        if (ob > best || (ob == best && os < bslot)) { best = ob; bslot = os; }
+      }
+      const int buf = c & 1;
+      if (bslot == 0x7fffffff) {
+        if (lane == 0) { sm.wval[buf][wave] = T(-1); sm.wslot[buf][wave] = bslot; }
+      } else if ((bslot & (kLuThreads - 1)) == tid) {
+        sm.wval[buf][wave] = best;
+        sm.wslot[buf][wave] = bslot;
+#pragma unroll
+        for (int r = 0; r < ROWS; r++)
+          if (r == bslot / kLuThreads)
+#pragma unroll
+            for (int cc = 0; cc < SP; cc++) sm.wrow[buf][wave][cc] = v[r][cc];
+      }
+      __syncthreads();
+      int wbest = 0;
+      best = sm.wval[buf][0];
+      bslot = sm.wslot[buf][0];
+#pragma unroll
+      for (int w = 1; w < kLuWaves; w++) {
+        const T ob = sm.wval[buf][w];
+        const int os = sm.wslot[buf][w];
+        if (ob > best || (ob == best && os < bslot)) { best = ob; bslot = os; wbest = w; }
+      }
+      const int ps = bslot;
+      pivslot[c] = ps;
+      T pr[SP];
+#pragma unroll
+      for (int cc = 0; cc < SP; cc++) pr[cc] = sm.wrow[buf][wbest][cc];
+      if ((ps & (kLuThreads - 1)) == tid) {
+#pragma unroll
+        for (int r = 0; r < ROWS; r++)
+          if (r == ps / kLuThreads) done[r] = true;
+      }
+      if (tid == 0) {
+#pragma unroll
+        for (int cc = 0; cc < SP; cc++) sm.PR[c * SP + cc] = pr[cc];
+      }
+      const T pv = pr[c];
+      if (!(pv != T(0) && isfinite(pv)) && info == 0) info = c0 + c + 1;
+      const T inv = pv != T(0) ? T(1) / pv : T(0);
+#pragma unroll
+      for (int r = 0; r < ROWS; r++) {
+        if (!done[r]) {
+          const T l = v[r][c] * inv;
+          v[r][c] = l;
+#pragma unroll
+          for (int cc = c + 1; cc < SP; cc++) v[r][cc] -= l * pr[cc];
+        }
+      }
+    }
+    // (d)
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+      const int s = tid + kLuThreads * r;
+      if (s < nrem) {
+        T* row = A + (size_t)phys[r] * lda;
+#pragma unroll
+        for (int c = 0; c < SP; c++) row[c0 + c] = v[r][c];
+      }
+    }
+    // (e)
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int pre[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+      const int s = tid + kLuThreads * r;
+      const bool keep = (s < nrem) && !done[r];
+      const unsigned long long mask = __ballot(keep);
+      pre[r] = __popcll(mask & lt);
+      if (lane == 0) sm.cnt[r * kLuWaves + wave] = __popcll(mask);
+    }
+    __syncthreads();
+    int base = c0 + SP;
+#pragma unroll
+    for (int r = 0; r < ROWS; r++) {
+      const int s = tid + kLuThreads * r;
+      int before = 0, tot = 0;
+#pragma unroll
+      for (int w = 0; w < kLuWaves; w++) {
+        const int cw = sm.cnt[r * kLuWaves + w];
+        tot += cw;
+        if (w < wave) before += cw;
+      }
+      if (s < nrem && !done[r]) perm[base + before + pre[r]] = phys[r];
+      base += tot;
+    }
+#pragma unroll
+    for (int c = 0; c < SP; c++) {
+      const int ps = pivslot[c];
+      if ((ps & (kLuThreads - 1)) == tid) {
+#pragma unroll
+        for (int r = 0; r < ROWS; r++)
+          if (r == ps / kLuThreads) perm[c0 + c] = phys[r];
+      }
+    }
+    __syncthreads();
+    // (f) M <- [[M, 0], [-Lq^{-1} lq M, Lq^{-1}]],  Nn <- [[Nn, -Nn ub Uq^{-1}], [0, Uq^{-1}]]
+    for (int e = tid; e < SP * npv; e += kLuThreads) {
+      const int i = e / npv, k = e - i * npv;
+      sm.lq[i * 64 + k] = A[(size_t)perm[c0 + i] * lda + j0 + k];
+    }
+    __syncthreads();
+    for (int e = tid; e < SP * npv; e += kLuThreads) {
+      const int i = e / npv, j = e - i * npv;
+      T s = T(0);
+      for (int k = j; k < npv; k++) s += sm.lq[i * 64 + k] * sm.M[k * 65 + j];
+      sm.t1[i * 64 + j] = s;
+    }
+    for (int e = tid; e < npv * SP; e += kLuThreads) {
+      const int r = e / SP, c = e - r * SP;
+      T s = T(0);
+      for (int i = r; i < npv; i++) s += sm.Nn[r * 65 + i] * sm.ub[i * SP + c];
+      sm.stg[e] = s;
+    }
+    __syncthreads();
+    if (tid < npv + SP) {
+      const int j = tid;
+      T x[SP];
+#pragma unroll
+      for (int i = 0; i < SP; i++) {
+        T s = j < npv ? -sm.t1[i * 64 + j] : (j - npv == i ? T(1) : T(0));
+#pragma unroll
+        for (int r = 0; r < i; r++) s -= sm.PR[i * SP + r] * x[r];
+        x[i] = s;
+        sm.M[(npv + i) * 65 + j] = s;
+      }
+    } else if (tid >= 64 && tid < 64 + SP) {
+      const int j = tid - 64;
+      T y[SP];
+#pragma unroll
+      for (int i = SP - 1; i >= 0; i--) {
+        T s = (i == j) ? T(1) : T(0);
+#pragma unroll
+        for (int k = i + 1; k < SP; k++) s -= sm.PR[i * SP + k] * y[k];
+        y[i] = s / sm.PR[i * SP + i];
+      }
+#pragma unroll
+      for (int i = 0; i < SP; i++) sm.uq[i * SP + j] = i <= j ? y[i] : T(0);
+    }
+    __syncthreads();
+    for (int e = tid; e < (npv + SP) * SP; e += kLuThreads) {
+      const int r = e / SP, j = e - r * SP;
+      T s;
+      if (r < npv) {
+        s = T(0);
+#pragma unroll
+        for (int i = 0; i < SP; i++) s -= sm.stg[r * SP + i] * sm.uq[i * SP + j];
+      } else {
+        s = sm.uq[(r - npv) * SP + j];
+      }
+      sm.Nn[r * 65 + npv + j] = s;
+    }
+    __syncthreads();
+  }
+  T* Linv = dinv_panel;
+  T* Uinv = dinv_panel + 64 * 64;
+  for (int e = tid; e < W * W; e += kLuThreads) {
+    const int i = e / W, k = e - i * W;
+    Linv[i * 64 + k] = i > k ? sm.M[i * 65 + k] : (i == k ? T(1) : T(0));
+    Uinv[i * 64 + k] = i <= k ? sm.Nn[i * 65 + k] : T(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+__device__ inline bool map_box_tile(int nbox, int ntile, int& box, int& tile) {
+  // consecutive workgroup ids go round-robin to the 8 XCDs: give all tiles of a
+  // box ids on one XCD so they share its L2
+  const int id = blockIdx.x;
+  const int xcd = id & 7, slot = id >> 3;
+  const int lb = slot / ntile;
+  tile = slot - lb * ntile;
+  box = xcd + 8 * lb;
+  return box < nbox;
+}
+
+__global__ void lu_init_kernel(int N, int* perm_all, int* info, int nbox) {
+  const int box = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+    perm_all[(size_t)box * N + i] = i;
+  if (blockIdx.x == 0 && threadIdx.x == 0) info[box] = 0;
+}
+
+template <typename T, int ROWS, int SP, int W>
+__global__ __launch_bounds__(kLuThreads, 1) void lu_panel_kernel(Geom g, T* A_all, int* perm_all, T* dinv_all,
+                                                                  int* info_all, int nbox, int c0) {
+  __shared__ LuSmem<T> sm;
+  const int box = blockIdx.x;
+  if (box >= nbox) return;
+  const int N = g.n_pad;
+  T* A = A_all + (size_t)box * N * N;
+  int* perm = perm_all + (size_t)box * N;
+  T* dp = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(c0 / kPanel) * 2 * 64 * 64;
+  int info = 0;
+  lu_panel<T, ROWS, SP, W>(g, A, perm, c0, sm, info, dp);
+  if (threadIdx.x == 0 && info != 0 && info_all[box] == 0) info_all[box] = info;
+}
+
+template <typename T> struct GemmCfg;
+template <> struct GemmCfg<float> { typedef TileGemm<float, 4, 4, 2, 2, 32> G; };
+template <> struct GemmCfg<double> { typedef TileGemm<double, 4, 2, 2, 2, 16> G; };
+
+// C[row(pos)][n] -= sum_k F[perm[pos]][k] * B[row(k)][n] for pos in [m0,m1),
+// n in [n0,n1), k in [k0,k1).  F is the factor (ld n_pad, rows via perm); B and
+// C are the target X: the factor itself (PERM, rows via perm) or a right-hand
+// side block (rows direct, ld ldx).  Row and k ranges never overlap within one
+// op, so reads and writes are disjoint.
+template <typename T, bool PERM>
+__global__ __launch_bounds__(256, 2) void gemm_op_kernel(Geom g, const T* F_all, const int* perm_all, T* X_all,
+                                                         int ld, size_t xstride, int m0, int m1, int n0, int n1,
+                                                         int k0, int k1, int nbox, int ntm, int ntn,
+                                                         const int* active) {
+  typedef typename GemmCfg<T>::G G;
+  constexpr int WRT = G::MT / (2 * 16), WCT = G::NT / (2 * 16);
+  __shared__ T smem[G::SMEM];
+  int box, tile;
+  if (!map_box_tile(nbox, ntm * ntn, box, tile)) return;
+  if (active && active[box] == 0) return;
+  const int N = g.n_pad;
+  const T* F = F_all + (size_t)box * N * N;
+  const int* perm = perm_all + (size_t)box * N;
+  T* X = X_all + (size_t)box * xstride;
+  const int tm = tile / ntn, tn = tile - tm * ntn;
+  const int mt = m0 + tm * G::MT, nt = n0 + tn * G::NT;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = wave % 2, wn = wave / 2;
+  typename G::acc_t acc[WRT][WCT];
+#pragma unroll
+  for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+    for (int ct = 0; ct < WCT; ct++) acc[rt][ct] = Mfma<T>::zero();
+  auto arow = [&](int r) -> const T* {
+    const int pos = mt + r;
+    return pos < m1 ? F + (size_t)perm[pos] * N : nullptr;
+  };
+  auto brow = [&](int k) -> const T* { return X + (size_t)(PERM ? perm[k] : k) * ld + nt; };
+  const int bcols = (n1 - nt) < G::NT ? (n1 - nt) : G::NT;
+  G::run(acc, arow, brow, bcols, k0, k1, smem);
+#pragma unroll
+  for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int pos = mt + (wm * WRT + rt) * 16 + Mfma<T>::row(lane, i);
+      if (pos < m1) {
+        T* row = X + (size_t)(PERM ? perm[pos] : pos) * ld + nt + wn * WCT * 16 + (lane & 15);
+#pragma unroll
+        for (int ct = 0; ct < WCT; ct++)
+          if (nt + (wn * WCT + ct) * 16 < n1) row[ct * 16] += acc[rt][ct][i];
+      }
+    }
+}
+
+// X[row(r0+i)][c] := sum_j Inv[i][j] X[row(r0+j)][c] for one 64-column tile,
+// Inv the stored inverse of the diagonal block of L (lower) or U (upper).
+constexpr int kLeafLd = 64 + 4;
+
+template <typename T, int W, bool UPPER, bool PERM>
+__global__ __launch_bounds__(256) void leaf_op_kernel(Geom g, const int* perm_all, const T* dinv_all, T* X_all,
+                                                      int ld, size_t xstride, int r0, int cA, int cB, int nbox,
+                                                      int ntn, const int* active) {
+  constexpr int NRT = W / 16;      // row tiles: 4 (W=64) or 2 (W=32)
+  constexpr int NCG = 4 / NRT;     // column groups over the 4 waves
+  constexpr int CT = 4 / NCG;      // 16-column tiles per wave
+  __shared__ T xs[64 * kLeafLd];
+  int box, tn;
+  if (!map_box_tile(nbox, ntn, box, tn)) return;
+  if (active && active[box] == 0) return;
+  const int N = g.n_pad;
+  const int* perm = perm_all + (size_t)box * N;
+  const T* Inv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(r0 / kPanel) * 2 * 64 * 64 +
+                 (UPPER ? 64 * 64 : 0);
+  T* X = X_all + (size_t)box * xstride;
+  const int c0 = cA + tn * 64;
+  const int ncol = (cB - c0) < 64 ? (cB - c0) : 64;
+  for (int e = threadIdx.x; e < W * 64; e += 256) {
+    const int i = e >> 6, c = e & 63;
+    xs[i * kLeafLd + c] = c < ncol ? X[(size_t)(PERM ? perm[r0 + i] : r0 + i) * ld + c0 + c] : T(0);
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rt = wave % NRT, cg = wave / NRT;
+  typename Mfma<T>::acc out[1][CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++) out[0][ct] = Mfma<T>::zero();
+  auto arow = [&](int) -> const T* { return Inv + (rt * 16 + (lane & 15)) * 64; };
+  wg_gemm_lds_add<T, 1, CT>(out, arow, xs, kLeafLd, W, cg * CT * 16);
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int r = rt * 16 + Mfma<T>::row(lane, i);
+      const int c = (cg * CT + ct) * 16 + (lane & 15);
+      if (c < ncol) X[(size_t)(PERM ? perm[r0 + r] : r0 + r) * ld + c0 + c] = out[0][ct][i];
+    }
+}
+
+// Y[box][i][:] = B[box][perm[i]][:]
+template <typename T>
+__global__ void gather_rows_kernel(Geom g, const int* perm_all, const T* B_all, T* Y_all, int nbox,
+                                   const int* active) {
+  const int box = blockIdx.y;
+  if (active && active[box] == 0) return;
+  const int N = g.n_pad, ldx = g.ldx;
+  const int* perm = perm_all + (size_t)box * N;
+  const T* B = B_all + (size_t)box * N * ldx;
+  T* Y = Y_all + (size_t)box * N * ldx;
+  for (int r = blockIdx.x; r < N; r += gridDim.x) {
+    const T* src = B + (size_t)perm[r] * ldx;
+    for (int c = threadIdx.x; c < ldx; c += blockDim.x) Y[(size_t)r * ldx + c] = src[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side sequencing
+// ---------------------------------------------------------------------------
+static int grid_for(int nbox, int ntile) { return 8 * ((nbox + 7) / 8) * ntile; }
+
+template <typename T, bool PERM>
+static hipError_t launch_gemm(const Geom& g, const T* F, const int* perm, T* X, int ld, size_t xstride, const int* op,
+                              int nbox, const int* active, hipStream_t st) {
+  typedef typename GemmCfg<T>::G G;
+  const int m0 = op[1], m1 = op[2], n0 = op[3], n1 = op[4], k0 = op[5], k1 = op[6];
+  const int ntm = (m1 - m0 + G::MT - 1) / G::MT, ntn = (n1 - n0 + G::NT - 1) / G::NT;
+  hipLaunchKernelGGL((gemm_op_kernel<T, PERM>), dim3(grid_for(nbox, ntm * ntn)), dim3(256), 0, st, g, F, perm, X, ld,
+                     xstride, m0, m1, n0, n1, k0, k1, nbox, ntm, ntn, active);
+  return hipGetLastError();
+}
+
+template <typename T, bool UPPER, bool PERM>
+static hipError_t launch_leaf(const Geom& g, const int* perm, const T* dinv, T* X, int ld, size_t xstride,
+                              const int* op, int nbox, const int* active, hipStream_t st) {
+  const int r0 = op[1], w = op[2], cA = op[3], cB = op[4];
+  const int ntn = (cB - cA + 63) / 64;
+  if (w == 64)
+    hipLaunchKernelGGL((leaf_op_kernel<T, 64, UPPER, PERM>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, perm,
+                       dinv, X, ld, xstride, r0, cA, cB, nbox, ntn, active);
+  else
+    hipLaunchKernelGGL((leaf_op_kernel<T, 32, UPPER, PERM>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, perm,
+                       dinv, X, ld, xstride, r0, cA, cB, nbox, ntn, active);
+  return hipGetLastError();
+}
+
+template <typename T, int ROWS, int SP>
+static hipError_t launch_panel(const Geom& g, T* A, int* perm, T* dinv, int* info, int nbox, int c0, int w,
+                               hipStream_t st) {
+  if (w == 64)
+    hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, SP, 64>), dim3(nbox), dim3(kLuThreads), 0, st, g, A, perm, dinv,
+                       info, nbox, c0);
+  else
+    hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, SP, 32>), dim3(nbox), dim3(kLuThreads), 0, st, g, A, perm, dinv,
+                       info, nbox, c0);
+  return hipGetLastError();
+}
+
+template <typename T, int ROWS, int SP>
+static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
+                         hipStream_t st) {
+  const int N = g.n_pad;
+  hipLaunchKernelGGL(lu_init_kernel, dim3((N + 255) / 256, nbox), dim3(256), 0, st, N, perm, info, nbox);
+  hipError_t e = hipGetLastError();
+  for (size_t q = 0; q + 8 <= ops.size() && e == hipSuccess; q += 8) {
+    const int* op = ops.data() + q;
+    if (op[0] == kOpPanel) e = launch_panel<T, ROWS, SP>(g, A, perm, dinv, info, nbox, op[1], op[2], st);
+    else if (op[0] == kOpLeaf) e = launch_leaf<T, false, true>(g, perm, dinv, A, N, (size_t)N * N, op, nbox, nullptr, st);
+    else e = launch_gemm<T, true>(g, A, perm, A, N, (size_t)N * N, op, nbox, nullptr, st);
+  }
+  return e;
+}
+
+template <typename T>
+hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
+                     hipStream_t st) {
+  const int rows = (g.n_pad + kLuThreads - 1) / kLuThreads;
+  constexpr int SP = sizeof(T) == 4 ? 8 : 4;
+  if (rows <= 1) return run_lu<T, 1, SP>(g, ops, A, perm, dinv, info, nbox, st);
+  if (rows <= 2) return run_lu<T, 2, SP>(g, ops, A, perm, dinv, info, nbox, st);
+  if (rows <= 4) return run_lu<T, 4, SP>(g, ops, A, perm, dinv, info, nbox, st);
+  if (rows <= 6) return run_lu<T, 6, SP>(g, ops, A, perm, dinv, info, nbox, st);
+  if (rows <= 8) return run_lu<T, 8, SP>(g, ops, A, perm, dinv, info, nbox, st);
+  if (rows <= 12) return run_lu<T, 12, SP>(g, ops, A, perm, dinv, info, nbox, st);
+  return hipErrorInvalidValue;
+}
+
+// X = A^{-1} B for every active box: Y = P B (gather), forward ops with L, backward
+// ops with U, in place in Y (B and Y must not alias).
+template <typename T>
+hipError_t getrs_run(const Geom& g, const std::vector<int>& fwd, const std::vector<int>& bwd, const T* F,
+                     const int* perm, const T* dinv, const T* B, T* Y, int nbox, const int* active, hipStream_t st) {
+  const size_t xs = (size_t)g.n_pad * g.ldx;
+  hipLaunchKernelGGL((gather_rows_kernel<T>), dim3(g.n_pad < 512 ? g.n_pad : 512, nbox), dim3(256), 0, st, g, perm, B,
+                     Y, nbox, active);
+  hipError_t e = hipGetLastError();
+  for (size_t q = 0; q + 8 <= fwd.size() && e == hipSuccess; q += 8) {
+    const int* op = fwd.data() + q;
+    if (op[0] == kOpLeaf) e = launch_leaf<T, false, false>(g, perm, dinv, Y, g.ldx, xs, op, nbox, active, st);
+    else e = launch_gemm<T, false>(g, F, perm, Y, g.ldx, xs, op, nbox, active, st);
+  }
+  for (size_t q = 0; q + 8 <= bwd.size() && e == hipSuccess; q += 8) {
+    const int* op = bwd.data() + q;
+    if (op[0] == kOpLeaf) e = launch_leaf<T, true, false>(g, perm, dinv, Y, g.ldx, xs, op, nbox, active, st);
+    else e = launch_gemm<T, false>(g, F, perm, Y, g.ldx, xs, op, nbox, active, st);
+  }
+  return e;
+}
+
+template hipError_t getrf_run<float>(const Geom&, const std::vector<int>&, float*, int*, float*, int*, int, hipStream_t);
+template hipError_t getrf_run<double>(const Geom&, const std::vector<int>&, double*, int*, double*, int*, int,
+                                      hipStream_t);
+template hipError_t getrs_run<float>(const Geom&, const std::vector<int>&, const std::vector<int>&, const float*,
+                                     const int*, const float*, const float*, float*, int, const int*, hipStream_t);
+template hipError_t getrs_run<double>(const Geom&, const std::vector<int>&, const std::vector<int>&, const double*,
+                                      const int*, const double*, const double*, double*, int, const int*,
+                                      hipStream_t);
+
+}  // namespace hps
