@@ -1,0 +1,198 @@
+"""Batched leaf reduction of several independent problems in one stream (spec a7).
+
+The paper batches boxes of one polynomial order and suggests separate arrays per
+order when p varies over a small set (Sec. 3.2, last paragraphs; its two-level
+scheduler caps how many DtN maps are built at once).  Here every problem is a
+size group with its own plan and buffers; each group is cut into chunks that
+fit an HBM budget, and every chunk runs operators -> LU -> solves/refinement ->
+DtN scatter as kernel launches that cover all boxes of the chunk.  The whole
+sequence of launches can be captured once in a HIP graph and replayed (no host
+work, no allocation, no memset nodes inside), and the chunk size per group can
+be picked by timing candidates (`autotune`).
+"""
+from __future__ import annotations
+
+import json
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import interface as itf
+from .leaf import LeafPlan, hps_interface_reduce
+from .solver import _box_origins
+
+
+@dataclass
+class Group:
+    nboxes: tuple
+    lo: tuple
+    hi: tuple
+    p: int
+    kappa: float
+    plan: LeafPlan = None
+    layout: itf.InterfaceLayout = None
+    chunk: int = 0
+    bufs: dict = None
+    b: torch.Tensor = None
+    f: Optional[torch.Tensor] = None
+    g_dir: torch.Tensor = None
+    T_vals: torch.Tensor = None
+    g_loads: torch.Tensor = None
+    info: torch.Tensor = None
+    iters: torch.Tensor = None
+    berr: torch.Tensor = None
+    slot_map: torch.Tensor = None
+    pairs: torch.Tensor = None
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def nbox(self) -> int:
+        return int(np.prod(self.nboxes))
+
+    @property
+    def h(self):
+        return tuple((self.hi[a] - self.lo[a]) / self.nboxes[a] for a in range(3))
+
+
+def bytes_per_box(info) -> int:
+    return info.a_bytes + info.perm_bytes + info.dinv_bytes + info.x_bytes + info.ws_bytes
+
+
+class BatchedLeafReduction:
+    """Build stage (Alg. 1 loop) for several problems, one stream, optional graph."""
+
+    def __init__(self, problems, precision: str = "fp32_ir", hbm_budget: float = 64e9, ir_max_iter: int = 3,
+                 ir_tol: float = 1e-11, chunks: Optional[List[int]] = None, device="cuda"):
+        self.device = torch.device(device)
+        self.precision = precision
+        self.groups: List[Group] = []
+        for q, pr in enumerate(problems):
+            gr = Group(nboxes=tuple(pr.nboxes), lo=tuple(pr.lo), hi=tuple(pr.hi), p=int(pr.p), kappa=float(pr.kappa))
+            gr.plan = LeafPlan(gr.p, gr.h, gr.kappa, precision, ir_max_iter, ir_tol)
+            gr.layout = itf.build_layout(gr.nboxes, gr.plan.info.m)
+            per_box = bytes_per_box(gr.plan.info)
+            fit = max(1, int(hbm_budget // max(per_box, 1)))
+            gr.chunk = int(chunks[q]) if chunks else min(gr.nbox, fit)
+            self.groups.append(gr)
+        self.graph = None
+
+    def set_inputs(self, q: int, b: torch.Tensor, f: Optional[torch.Tensor], g_dir: torch.Tensor) -> None:
+        gr = self.groups[q]
+        gr.b, gr.f, gr.g_dir = b.contiguous(), (f.contiguous() if f is not None else None), g_dir.contiguous()
+
+    def sample_inputs(self, q: int, prob) -> None:
+        """Evaluate the problem's b, f, g at this group's nodes (device tensors)."""
+        gr = self.groups[q]
+        i = gr.plan.info
+        org = torch.tensor(_box_origins(gr.nboxes, gr.lo, gr.h), device=self.device)
+        xi = torch.empty(gr.nbox * i.n_i * 3, dtype=torch.float64, device=self.device)
+        xb = torch.empty(gr.nbox * i.n_b * 3, dtype=torch.float64, device=self.device)
+        gr.plan.hps_leaf_nodes(gr.nbox, org, xi, xb)
+        xi_h = xi.view(gr.nbox, i.n_i, 3).cpu().numpy()
+        xb_h = xb.view(gr.nbox, i.n_b, 3).cpu().numpy()
+        bmask = itf.boundary_mask(gr.layout)
+        b = torch.tensor(prob.b(xi_h), device=self.device)
+        f = torch.tensor(prob.f(xi_h), device=self.device)
+        g = torch.tensor(np.where(bmask, prob.g(xb_h), 0.0), device=self.device)
+        gr.extra["xi"], gr.extra["xb"] = xi_h, xb_h
+        self.set_inputs(q, b, f, g)
+
+    def allocate(self) -> None:
+        for gr in self.groups:
+            i = gr.plan.info
+            mm = i.m * i.m
+            gr.bufs = gr.plan.alloc(gr.chunk, self.device)
+            gr.T_vals = torch.zeros(gr.layout.nslot_total * mm * mm + 1, dtype=torch.float64, device=self.device)
+            gr.g_loads = torch.zeros(gr.nbox, i.n_b, dtype=torch.float64, device=self.device)
+            gr.info = torch.zeros(gr.nbox, dtype=torch.int32, device=self.device)
+            gr.iters = torch.zeros(gr.nbox, dtype=torch.int32, device=self.device)
+            gr.berr = torch.zeros(gr.nbox, dtype=torch.float64, device=self.device)
+            gr.slot_map = torch.tensor(gr.layout.slot_map, device=self.device)
+            gr.pairs = torch.tensor(gr.layout.reduce_pairs, device=self.device)
+
+    def enqueue(self) -> None:
+        """All launches of the build stage for every group, on the current stream."""
+        for gr in self.groups:
+            plan, B, C, mm = gr.plan, gr.bufs, gr.chunk, gr.plan.info.m ** 2
+            for c0 in range(0, gr.nbox, C):
+                nb = min(C, gr.nbox - c0)
+                sl = slice(c0, c0 + nb)
+                plan.hps_leaf_operators(nb, gr.b[sl], B["A"], B["anorm"])
+                plan.hps_leaf_factor(nb, B["A"], B["perm"], B["dinv"], gr.info[sl])
+                plan.hps_leaf_dtn(nb, B["A"], B["perm"], B["dinv"], gr.b[sl], B["anorm"],
+                                  gr.f[sl] if gr.f is not None else None, gr.g_dir[sl], gr.slot_map[sl],
+                                  gr.T_vals, gr.g_loads[sl], B["X"], gr.iters[sl], gr.berr[sl], B["ws"])
+            if gr.pairs.shape[0]:
+                hps_interface_reduce(gr.pairs, mm * mm, gr.T_vals)
+
+    def capture(self) -> None:
+        """Record the whole build stage in a HIP graph (after one eager warm-up run)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.enqueue()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.enqueue()
+        torch.cuda.synchronize()
+
+    def run(self) -> None:
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self.enqueue()
+
+
+def autotune(problems, precision="fp32_ir", candidates=(128, 256, 512, 1024), hbm_budget=64e9, cache=None,
+             reps=1):
+    """Pick a chunk size per problem by timing the build stage; results cached as JSON.
+
+    Returns a list of chunk sizes.  The cache key is (p, nbox, precision, GPU name).
+    """
+    name = torch.cuda.get_device_name(0)
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as fh:
+            table = json.load(fh)
+    out = []
+    for pr in problems:
+        nbox = int(np.prod(pr.nboxes))
+        key = f"{name}|p={pr.p}|nbox={nbox}|{precision}"
+        if key in table:
+            out.append(int(table[key]["chunk"]))
+            continue
+        best, best_ms, trials = None, float("inf"), {}
+        for c in candidates:
+            c = min(c, nbox)
+            if c in trials:
+                continue
+            br = BatchedLeafReduction([pr], precision, hbm_budget, chunks=[c])
+            if bytes_per_box(br.groups[0].plan.info) * c > hbm_budget:
+                continue
+            br.sample_inputs(0, pr)
+            br.allocate()
+            br.run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                br.run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            trials[c] = ms
+            if ms < best_ms:
+                best, best_ms = c, ms
+            del br
+            torch.cuda.empty_cache()
+        table[key] = {"chunk": best, "ms": best_ms, "trials": trials}
+        out.append(int(best))
+    if cache:
+        with open(cache, "w") as fh:
+            json.dump(table, fh, indent=1)
+    return out

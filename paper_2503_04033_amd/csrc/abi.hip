@@ -115,15 +115,15 @@ Sizes sizes_of(const hps_plan_s* pl) {
   s.dinv = es * (size_t)g.npanel * 2 * 64 * 64;
   s.x = 8 * (size_t)g.n_pad * g.ldx;
   const size_t elems = (size_t)g.n_pad * g.ldx;
-  // FP32_IR: B32, Y32, Rz (FP64); FP64: B64 (reused as Rz).  Plus per-box scalars.
-  s.ws = (pl->desc.precision == HPS_FP32_IR ? 16 : 8) * elems + 64;
+  // FP32_IR: B32 (right-hand side, later the FP32 residual) and Y32; FP64: B64.
+  // Plus per-box scalars.
+  s.ws = 8 * elems + 64;
   return s;
 }
 
 struct WsLayout {
   void* B;      // B32 or B64
   float* Y32;
-  double* Rz;
   double *maxb, *maxr, *maxx;
   int* active;
 };
@@ -133,17 +133,9 @@ WsLayout ws_layout(const hps_plan_s* pl, int nbox, void* ws) {
   const size_t elems = (size_t)g.n_pad * g.ldx * nbox;
   char* p = static_cast<char*>(ws);
   WsLayout L;
-  if (pl->desc.precision == HPS_FP32_IR) {
-    L.B = p;
-    L.Y32 = reinterpret_cast<float*>(p + 4 * elems);
-    L.Rz = reinterpret_cast<double*>(p + 8 * elems);
-    p += 16 * elems;
-  } else {
-    L.B = p;
-    L.Y32 = nullptr;
-    L.Rz = reinterpret_cast<double*>(p);
-    p += 8 * elems;
-  }
+  L.B = p;
+  L.Y32 = pl->desc.precision == HPS_FP32_IR ? reinterpret_cast<float*>(p + 4 * elems) : nullptr;
+  p += 8 * elems;
   L.maxb = reinterpret_cast<double*>(p);
   L.maxr = L.maxb + nbox;
   L.maxx = L.maxr + nbox;
@@ -213,6 +205,11 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
   sched_lu(pl->lu_ops, 0, g.n_pad, g.n_pad);
   sched_trsm(pl->fwd_ops, 0, g.n_pad, 0, g.ldx);
   sched_trsm_up(pl->bwd_ops, 0, g.n_pad, 0, g.ldx);
+  if (hps::residual_prepare(g) != hipSuccess) {
+    (void)hipFree(pl->tables);
+    delete pl;
+    return HPS_EDEVICE;
+  }
   *out = pl;
   return HPS_OK;
 }
@@ -289,7 +286,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     if (ir_iters) HPS_TRY(hps::launch_fill_int(ir_iters, 0, nbox, st));
     if (berr) {
       HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
-      HPS_TRY(hps::launch_residual(g, nbox, b, f, X, L.Rz, nullptr, L.maxr, L.maxx, nullptr, st));
+      HPS_TRY(hps::launch_residual(g, nbox, b, f, X, nullptr, L.maxr, L.maxx, nullptr, st));
       HPS_TRY(hps::launch_ir_check(nbox, 0, 1, INFINITY, anorm, L.maxb, L.maxr, L.maxx, L.active, nullptr, berr,
                                    st));
     }
@@ -305,7 +302,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     const double tol = pl->desc.ir_tol;
     for (int it = 0; it <= kmax; it++) {
       const int last = it == kmax;
-      HPS_TRY(hps::launch_residual(g, nbox, b, f, X, L.Rz, B, L.maxr, L.maxx, L.active, st));
+      HPS_TRY(hps::launch_residual(g, nbox, b, f, X, B, L.maxr, L.maxx, L.active, st));
       HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
                                    st));
       if (last) break;

@@ -24,8 +24,9 @@ template <typename T>
 hipError_t launch_operators(const Geom& g, int nbox, const double* b, T* A, double* anorm, hipStream_t st);
 template <typename T>
 hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* maxb, hipStream_t st);
-hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const double* X, double* Rz,
-                           float* R32, double* maxr, double* maxx, const int* active, hipStream_t st);
+hipError_t residual_prepare(const Geom& g);
+hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const double* X, float* R32,
+                           double* maxr, double* maxx, const int* active, hipStream_t st);
 hipError_t launch_ir_check(int nbox, int it, int last, double tol, const double* anorm, const double* maxb,
                            const double* maxr, const double* maxx, int* active, int* iters, double* berr,
                            hipStream_t st);

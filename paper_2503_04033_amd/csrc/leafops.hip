@@ -228,81 +228,65 @@ template hipError_t launch_rhs<float>(const Geom&, int, const double*, float*, d
 template hipError_t launch_rhs<double>(const Geom&, int, const double*, double*, double*, hipStream_t);
 
 // ----------------------------------------------------------------------------
-// FP64 residual R = B - A_ii X through the tensor structure of A_ii.
-// Pass 1 (one wave per z-line and 64 columns): Rz = B + s2z D2 X (along z)
-//                                                  + kappa^2 b X.
-// Pass 2 (workgroup per z-plane and 16 columns, plane staged in LDS):
-//        R = Rz + s2x D2 X (along x) + s2y D2 X (along y); R -> FP32 for the
-//        correction solve, max|R| and max|X| per box.
+// FP64 residual R = B - A_ii X through the tensor structure of A_ii (never a
+// dense FP64 A_ii): -A_ii X = s2x D2 X (along x) + s2y (along y) + s2z (along z)
+// + kappa^2 b X.  One workgroup per (box, CW-column chunk) stages the chunk
+// X[0:n, c0:c0+CW) in LDS (read from HBM once) and forms every output from LDS;
+// R goes to FP32 for the correction solve (R32 may be null), max|R| and max|X|
+// per box feed the stopping test.
 // ----------------------------------------------------------------------------
-constexpr int kMaxM = 18;
+constexpr int kResThreads = 512;
 
-__global__ __launch_bounds__(256) void residual_z_kernel(Geom g, int nbox, const double* b, const double* f,
-                                                         const double* X_all, double* Rz_all, const int* active) {
-  const int box = blockIdx.z;
-  if (active && active[box] == 0) return;
-  const int m = g.m, mm = m * m, n = g.n, ldx = g.ldx, p = g.p;
-  const int pencil = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (pencil >= mm) return;
-  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
-  const int ii = pencil % m, jj = pencil / m;
-  const double* X = X_all + (size_t)box * g.n_pad * ldx;
-  double* Rz = Rz_all + (size_t)box * g.n_pad * ldx;
-  double x[kMaxM];
-#pragma unroll
-  for (int k = 0; k < kMaxM; k++)
-    if (k < m) x[k] = X[(size_t)(pencil + mm * k) * ldx + c];
-#pragma unroll
-  for (int k = 0; k < kMaxM; k++) {
-    if (k < m) {
-    const int node = pencil + mm * k;
-    double s = 0.0;
-#pragma unroll
-    for (int k2 = 0; k2 < kMaxM; k2++)
-      if (k2 < m) s += g.D2[(k + 1) * p + k2 + 1] * x[k2];
-    double bv = 0.0;
-    if (c < g.nb) bv = aib_entry(g, ii, jj, k, c);
-    else if (c == g.nb && f) bv = f[(size_t)box * n + node];
-    Rz[(size_t)node * ldx + c] = bv + g.s2[2] * s + g.kappa2 * b[(size_t)box * n + node] * x[k];
-    }
-  }
+__device__ inline bool map_box_chunk(int nbox, int nchunk, int& box, int& chunk) {
+  const int id = blockIdx.x;
+  const int xcd = id & 7, slot = id >> 3;
+  const int lb = slot / nchunk;
+  chunk = slot - lb * nchunk;
+  box = xcd + 8 * lb;
+  return box < nbox;
 }
 
-constexpr int kResCols = 16;
-
-__global__ __launch_bounds__(256) void residual_xy_kernel(Geom g, int nbox, const double* X_all, const double* Rz_all,
-                                                          float* R32_all, double* maxr, double* maxx,
-                                                          const int* active) {
-  __shared__ double plane[kMaxM * kMaxM * kResCols];
-  __shared__ double d2s[kMaxM * kMaxM];
-  const int box = blockIdx.z;
+template <int CW>
+__global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox, const double* b, const double* f,
+                                                               const double* X_all, float* R32_all, double* maxr,
+                                                               double* maxx, const int* active) {
+  extern __shared__ double xs[];  // [n][CW] then D2 interior block [m][m]
+  int box, chunk;
+  if (!map_box_chunk(nbox, g.ldx / CW, box, chunk)) return;
   if (active && active[box] == 0) return;
-  const int m = g.m, mm = m * m, ldx = g.ldx, p = g.p;
-  const int kk = blockIdx.x;
-  const int c0 = blockIdx.y * kResCols;
+  const int m = g.m, mm = m * m, n = g.n, ldx = g.ldx, p = g.p;
+  double* d2s = xs + (size_t)n * CW;
+  const int c0 = chunk * CW;
   const double* X = X_all + (size_t)box * g.n_pad * ldx;
-  const double* Rz = Rz_all + (size_t)box * g.n_pad * ldx;
-  float* R32 = R32_all + (size_t)box * g.n_pad * ldx;
-  for (int e = threadIdx.x; e < mm * kResCols; e += blockDim.x) {
-    const int node2 = e / kResCols, c = e % kResCols;
-    plane[e] = X[(size_t)(node2 + mm * kk) * ldx + c0 + c];
+  for (int e = threadIdx.x; e < n * CW; e += kResThreads) {
+    const int node = e / CW, c = e - node * CW;
+    xs[e] = X[(size_t)node * ldx + c0 + c];
   }
-  for (int e = threadIdx.x; e < mm; e += blockDim.x) d2s[e] = g.D2[(e / m + 1) * p + e % m + 1];
+  for (int e = threadIdx.x; e < mm; e += kResThreads) d2s[e] = g.D2[(e / m + 1) * p + e % m + 1];
   __syncthreads();
   double mr = 0.0, mxv = 0.0;
-  for (int e = threadIdx.x; e < mm * kResCols; e += blockDim.x) {
-    const int node2 = e / kResCols, c = e % kResCols;
-    const int ii = node2 % m, jj = node2 / m;
-    double ax = 0.0, ay = 0.0;
+  const double* bb = b + (size_t)box * n;
+  for (int e = threadIdx.x; e < n * CW; e += kResThreads) {
+    const int node = e / CW, c = e - node * CW;
+    const int ii = node % m, jj = (node / m) % m, kk = node / mm;
+    const double* xl = xs + (size_t)(node - ii) * CW + c;           // x-line: stride CW
+    const double* yl = xs + (size_t)(node - m * jj) * CW + c;       // y-line: stride m*CW
+    const double* zl = xs + (size_t)(node - mm * kk) * CW + c;      // z-line: stride mm*CW
+    double ax = 0.0, ay = 0.0, az = 0.0;
     for (int q = 0; q < m; q++) {
-      ax += d2s[ii * m + q] * plane[(q + m * jj) * kResCols + c];
-      ay += d2s[jj * m + q] * plane[(ii + m * q) * kResCols + c];
+      ax += d2s[ii * m + q] * xl[q * CW];
+      ay += d2s[jj * m + q] * yl[q * m * CW];
+      az += d2s[kk * m + q] * zl[q * mm * CW];
     }
-    const size_t off = (size_t)(node2 + mm * kk) * ldx + c0 + c;
-    const double r = Rz[off] + g.s2[0] * ax + g.s2[1] * ay;
-    if (R32) R32[off] = (float)r;
+    const int col = c0 + c;
+    const double xv = xs[e];
+    double bv = 0.0;
+    if (col < g.nb) bv = aib_entry(g, ii, jj, kk, col);
+    else if (col == g.nb && f) bv = f[(size_t)box * n + node];
+    const double r = bv + g.s2[0] * ax + g.s2[1] * ay + g.s2[2] * az + g.kappa2 * bb[node] * xv;
+    if (R32_all) R32_all[(size_t)box * g.n_pad * ldx + (size_t)node * ldx + col] = (float)r;
     mr = fmax(mr, fabs(r));
-    mxv = fmax(mxv, fabs(plane[e]));
+    mxv = fmax(mxv, fabs(xv));
   }
   mr = wave_max(mr);
   mxv = wave_max(mxv);
@@ -312,18 +296,33 @@ __global__ __launch_bounds__(256) void residual_xy_kernel(Geom g, int nbox, cons
   }
 }
 
-hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const double* X, double* Rz,
-                           float* R32, double* maxr, double* maxx, const int* active, hipStream_t st) {
+// Kernel attributes are set once per plan (outside any stream capture).
+hipError_t residual_prepare(const Geom& g) {
+  const size_t shm4 = ((size_t)g.n * 4 + g.m * g.m) * sizeof(double);
+  const size_t shm2 = ((size_t)g.n * 2 + g.m * g.m) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&residual_kernel<4>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)(shm4 < 160 * 1024 ? shm4 : 160 * 1024));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&residual_kernel<2>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)(shm2 < 160 * 1024 ? shm2 : 160 * 1024));
+  return e;
+}
+
+hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const double* X, float* R32,
+                           double* maxr, double* maxx, const int* active, hipStream_t st) {
   hipError_t e = launch_fill_zero(maxr, sizeof(double) * nbox, st);
   if (e == hipSuccess) e = launch_fill_zero(maxx, sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
-  const int mm = g.m * g.m;
-  hipLaunchKernelGGL(residual_z_kernel, dim3((mm + 3) / 4, g.ldx / 64, nbox), dim3(256), 0, st, g, nbox, b, f, X, Rz,
-                     active);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(residual_xy_kernel, dim3(g.m, g.ldx / kResCols, nbox), dim3(256), 0, st, g, nbox, X, Rz, R32,
-                     maxr, maxx, active);
+  const int grid_boxes = 8 * ((nbox + 7) / 8);
+  if ((size_t)g.n * 4 * sizeof(double) + g.m * g.m * sizeof(double) <= 96 * 1024) {
+    const size_t shm = ((size_t)g.n * 4 + g.m * g.m) * sizeof(double);
+    hipLaunchKernelGGL(residual_kernel<4>, dim3(grid_boxes * (g.ldx / 4)), dim3(kResThreads), shm, st, g, nbox, b, f,
+                       X, R32, maxr, maxx, active);
+  } else {
+    const size_t shm = ((size_t)g.n * 2 + g.m * g.m) * sizeof(double);
+    hipLaunchKernelGGL(residual_kernel<2>, dim3(grid_boxes * (g.ldx / 2)), dim3(kResThreads), shm, st, g, nbox, b, f,
+                       X, R32, maxr, maxx, active);
+  }
   return hipGetLastError();
 }
 

@@ -1,0 +1,77 @@
+"""GPU parity of the misfit gradient dJ/db (adjoint of the two-level solve).
+
+The oracle computes the same gradient with dense per-box LU and SciPy's sparse
+LU (oracle/adjoint.py, itself pinned to the dense global adjoint and to finite
+differences).  Configuration 5 boxes (p = 10, kappa = 15) are used on a 4^3 grid:
+every per-box GPU operation has the size it has on 8^3 boxes, while the host
+sparse interface solve stays within a test budget.
+Tolerance: FP64 path, 1e-9 relative (l2 over all interior nodes).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint as oa
+from oracle import interface as oi
+from tests.gpu_helpers import rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(nboxes, p, kappa, nobs, seed=5):
+    from paper_2503_04033_amd.solver import TwoLevelSolver
+    inv = W.config5(nboxes=nboxes, p=p, kappa=kappa, seed=seed, nobs=nobs)
+    prob = inv.forward
+    ref_obs = oi.solve(prob, b_field=inv.b_obs)
+    data = oa.observe(ref_obs.u_i, inv.obs_nodes, p)
+    s = TwoLevelSolver.for_problem(prob, precision="fp64")
+    bv, fv, gv, xi, xb = s.sample(prob.b, prob.f, prob.g)
+    tl = oa.obs_local_index(inv.obs_nodes, p)
+    return inv, prob, data, s, bv, fv, gv, xi, torch.tensor(tl, device="cuda")
+
+
+def _gpu_grad(s, bv, fv, gv, tl, data):
+    from paper_2503_04033_amd.adjoint import HPSSolve
+    b = bv.clone().requires_grad_(True)
+    u = HPSSolve.apply(b, s, fv, gv)
+    r = u[tl[:, 0], tl[:, 1]] - torch.tensor(data, device="cuda")
+    J = 0.5 * (r * r).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    return float(J), b.grad.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("nboxes,p,kappa,nobs", [((2, 2, 2), 6, 6.0, 40), ((4, 4, 4), 10, 15.0, 500)])
+def test_adjoint_gradient_matches_oracle(gpu, nboxes, p, kappa, nobs):
+    say(f"adjoint case nboxes={nboxes} p={p} kappa={kappa} nobs={nobs}")
+    inv, prob, data, s, bv, fv, gv, xi, tl = _setup(nboxes, p, kappa, nobs)
+    J, g = _gpu_grad(s, bv, fv, gv, tl, data)
+    J0, g0, _ = oa.two_level_gradient(prob, inv.obs_nodes, data)
+    e = rel(g, g0)
+    say(f"  J gpu {J:.6e} oracle {J0:.6e}; grad rel err {e:.2e}")
+    assert J == pytest.approx(J0, rel=1e-9)
+    assert e < 1e-9
+
+
+def test_adjoint_central_differences(gpu):
+    from paper_2503_04033_amd.adjoint import ResidentForward
+    inv, prob, data, s, bv, fv, gv, xi, tl = _setup((2, 2, 2), 8, 9.0, 60, seed=15)
+    J, g = _gpu_grad(s, bv, fv, gv, tl, data)
+    d = torch.tensor(data, device="cuda")
+    rng = np.random.default_rng(4)
+    for trial in range(2):
+        c = rng.uniform(size=3)
+        v = np.exp(-np.sum((xi - c) ** 2, axis=-1) / 0.05)
+        vd = torch.tensor(v, device="cuda")
+        h = 1e-6
+        Js = []
+        for sgn in (1.0, -1.0):
+            fwd = ResidentForward(s)
+            u, _ = fwd.forward(bv + sgn * h * vd, fv, gv)
+            r = u[tl[:, 0], tl[:, 1]] - d
+            Js.append(0.5 * float((r * r).sum()))
+        fd = (Js[0] - Js[1]) / (2 * h)
+        an = float((g * v).sum())
+        say(f"  direction {trial}: adjoint {an:.8e} central difference {fd:.8e}")
+        assert an == pytest.approx(fd, rel=1e-5, abs=1e-9 * abs(J))
