@@ -115,10 +115,15 @@ class TwoLevelSolver:
         return BuildResult(T_vals=T_vals, g_loads=g_loads, info=info, ir_iters=iters, berr=berr, X=X_all)
 
     # ---- solve stage (Alg. 2) ---------------------------------------------------
-    def solve(self, br: BuildResult, g_dir: torch.Tensor, isolver: Optional[itf.InterfaceSolver] = None):
-        """Return (u_face, u_b [nbox, n_b], u_i [nbox, n_i], interface solver)."""
-        if br.X is None:
-            raise ValueError("reconstruction needs X: build with keep_X=True")
+    def solve(self, br: BuildResult, g_dir: torch.Tensor, isolver: Optional[itf.InterfaceSolver] = None,
+              b: Optional[torch.Tensor] = None, f: Optional[torch.Tensor] = None):
+        """Return (u_face, u_b [nbox, n_b], u_i [nbox, n_i], interface solver).
+
+        With X kept from the build the interiors are one GEMV per box.  Otherwise
+        (keep_X=False) every chunk's operators, factors and X are recomputed here,
+        as the paper does for problems whose local operators do not fit in
+        memory (Sec. 3.2); b and f must then be passed again.
+        """
         if isolver is None:
             isolver = itf.InterfaceSolver(self.layout, br.T_vals.cpu().numpy())
         rhs = itf.interface_rhs(self.layout, br.g_loads.cpu().numpy())
@@ -126,12 +131,33 @@ class TwoLevelSolver:
         ub = itf.box_face_values(self.layout, u_face, g_dir.cpu().numpy())
         ub_d = torch.tensor(ub, device=self.device)
         ui = torch.empty(self.nbox, self.info.n_i, dtype=torch.float64, device=self.device)
-        self.plan.hps_leaf_reconstruct(self.nbox, br.X, ub_d, ui)
+        if br.X is not None:
+            self.plan.hps_leaf_reconstruct(self.nbox, br.X, ub_d, ui)
+            return u_face, ub, ui, isolver
+        if b is None:
+            raise ValueError("recompute mode needs b (and f) again")
+        i, plan, nbox = self.info, self.plan, self.nbox
+        mm = i.m * i.m
+        C = min(self.chunk, nbox)
+        bufs = plan.alloc(C, self.device)
+        scratch_T = torch.zeros(self.layout.nslot_total * mm * mm + 1, dtype=torch.float64, device=self.device)
+        scratch_g = torch.empty(C, i.n_b, dtype=torch.float64, device=self.device)
+        for c0 in range(0, nbox, C):
+            nb = min(C, nbox - c0)
+            sl = slice(c0, c0 + nb)
+            bb = b[sl].contiguous()
+            ff = f[sl].contiguous() if f is not None else None
+            plan.hps_leaf_operators(nb, bb, bufs["A"], bufs["anorm"])
+            plan.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], bufs["info"])
+            plan.hps_leaf_dtn(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
+                              g_dir[sl].contiguous(), self.slot_map[sl].contiguous(), scratch_T, scratch_g[:nb],
+                              bufs["X"], bufs["ir_iters"], bufs["berr"], bufs["ws"])
+            plan.hps_leaf_reconstruct(nb, bufs["X"], ub_d[sl].contiguous(), ui[sl])
         return u_face, ub, ui, isolver
 
     def solve_problem(self, prob):
         bv, fv, gv, xi, xb = self.sample(prob.b, prob.f, prob.g)
         br = self.build(bv, fv, gv)
-        u_face, ub, ui, isolver = self.solve(br, gv)
+        u_face, ub, ui, isolver = self.solve(br, gv, b=bv, f=fv)
         return {"build": br, "u_face": u_face, "u_b": ub, "u_i": ui, "xi": xi, "xb": xb, "b": bv, "f": fv,
                 "g_dir": gv, "isolver": isolver}

@@ -109,6 +109,28 @@ def test_pipeline_ragged_grid(gpu, precision, tol):
     _pipeline(prob, precision, tol)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32_ir", IR_TOL)])
+def test_pipeline_recompute_chunked(gpu, precision, tol):
+    # chunks of 5 boxes (ragged last chunk) and X recomputed in the solve stage
+    from paper_2503_04033_amd.solver import TwoLevelSolver
+    prob = W.multi_bump((3, 2, 2), 7, 8.0, 23, gaussian_source=True, name="recompute_p7")
+    say(f"pipeline recompute {prob.name} {precision}")
+    s = TwoLevelSolver.for_problem(prob, precision=precision, chunk=5, keep_X=False)
+    out = s.solve_problem(prob)
+    torch.cuda.synchronize()
+    ref = oi.solve(prob)
+    eu = rel(out["u_i"].cpu().numpy(), ref.u_i)
+    ef = rel(out["u_face"], ref.u_face)
+    say(f"  u_i err {eu:.2e}  u_face err {ef:.2e}")
+    assert eu < tol and ef < tol
+
+
+def test_leaf_p20_sampled_fp32_ir(gpu):
+    # the 4^3, p = 20 case of configuration 3 (5832 interior nodes, ragged last panel)
+    prob = W.config3_p20()
+    _check_leaf(prob, [21], "fp32_ir", IR_TOL, f_on=False)
+
+
 def test_pipeline_single_box(gpu):
     prob = W.multi_bump((1, 1, 1), 7, 5.0, 22, gaussian_source=True, name="one_box")
     _pipeline(prob, "fp64", FP64_TOL)
