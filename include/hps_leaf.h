@@ -178,6 +178,24 @@ hps_status hps_leaf_adjoint_grad(hps_plan plan, int32_t nbox, const double* lam_
 /* Human-readable message for a status code (static storage). */
 const char* hps_status_string(hps_status s);
 
+/* Kernel timing (tracing aid, not part of the method).  While enabled, every
+ * launch the plan makes is bracketed by HIP events on its stream and counted
+ * per kernel family; hps_plan_profile_read synchronizes on the recorded events
+ * and returns, per family, launches, total milliseconds and the algorithmic
+ * flops of those launches (2*M*N*K for tile GEMMs, 2*w*w*ncols for leaves, 0
+ * for bandwidth kernels).  Families: 0 LU GEMM, 1 LU panel, 2 LU leaf,
+ * 3 solve GEMM, 4 solve leaf, 5 residual, 6 DtN, 7 operators.  Enabling clears
+ * the counters.  Event recording adds launch overhead; leave it off in
+ * production. */
+#define HPS_PROFILE_FAMILIES 8
+typedef struct {
+  int64_t launches[HPS_PROFILE_FAMILIES];
+  double ms[HPS_PROFILE_FAMILIES];
+  double flops[HPS_PROFILE_FAMILIES];
+} hps_profile;
+hps_status hps_plan_profile_enable(hps_plan plan, int32_t enable);
+hps_status hps_plan_profile_read(hps_plan plan, hps_profile* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,8 +14,10 @@ HPS_FP64, HPS_FP32_IR = 0, 1
 EXPORTS = (
     "hps_plan_create", "hps_plan_destroy", "hps_plan_get_info", "hps_leaf_nodes", "hps_leaf_operators",
     "hps_leaf_factor", "hps_leaf_dtn", "hps_interface_reduce", "hps_leaf_reconstruct", "hps_leaf_adjoint_solve",
-    "hps_leaf_adjoint_grad", "hps_status_string",
+    "hps_leaf_adjoint_grad", "hps_status_string", "hps_plan_profile_enable", "hps_plan_profile_read",
 )
+
+PROFILE_FAMILIES = ("lu_gemm", "lu_panel", "lu_leaf", "solve_gemm", "solve_leaf", "residual", "dtn", "operators")
 
 
 class LeafDesc(C.Structure):
@@ -28,6 +30,10 @@ class PlanInfo(C.Structure):
                 ("nrhs", C.c_int32), ("ldx", C.c_int32), ("npanel", C.c_int32), ("elem_bytes", C.c_int32),
                 ("a_bytes", C.c_size_t), ("perm_bytes", C.c_size_t), ("dinv_bytes", C.c_size_t),
                 ("x_bytes", C.c_size_t), ("ws_bytes", C.c_size_t)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8), ("flops", C.c_double * 8)]
 
 
 class HpsError(RuntimeError):
@@ -59,6 +65,8 @@ def load() -> C.CDLL:
         "hps_leaf_reconstruct": [P, I32, P, P, P, P],
         "hps_leaf_adjoint_solve": [P, I32, P, P, P, P, P, P, P, P, P, P],
         "hps_leaf_adjoint_grad": [P, I32, P, P, P, P],
+        "hps_plan_profile_enable": [P, I32],
+        "hps_plan_profile_read": [P, C.POINTER(Profile)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -15,6 +15,7 @@ struct hps_plan_s {
   int device;
   double* tables;  // device: t[p], D[p*p], D2[p*p]
   std::vector<int> lu_ops, fwd_ops, bwd_ops;  // schedules (records of 8 ints)
+  hps::Profiler prof;                          // optional kernel timing
   const double* t;
 };
 
@@ -252,6 +253,7 @@ hps_status hps_leaf_operators(hps_plan pl, int32_t nbox, const double* b, void* 
                               hipStream_t st) {
   if (bad_plan(pl) || nbox < 0 || nbox > 65535 || (nbox > 0 && (!b || !A || !anorm))) return HPS_EINVAL;
   if (nbox == 0) return HPS_OK;
+  hps::ProfScope ps(&pl->prof, hps::Profiler::kOperators, 0.0, st);
   if (pl->desc.precision == HPS_FP32_IR)
     return dev(hps::launch_operators<float>(pl->g, nbox, b, static_cast<float*>(A), anorm, st));
   return dev(hps::launch_operators<double>(pl->g, nbox, b, static_cast<double*>(A), anorm, st));
@@ -263,9 +265,9 @@ hps_status hps_leaf_factor(hps_plan pl, int32_t nbox, void* A, int32_t* perm, vo
   if (nbox == 0) return HPS_OK;
   if (pl->desc.precision == HPS_FP32_IR)
     return dev(hps::getrf_run<float>(pl->g, pl->lu_ops, static_cast<float*>(A), perm, static_cast<float*>(dinv),
-                                     info, nbox, st));
+                                     info, nbox, st, &pl->prof));
   return dev(hps::getrf_run<double>(pl->g, pl->lu_ops, static_cast<double*>(A), perm, static_cast<double*>(dinv),
-                                    info, nbox, st));
+                                    info, nbox, st, &pl->prof));
 }
 
 hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t* perm, const void* dinv,
@@ -282,10 +284,11 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     double* B = static_cast<double*>(L.B);
     HPS_TRY(hps::launch_rhs<double>(g, nbox, f, B, L.maxb, st));
     HPS_TRY(hps::getrs_run<double>(g, pl->fwd_ops, pl->bwd_ops, static_cast<const double*>(LU), perm,
-                                   static_cast<const double*>(dinv), B, X, nbox, nullptr, st));
+                                   static_cast<const double*>(dinv), B, X, nbox, nullptr, st, &pl->prof));
     if (ir_iters) HPS_TRY(hps::launch_fill_int(ir_iters, 0, nbox, st));
     if (berr) {
       HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
+      hps::ProfScope ps(&pl->prof, hps::Profiler::kResidual, 0.0, st);
       HPS_TRY(hps::launch_residual(g, nbox, b, f, X, nullptr, L.maxr, L.maxx, nullptr, st));
       HPS_TRY(hps::launch_ir_check(nbox, 0, 1, INFINITY, anorm, L.maxb, L.maxr, L.maxx, L.active, nullptr, berr,
                                    st));
@@ -295,21 +298,27 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     const float* LUf = static_cast<const float*>(LU);
     const float* Dinv = static_cast<const float*>(dinv);
     HPS_TRY(hps::launch_rhs<float>(g, nbox, f, B, L.maxb, st));
-    HPS_TRY(hps::getrs_run<float>(g, pl->fwd_ops, pl->bwd_ops, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st));
+    HPS_TRY(hps::getrs_run<float>(g, pl->fwd_ops, pl->bwd_ops, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st,
+                                  &pl->prof));
     HPS_TRY(hps::launch_ir_add(g, nbox, L.Y32, X, 1, nullptr, st));
     HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
     const int kmax = pl->desc.ir_max_iter;
     const double tol = pl->desc.ir_tol;
     for (int it = 0; it <= kmax; it++) {
       const int last = it == kmax;
-      HPS_TRY(hps::launch_residual(g, nbox, b, f, X, B, L.maxr, L.maxx, L.active, st));
+      {
+        hps::ProfScope ps(&pl->prof, hps::Profiler::kResidual, 0.0, st);
+        HPS_TRY(hps::launch_residual(g, nbox, b, f, X, B, L.maxr, L.maxx, L.active, st));
+      }
       HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
                                    st));
       if (last) break;
-      HPS_TRY(hps::getrs_run<float>(g, pl->fwd_ops, pl->bwd_ops, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st));
+      HPS_TRY(hps::getrs_run<float>(g, pl->fwd_ops, pl->bwd_ops, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st,
+                                    &pl->prof));
       HPS_TRY(hps::launch_ir_add(g, nbox, L.Y32, X, 0, L.active, st));
     }
   }
+  hps::ProfScope ps(&pl->prof, hps::Profiler::kDtn, 0.0, st);
   return dev(hps::launch_dtn(g, nbox, X, g_dir, slot_map, T_vals, gload, st));
 }
 
@@ -342,6 +351,24 @@ hps_status hps_leaf_adjoint_solve(hps_plan pl, int32_t nbox, const void* LU, con
                               zt, st));
   HPS_TRY(hps::launch_compact(g, nbox, zt, z, st));
   if (y_b) HPS_TRY(hps::launch_adjoint_yb(g, nbox, zt, y_b, st));
+  return HPS_OK;
+}
+
+hps_status hps_plan_profile_enable(hps_plan pl, int32_t enable) {
+  if (bad_plan(pl)) return HPS_EINVAL;
+  pl->prof.reset();
+  pl->prof.on = enable != 0;
+  return HPS_OK;
+}
+
+hps_status hps_plan_profile_read(hps_plan pl, hps_profile* out) {
+  if (bad_plan(pl) || !out) return HPS_EINVAL;
+  pl->prof.flush();
+  for (int f = 0; f < HPS_PROFILE_FAMILIES; f++) {
+    out->launches[f] = pl->prof.launches[f];
+    out->ms[f] = pl->prof.ms[f];
+    out->flops[f] = pl->prof.flops[f];
+  }
   return HPS_OK;
 }
 

@@ -9,13 +9,82 @@
 
 namespace hps {
 
+// Optional per-family kernel timing (see hps_plan_profile_enable).
+struct Profiler {
+  enum { kLuGemm = 0, kLuPanel, kLuLeaf, kSolveGemm, kSolveLeaf, kResidual, kDtn, kOperators, kFamilies };
+  struct Rec {
+    int fam;
+    double flops;
+    hipEvent_t a, b;
+  };
+  bool on = false;
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  long long launches[kFamilies] = {};
+  double ms[kFamilies] = {};
+  double flops[kFamilies] = {};
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void reset() {
+    flush();
+    for (int f = 0; f < kFamilies; f++) launches[f] = 0, ms[f] = 0.0, flops[f] = 0.0;
+  }
+  void flush() {
+    for (auto& r : pending) {
+      float t = 0.f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        launches[r.fam] += 1;
+        ms[r.fam] += t;
+        flops[r.fam] += r.flops;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  ~Profiler() {
+    flush();
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+  Profiler* p;
+  hipStream_t st;
+  Profiler::Rec r;
+  ProfScope(Profiler* prof, int fam, double flops, hipStream_t s) : p(prof && prof->on ? prof : nullptr), st(s) {
+    if (!p) return;
+    r.fam = fam;
+    r.flops = flops;
+    r.a = p->get();
+    r.b = p->get();
+    (void)hipEventRecord(r.a, st);
+  }
+  ~ProfScope() {
+    if (!p) return;
+    (void)hipEventRecord(r.b, st);
+    p->pending.push_back(r);
+  }
+};
+
 // lu.hip: one kernel launch per schedule record (records of 8 ints, see common.h)
 template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
-                     hipStream_t st);
+                     hipStream_t st, Profiler* prof);
 template <typename T>
 hipError_t getrs_run(const Geom& g, const std::vector<int>& fwd, const std::vector<int>& bwd, const T* F,
-                     const int* perm, const T* dinv, const T* B, T* Y, int nbox, const int* active, hipStream_t st);
+                     const int* perm, const T* dinv, const T* B, T* Y, int nbox, const int* active, hipStream_t st,
+                     Profiler* prof);
 
 // leafops.hip
 hipError_t launch_nodes(const Geom& g, const double* t, const double* h, int nbox, const double* origin, double* xi,

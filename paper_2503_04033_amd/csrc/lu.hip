@@ -472,6 +472,12 @@ __global__ void gather_rows_kernel(Geom g, const int* perm_all, const T* B_all, 
 // ---------------------------------------------------------------------------
 static int grid_for(int nbox, int ntile) { return 8 * ((nbox + 7) / 8) * ntile; }
 
+// algorithmic flops of one schedule record over nbox boxes (for the profiler)
+static double gemm_flops(const int* op, int nbox) {
+  return 2.0 * (op[2] - op[1]) * (double)(op[4] - op[3]) * (op[6] - op[5]) * nbox;
+}
+static double leaf_flops(const int* op, int nbox) { return 2.0 * op[2] * (double)op[2] * (op[4] - op[3]) * nbox; }
+
 template <typename T, bool PERM>
 static hipError_t launch_gemm(const Geom& g, const T* F, const int* perm, T* X, int ld, size_t xstride, const int* op,
                               int nbox, const int* active, hipStream_t st) {
@@ -511,30 +517,37 @@ static hipError_t launch_panel(const Geom& g, T* A, int* perm, T* dinv, int* inf
 
 template <typename T, int ROWS, int SP>
 static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
-                         hipStream_t st) {
+                         hipStream_t st, Profiler* prof) {
   const int N = g.n_pad;
   hipLaunchKernelGGL(lu_init_kernel, dim3((N + 255) / 256, nbox), dim3(256), 0, st, N, perm, info, nbox);
   hipError_t e = hipGetLastError();
   for (size_t q = 0; q + 8 <= ops.size() && e == hipSuccess; q += 8) {
     const int* op = ops.data() + q;
-    if (op[0] == kOpPanel) e = launch_panel<T, ROWS, SP>(g, A, perm, dinv, info, nbox, op[1], op[2], st);
-    else if (op[0] == kOpLeaf) e = launch_leaf<T, false, true>(g, perm, dinv, A, N, (size_t)N * N, op, nbox, nullptr, st);
-    else e = launch_gemm<T, true>(g, A, perm, A, N, (size_t)N * N, op, nbox, nullptr, st);
+    if (op[0] == kOpPanel) {
+      ProfScope ps(prof, Profiler::kLuPanel, 0.0, st);
+      e = launch_panel<T, ROWS, SP>(g, A, perm, dinv, info, nbox, op[1], op[2], st);
+    } else if (op[0] == kOpLeaf) {
+      ProfScope ps(prof, Profiler::kLuLeaf, leaf_flops(op, nbox), st);
+      e = launch_leaf<T, false, true>(g, perm, dinv, A, N, (size_t)N * N, op, nbox, nullptr, st);
+    } else {
+      ProfScope ps(prof, Profiler::kLuGemm, gemm_flops(op, nbox), st);
+      e = launch_gemm<T, true>(g, A, perm, A, N, (size_t)N * N, op, nbox, nullptr, st);
+    }
   }
   return e;
 }
 
 template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
-                     hipStream_t st) {
+                     hipStream_t st, Profiler* prof) {
   const int rows = (g.n_pad + kLuThreads - 1) / kLuThreads;
   constexpr int SP = sizeof(T) == 4 ? 8 : 4;
-  if (rows <= 1) return run_lu<T, 1, SP>(g, ops, A, perm, dinv, info, nbox, st);
-  if (rows <= 2) return run_lu<T, 2, SP>(g, ops, A, perm, dinv, info, nbox, st);
-  if (rows <= 4) return run_lu<T, 4, SP>(g, ops, A, perm, dinv, info, nbox, st);
-  if (rows <= 6) return run_lu<T, 6, SP>(g, ops, A, perm, dinv, info, nbox, st);
-  if (rows <= 8) return run_lu<T, 8, SP>(g, ops, A, perm, dinv, info, nbox, st);
-  if (rows <= 12) return run_lu<T, 12, SP>(g, ops, A, perm, dinv, info, nbox, st);
+  if (rows <= 1) return run_lu<T, 1, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 2) return run_lu<T, 2, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 4) return run_lu<T, 4, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 6) return run_lu<T, 6, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 8) return run_lu<T, 8, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 12) return run_lu<T, 12, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
   return hipErrorInvalidValue;
 }
 
@@ -542,31 +555,44 @@ hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm
 // ops with U, in place in Y (B and Y must not alias).
 template <typename T>
 hipError_t getrs_run(const Geom& g, const std::vector<int>& fwd, const std::vector<int>& bwd, const T* F,
-                     const int* perm, const T* dinv, const T* B, T* Y, int nbox, const int* active, hipStream_t st) {
+                     const int* perm, const T* dinv, const T* B, T* Y, int nbox, const int* active, hipStream_t st,
+                     Profiler* prof) {
   const size_t xs = (size_t)g.n_pad * g.ldx;
   hipLaunchKernelGGL((gather_rows_kernel<T>), dim3(g.n_pad < 512 ? g.n_pad : 512, nbox), dim3(256), 0, st, g, perm, B,
                      Y, nbox, active);
   hipError_t e = hipGetLastError();
   for (size_t q = 0; q + 8 <= fwd.size() && e == hipSuccess; q += 8) {
     const int* op = fwd.data() + q;
-    if (op[0] == kOpLeaf) e = launch_leaf<T, false, false>(g, perm, dinv, Y, g.ldx, xs, op, nbox, active, st);
-    else e = launch_gemm<T, false>(g, F, perm, Y, g.ldx, xs, op, nbox, active, st);
+    if (op[0] == kOpLeaf) {
+      ProfScope ps(prof, Profiler::kSolveLeaf, leaf_flops(op, nbox), st);
+      e = launch_leaf<T, false, false>(g, perm, dinv, Y, g.ldx, xs, op, nbox, active, st);
+    } else {
+      ProfScope ps(prof, Profiler::kSolveGemm, gemm_flops(op, nbox), st);
+      e = launch_gemm<T, false>(g, F, perm, Y, g.ldx, xs, op, nbox, active, st);
+    }
   }
   for (size_t q = 0; q + 8 <= bwd.size() && e == hipSuccess; q += 8) {
     const int* op = bwd.data() + q;
-    if (op[0] == kOpLeaf) e = launch_leaf<T, true, false>(g, perm, dinv, Y, g.ldx, xs, op, nbox, active, st);
-    else e = launch_gemm<T, false>(g, F, perm, Y, g.ldx, xs, op, nbox, active, st);
+    if (op[0] == kOpLeaf) {
+      ProfScope ps(prof, Profiler::kSolveLeaf, leaf_flops(op, nbox), st);
+      e = launch_leaf<T, true, false>(g, perm, dinv, Y, g.ldx, xs, op, nbox, active, st);
+    } else {
+      ProfScope ps(prof, Profiler::kSolveGemm, gemm_flops(op, nbox), st);
+      e = launch_gemm<T, false>(g, F, perm, Y, g.ldx, xs, op, nbox, active, st);
+    }
   }
   return e;
 }
 
-template hipError_t getrf_run<float>(const Geom&, const std::vector<int>&, float*, int*, float*, int*, int, hipStream_t);
+template hipError_t getrf_run<float>(const Geom&, const std::vector<int>&, float*, int*, float*, int*, int, hipStream_t,
+                                     Profiler*);
 template hipError_t getrf_run<double>(const Geom&, const std::vector<int>&, double*, int*, double*, int*, int,
-                                      hipStream_t);
+                                      hipStream_t, Profiler*);
 template hipError_t getrs_run<float>(const Geom&, const std::vector<int>&, const std::vector<int>&, const float*,
-                                     const int*, const float*, const float*, float*, int, const int*, hipStream_t);
+                                     const int*, const float*, const float*, float*, int, const int*, hipStream_t,
+                                     Profiler*);
 template hipError_t getrs_run<double>(const Geom&, const std::vector<int>&, const std::vector<int>&, const double*,
                                       const int*, const double*, const double*, double*, int, const int*,
-                                      hipStream_t);
+                                      hipStream_t, Profiler*);
 
 }  // namespace hps

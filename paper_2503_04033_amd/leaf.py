@@ -84,6 +84,16 @@ class LeafPlan:
             self.lib.hps_plan_destroy(h)
             self.handle = None
 
+    # ---- kernel timing ---------------------------------------------------------
+    def profile_enable(self, on: bool = True) -> None:
+        check(self.lib.hps_plan_profile_enable(self.handle, 1 if on else 0), "hps_plan_profile_enable")
+
+    def profile_read(self) -> dict:
+        pr = _lib.Profile()
+        check(self.lib.hps_plan_profile_read(self.handle, C.byref(pr)), "hps_plan_profile_read")
+        return {name: {"launches": int(pr.launches[k]), "ms": float(pr.ms[k]), "flops": float(pr.flops[k])}
+                for k, name in enumerate(_lib.PROFILE_FAMILIES)}
+
     # ---- allocation helpers -------------------------------------------------
     def alloc(self, nbox: int, device="cuda") -> dict:
         """Caller-owned device buffers for `nbox` boxes."""
