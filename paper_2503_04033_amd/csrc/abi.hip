@@ -14,6 +14,7 @@ struct hps_plan_s {
   hps::Geom g;
   int device;
   double* tables;  // device: t[p], D[p*p], D2[p*p]
+  int* coords;     // device: interior node coordinates (packed)
   std::vector<int> lu_ops, fwd_ops, bwd_ops;  // schedules (records of 8 ints)
   hps::Profiler prof;                          // optional kernel timing
   const double* t;
@@ -203,10 +204,26 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
   pl->t = pl->tables;
   g.D = pl->tables + g.p;
   g.D2 = pl->tables + g.p + (size_t)g.p * g.p;
+  std::vector<int> coords(g.n);
+  for (int node = 0; node < g.n; node++)
+    coords[node] = (node % g.m) | (((node / g.m) % g.m) << 8) | ((node / (g.m * g.m)) << 16);
+  if (hipMalloc(&pl->coords, coords.size() * sizeof(int)) != hipSuccess) {
+    (void)hipFree(pl->tables);
+    delete pl;
+    return HPS_ENOMEM;
+  }
+  if (hipMemcpy(pl->coords, coords.data(), coords.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(pl->coords);
+    (void)hipFree(pl->tables);
+    delete pl;
+    return HPS_EDEVICE;
+  }
+  g.coords = pl->coords;
   sched_lu(pl->lu_ops, 0, g.n_pad, g.n_pad);
   sched_trsm(pl->fwd_ops, 0, g.n_pad, 0, g.ldx);
   sched_trsm_up(pl->bwd_ops, 0, g.n_pad, 0, g.ldx);
   if (hps::residual_prepare(g) != hipSuccess) {
+    (void)hipFree(pl->coords);
     (void)hipFree(pl->tables);
     delete pl;
     return HPS_EDEVICE;
@@ -217,6 +234,7 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
 
 hps_status hps_plan_destroy(hps_plan pl) {
   if (!pl) return HPS_EINVAL;
+  (void)hipFree(pl->coords);
   (void)hipFree(pl->tables);
   delete pl;
   return HPS_OK;

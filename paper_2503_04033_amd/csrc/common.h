@@ -72,6 +72,7 @@ struct Geom {
   double kappa2;   // kappa^2
   const double* D;     // [p][p] Gauss-Lobatto differentiation matrix on [-1,1]
   const double* D2;    // [p][p] D*D
+  const int* coords;   // [n] interior node -> ii | jj << 8 | kk << 16
 };
 
 // Schedule record kinds for the recursive LU and solves (record = {kind, a1..a7}):

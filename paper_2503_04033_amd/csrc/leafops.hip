@@ -250,12 +250,13 @@ template <int CW>
 __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox, const double* b, const double* f,
                                                                const double* X_all, float* R32_all, double* maxr,
                                                                double* maxx, const int* active) {
-  extern __shared__ double xs[];  // [n][CW] then D2 interior block [m][m]
+  extern __shared__ double xs[];  // [n][CW] then D2 interior block [m][m] and its two boundary columns
   int box, chunk;
   if (!map_box_chunk(nbox, g.ldx / CW, box, chunk)) return;
   if (active && active[box] == 0) return;
   const int m = g.m, mm = m * m, n = g.n, ldx = g.ldx, p = g.p;
-  double* d2s = xs + (size_t)n * CW;
+  double* d2s = xs + (size_t)n * CW;   // D2[i+1][j+1]
+  double* d2e = d2s + mm;              // D2[i+1][0] and D2[i+1][p-1]
   const int c0 = chunk * CW;
   const double* X = X_all + (size_t)box * g.n_pad * ldx;
   for (int e = threadIdx.x; e < n * CW; e += kResThreads) {
@@ -263,28 +264,51 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox,
     xs[e] = X[(size_t)node * ldx + c0 + c];
   }
   for (int e = threadIdx.x; e < mm; e += kResThreads) d2s[e] = g.D2[(e / m + 1) * p + e % m + 1];
+  for (int e = threadIdx.x; e < 2 * m; e += kResThreads) d2e[e] = g.D2[(e % m + 1) * p + (e < m ? 0 : p - 1)];
   __syncthreads();
+  // this thread's column and its A_ib face node (if any)
+  const int c = threadIdx.x % CW;
+  const int col = c0 + c;
+  int axis = -1, qq = 0, side = 0;
+  if (col < g.nb) {
+    const int a = col / mm;
+    qq = col - a * mm;
+    axis = a >> 1;
+    side = a & 1;
+  }
+  const bool fcol = (col == g.nb) && f;
+  const double s2a = axis >= 0 ? g.s2[axis] : 0.0;
   double mr = 0.0, mxv = 0.0;
   const double* bb = b + (size_t)box * n;
-  for (int e = threadIdx.x; e < n * CW; e += kResThreads) {
-    const int node = e / CW, c = e - node * CW;
-    const int ii = node % m, jj = (node / m) % m, kk = node / mm;
-    const double* xl = xs + (size_t)(node - ii) * CW + c;           // x-line: stride CW
-    const double* yl = xs + (size_t)(node - m * jj) * CW + c;       // y-line: stride m*CW
-    const double* zl = xs + (size_t)(node - mm * kk) * CW + c;      // z-line: stride mm*CW
+  float* R32 = R32_all ? R32_all + (size_t)box * g.n_pad * ldx : nullptr;
+  for (int node = threadIdx.x / CW; node < n; node += kResThreads / CW) {
+    const int cd = g.coords[node];
+    const int ii = cd & 255, jj = (cd >> 8) & 255, kk = cd >> 16;
+    const double* xl = xs + (size_t)(node - ii) * CW + c;       // x-line: stride CW
+    const double* yl = xs + (size_t)(node - m * jj) * CW + c;   // y-line: stride m*CW
+    const double* zl = xs + (size_t)(node - mm * kk) * CW + c;  // z-line: stride mm*CW
+    const double* dx = d2s + ii * m;
+    const double* dy = d2s + jj * m;
+    const double* dz = d2s + kk * m;
     double ax = 0.0, ay = 0.0, az = 0.0;
     for (int q = 0; q < m; q++) {
-      ax += d2s[ii * m + q] * xl[q * CW];
-      ay += d2s[jj * m + q] * yl[q * m * CW];
-      az += d2s[kk * m + q] * zl[q * mm * CW];
+      ax += dx[q] * xl[q * CW];
+      ay += dy[q] * yl[q * m * CW];
+      az += dz[q] * zl[q * mm * CW];
     }
-    const int col = c0 + c;
-    const double xv = xs[e];
+    const double xv = xs[(size_t)node * CW + c];
     double bv = 0.0;
-    if (col < g.nb) bv = aib_entry(g, ii, jj, kk, col);
-    else if (col == g.nb && f) bv = f[(size_t)box * n + node];
+    if (axis == 0) {
+      if (jj + m * kk == qq) bv = -s2a * d2e[side * m + ii];
+    } else if (axis == 1) {
+      if (ii + m * kk == qq) bv = -s2a * d2e[side * m + jj];
+    } else if (axis == 2) {
+      if (ii + m * jj == qq) bv = -s2a * d2e[side * m + kk];
+    } else if (fcol) {
+      bv = f[(size_t)box * n + node];
+    }
     const double r = bv + g.s2[0] * ax + g.s2[1] * ay + g.s2[2] * az + g.kappa2 * bb[node] * xv;
-    if (R32_all) R32_all[(size_t)box * g.n_pad * ldx + (size_t)node * ldx + col] = (float)r;
+    if (R32) R32[(size_t)node * ldx + col] = (float)r;
     mr = fmax(mr, fabs(r));
     mxv = fmax(mxv, fabs(xv));
   }
@@ -298,8 +322,8 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox,
 
 // Kernel attributes are set once per plan (outside any stream capture).
 hipError_t residual_prepare(const Geom& g) {
-  const size_t shm4 = ((size_t)g.n * 4 + g.m * g.m) * sizeof(double);
-  const size_t shm2 = ((size_t)g.n * 2 + g.m * g.m) * sizeof(double);
+  const size_t shm4 = ((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double);
+  const size_t shm2 = ((size_t)g.n * 2 + g.m * g.m + 2 * g.m) * sizeof(double);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&residual_kernel<4>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)(shm4 < 160 * 1024 ? shm4 : 160 * 1024));
   if (e == hipSuccess)
@@ -314,12 +338,12 @@ hipError_t launch_residual(const Geom& g, int nbox, const double* b, const doubl
   if (e == hipSuccess) e = launch_fill_zero(maxx, sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
   const int grid_boxes = 8 * ((nbox + 7) / 8);
-  if ((size_t)g.n * 4 * sizeof(double) + g.m * g.m * sizeof(double) <= 96 * 1024) {
-    const size_t shm = ((size_t)g.n * 4 + g.m * g.m) * sizeof(double);
+  if (((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double) <= 96 * 1024) {
+    const size_t shm = ((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double);
     hipLaunchKernelGGL(residual_kernel<4>, dim3(grid_boxes * (g.ldx / 4)), dim3(kResThreads), shm, st, g, nbox, b, f,
                        X, R32, maxr, maxx, active);
   } else {
-    const size_t shm = ((size_t)g.n * 2 + g.m * g.m) * sizeof(double);
+    const size_t shm = ((size_t)g.n * 2 + g.m * g.m + 2 * g.m) * sizeof(double);
     hipLaunchKernelGGL(residual_kernel<2>, dim3(grid_boxes * (g.ldx / 2)), dim3(kResThreads), shm, st, g, nbox, b, f,
                        X, R32, maxr, maxx, active);
   }

@@ -354,8 +354,11 @@ __global__ __launch_bounds__(kLuThreads, 1) void lu_panel_kernel(Geom g, T* A_al
 }
 
 template <typename T> struct GemmCfg;
-template <> struct GemmCfg<float> { typedef TileGemm<float, 4, 4, 2, 2, 32> G; };
-template <> struct GemmCfg<double> { typedef TileGemm<double, 4, 2, 2, 2, 16> G; };
+// 64 x 64 workgroup tiles, 4 waves of 32 x 32: the best or near-best shape for
+// every update size in the recursion on gfx950 (more resident workgroups per CU
+// outweigh the smaller operand reuse).
+template <> struct GemmCfg<float> { typedef TileGemm<float, 2, 2, 2, 2, 32> G; };
+template <> struct GemmCfg<double> { typedef TileGemm<double, 2, 2, 2, 2, 16> G; };
 
 // C[row(pos)][n] -= sum_k F[perm[pos]][k] * B[row(k)][n] for pos in [m0,m1),
 // n in [n0,n1), k in [k0,k1).  F is the factor (ld n_pad, rows via perm); B and
@@ -363,7 +366,7 @@ template <> struct GemmCfg<double> { typedef TileGemm<double, 4, 2, 2, 2, 16> G;
 // side block (rows direct, ld ldx).  Row and k ranges never overlap within one
 // op, so reads and writes are disjoint.
 template <typename T, bool PERM>
-__global__ __launch_bounds__(256, 2) void gemm_op_kernel(Geom g, const T* F_all, const int* perm_all, T* X_all,
+__global__ __launch_bounds__(256, 4) void gemm_op_kernel(Geom g, const T* F_all, const int* perm_all, T* X_all,
                                                          int ld, size_t xstride, int m0, int m1, int n0, int n1,
                                                          int k0, int k1, int nbox, int ntm, int ntn,
                                                          const int* active) {
