@@ -41,7 +41,7 @@ def flops_per_box(n_i: int, n_b: int, passes: int) -> dict:
 class Runner:
     """Buffers and the per-chunk ABI call sequence for one precision."""
 
-    def __init__(self, prob, precision, nbox, chunk, ir_max_iter=3, ir_tol=1e-11):
+    def __init__(self, prob, precision, nbox, chunk, ir_max_iter=3, ir_tol=1e-11, streams=1):
         import torch
         from paper_2503_04033_amd import interface as itf
         from paper_2503_04033_amd.leaf import LeafPlan
@@ -60,34 +60,57 @@ class Runner:
         self.infov = torch.zeros(nbox, dtype=torch.int32, device=dev)
         self.iters = torch.zeros(nbox, dtype=torch.int32, device=dev)
         self.berr = torch.zeros(nbox, dtype=torch.float64, device=dev)
-        self.bufs = self.plan.alloc(self.chunk, dev)
+        # one buffer set per stream; chunk j runs on stream j % streams so that the pivoted
+        # panels of one chunk overlap the GEMMs of the next
+        self.streams = [torch.cuda.Stream() for _ in range(streams)] if streams > 1 else None
+        self.bufsets = [self.plan.alloc(self.chunk, dev) for _ in range(max(streams, 1))]
         self.slot_map = torch.tensor(self.layout.slot_map[:nbox], device=dev).contiguous()
         self.pairs = torch.tensor(self.layout.reduce_pairs, device=dev)
         self.ev = {k: [] for k in ("operators", "factor", "dtn")}
 
     def step(self, b, g_dir, record=False):
         torch = self.torch
-        plan, B, C = self.plan, self.bufs, self.chunk
-        for c0 in range(0, self.nbox, C):
-            nb = min(C, self.nbox - c0)
-            sl = slice(c0, c0 + nb)
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
-            if record:
-                e[0].record()
-            plan.hps_leaf_operators(nb, b[sl], B["A"], B["anorm"])
-            if record:
-                e[1].record()
-            plan.hps_leaf_factor(nb, B["A"], B["perm"], B["dinv"], self.infov[sl])
-            if record:
-                e[2].record()
-            plan.hps_leaf_dtn(nb, B["A"], B["perm"], B["dinv"], b[sl], B["anorm"], None, g_dir[sl],
-                              self.slot_map[sl], self.T_vals, self.g_loads[sl], B["X"], self.iters[sl],
-                              self.berr[sl], B["ws"])
-            if record:
-                e[3].record()
-                self.ev["operators"].append((e[0], e[1], nb))
-                self.ev["factor"].append((e[1], e[2], nb))
-                self.ev["dtn"].append((e[2], e[3], nb))
+        plan, C = self.plan, self.chunk
+        main = torch.cuda.current_stream()
+        if self.streams:
+            for s in self.streams:
+                s.wait_stream(main)
+        for j, c0 in enumerate(range(0, self.nbox, C)):
+            if self.streams:
+                with torch.cuda.stream(self.streams[j % len(self.streams)]):
+                    self._chunk(j, c0, b, g_dir, record)
+            else:
+                self._chunk(j, c0, b, g_dir, record)
+        if self.streams:
+            for s in self.streams:
+                main.wait_stream(s)
+        self._reduce()
+
+    def _chunk(self, j, c0, b, g_dir, record):
+        torch = self.torch
+        plan, C = self.plan, self.chunk
+        B = self.bufsets[j % len(self.bufsets)]
+        nb = min(C, self.nbox - c0)
+        sl = slice(c0, c0 + nb)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+        if record:
+            e[0].record()
+        plan.hps_leaf_operators(nb, b[sl], B["A"], B["anorm"])
+        if record:
+            e[1].record()
+        plan.hps_leaf_factor(nb, B["A"], B["perm"], B["dinv"], self.infov[sl])
+        if record:
+            e[2].record()
+        plan.hps_leaf_dtn(nb, B["A"], B["perm"], B["dinv"], b[sl], B["anorm"], None, g_dir[sl],
+                          self.slot_map[sl], self.T_vals, self.g_loads[sl], B["X"], self.iters[sl],
+                          self.berr[sl], B["ws"])
+        if record:
+            e[3].record()
+            self.ev["operators"].append((e[0], e[1], nb))
+            self.ev["factor"].append((e[1], e[2], nb))
+            self.ev["dtn"].append((e[2], e[3], nb))
+
+    def _reduce(self):
         if self.pairs.shape[0] and self.nbox == self.prob.nbox:
             from paper_2503_04033_amd.leaf import hps_interface_reduce
             mm = self.info.m ** 2
@@ -129,6 +152,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nbox", type=int, default=0, help="time only the first N boxes (profiling)")
     ap.add_argument("--chunk", type=int, default=1024)
+    ap.add_argument("--streams", type=int, default=1, help="chunks interleaved over this many HIP streams")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=24)
@@ -147,7 +171,7 @@ def main():
     dev = torch.device("cuda")
     log(f"workload {prob.name}: nbox={nbox} p={prob.p} kappa={prob.kappa}")
     # ---- inputs resident in HBM ----
-    fp32 = Runner(prob, "fp32_ir", nbox, a.chunk, a.ir_max_iter, a.ir_tol)
+    fp32 = Runner(prob, "fp32_ir", nbox, a.chunk, a.ir_max_iter, a.ir_tol, a.streams)
     from paper_2503_04033_amd.solver import TwoLevelSolver  # noqa: F401  (import check of the package)
     i = fp32.info
     xi = torch.empty(nbox * i.n_i * 3, dtype=torch.float64, device=dev)
@@ -204,7 +228,7 @@ def main():
         "vs_baseline": None, "dtype": "f32 MFMA LU/solves + f64 refinement and DtN", "data": "synthetic",
         "config": {"workload": "16x16x16 leaf boxes, p=16 (2744 interior nodes/box), kappa=40, "
                                "b=1+0.3*sum of 8 seeded Gaussian bumps (width 0.1), plane-wave g, f=0",
-                   "nbox": nbox, "p": prob.p, "n_i": i.n_i, "n_b": i.n_b, "chunk": fp32.chunk,
+                   "nbox": nbox, "p": prob.p, "n_i": i.n_i, "n_b": i.n_b, "chunk": fp32.chunk, "streams": a.streams,
                    "ir_tol": a.ir_tol, "ir_max_iter": a.ir_max_iter},
         "mfma_frac_lu_solve": round(tot_flops / (ms / 1e3) / PEAK_FP32_MFMA, 4),
         "tflops_lu_solve": round(tot_flops / (ms / 1e3) / 1e12, 2),
@@ -227,7 +251,7 @@ def main():
         g32 = fp32.g_loads.clone()
         del fp32
         torch.cuda.empty_cache()
-        fp64 = Runner(prob, "fp64", nbox, a.chunk)
+        fp64 = Runner(prob, "fp64", nbox, a.chunk, streams=a.streams)
         fp64.step(b, g_dir)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

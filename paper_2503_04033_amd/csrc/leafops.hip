@@ -320,6 +320,245 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox,
   }
 }
 
+// Residual for boxes with m <= 16 interior nodes per direction.  One workgroup of 1024
+// threads per (box, CB = 16 / NW columns); NW waves share a column, each owning a run of
+// H = ceil(m / NW) output slabs.  For a fixed column the z-slab kk of X is an m x m
+// matrix S[ii][jj]; its x- and y-derivative terms are D2i S and S D2i^T, both written as
+// 16x16x4 FP64 MFMA chains into one 16x16 accumulator (rows ii, columns jj, zero
+// padded), by the wave that owns slab kk.  The z-derivative couples slabs: as each slab
+// q arrives every wave adds D2i[kk][q] X[.., q] to its accumulators of its slabs kk
+// (VALU).  X, b and f are read once: branch-free 8-byte loads run PD slabs ahead in
+// registers and pass through two LDS slab buffers.  R32 is written through LDS in
+// row segments of CB floats.
+#ifndef HPS_RES_NW
+#define HPS_RES_NW 2  // waves per column (2: 8-column blocks, 4: 4-column blocks)
+#endif
+constexpr int kRmThreads = 1024;
+constexpr int kRmLd = 17;                // row stride of a 16x16 slab tile in LDS
+constexpr int kRmTile = 16 * kRmLd + 4;  // doubles per tile plane
+
+// A value known to be equal in all lanes, moved to scalar registers.
+__device__ inline double wave_uniform(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)bits);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(bits >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int M, int NW>
+__global__ __launch_bounds__(kRmThreads) void residual_mfma_kernel(Geom g, int nbox, int ncb, const double* b,
+                                                                   const double* f, const double* X_all,
+                                                                   float* R32_all, double* maxr, double* maxx,
+                                                                   const int* active) {
+  constexpr int m = M, mm = M * M;
+  constexpr int CB = 16 / NW;                 // columns per workgroup
+  constexpr int H = (M + NW - 1) / NW;        // output slabs per wave
+  constexpr int PLANES = CB + 2;              // CB columns of X, then b and f
+  constexpr int BUF = PLANES * kRmTile;       // one slab buffer
+  constexpr int DISCARD = 2 * BUF;            // write slot of idle staging tasks
+  constexpr int NTK = ((CB + 2) * mm + kRmThreads - 1) / kRmThreads;  // staging tasks per thread
+  constexpr int PD = (NTK >= 3 || H >= 7) ? 2 : 3;  // slabs in flight
+  static_assert(16 % NW == 0 && 4 * mm * CB <= 2 * BUF * 2, "output staging must fit the slab buffers");
+  __shared__ double sm[2 * BUF + 2];
+  __shared__ double tz[16 * 16];     // s2z * D2i[kk][q] at [q][kk]
+  __shared__ double te[2 * 16];      // D2[i+1][0] and D2[i+1][p-1]
+  __shared__ double td[2][16 * 16];  // s2x D2i and s2y D2i at [k][l], zero padded (MFMA operands)
+  int box, cb;
+  if (!map_box_chunk(nbox, ncb, box, cb)) return;
+  if (active && active[box] == 0) return;
+  const int p = g.p, ldx = g.ldx;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wc = w % CB, part = w / CB;  // column within the block, run of slabs
+  const int c0 = cb * CB, col = c0 + wc;
+  const int lr = lane >> 4, lc = lane & 15;
+  const double* X = X_all + (size_t)box * g.n_pad * ldx;
+  const double* bb = b + (size_t)box * g.n;
+  const double* fb = f ? f + (size_t)box * g.n : X;
+  for (int e = threadIdx.x; e < 2 * BUF + 2; e += kRmThreads) sm[e] = 0.0;
+  for (int e = threadIdx.x; e < mm; e += kRmThreads) tz[(e % m) * 16 + e / m] = g.s2[2] * g.D2[(e / m + 1) * p + e % m + 1];
+  for (int e = threadIdx.x; e < 2 * m; e += kRmThreads) te[e] = g.D2[(e % m + 1) * p + (e < m ? 0 : p - 1)];
+  for (int e = threadIdx.x; e < 256; e += kRmThreads) {
+    const int l = e & 15, k = e >> 4;
+    const double d = (l < m && k < m) ? g.D2[(l + 1) * p + k + 1] : 0.0;
+    td[0][e] = g.s2[0] * d;
+    td[1][e] = g.s2[1] * d;
+  }
+  // staging task t of a slab: t < CB m^2 is X[row t / CB][c0 + t % CB], then b, then f,
+  // stored at tile [ii][jj] of their plane; other tasks reread one element and discard it
+  const double* fp[NTK];
+  int inc[NTK], loff[NTK];
+#pragma unroll
+  for (int s = 0; s < NTK; s++) {
+    const int t = threadIdx.x + s * kRmThreads;
+    fp[s] = X;
+    inc[s] = 0;
+    loff[s] = DISCARD;
+    if (t < CB * mm) {
+      const int r = t / CB, c = t % CB;
+      fp[s] = X + (size_t)r * ldx + c0 + c;
+      inc[s] = mm * ldx;
+      loff[s] = c * kRmTile + (r % m) * kRmLd + r / m;
+    } else if (t < (CB + 1) * mm) {
+      const int r = t - CB * mm;
+      fp[s] = bb + r;
+      inc[s] = mm;
+      loff[s] = CB * kRmTile + (r % m) * kRmLd + r / m;
+    } else if (t < (CB + 2) * mm && f) {
+      const int r = t - (CB + 1) * mm;
+      fp[s] = fb + r;
+      inc[s] = mm;
+      loff[s] = (CB + 1) * kRmTile + (r % m) * kRmLd + r / m;
+    }
+  }
+  // This wave's column of [A_ib | f].  A_ib column col is nonzero on the normal line of
+  // face node (la, lb); bit i of emask marks this lane's node (lr + 4i, lc) on it, whose
+  // entry is -s2[axis] D2[t+1][edge] with t the node's coordinate along the axis.
+  int axis = -1, side = 0, la = 0, lb = 0;
+  if (col < g.nb) {
+    const int a = col / mm, qq = col - a * mm;
+    axis = a >> 1;
+    side = a & 1;
+    la = qq % m;
+    lb = qq / m;
+  }
+  const bool fcol = (col == g.nb) && f;
+  int emask = 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int ii = lr + 4 * i;
+    bool on = false;
+    if (ii < m && lc < m) {
+      if (axis == 0) on = lc == la;
+      else if (axis == 1) on = ii == la;
+      else if (axis == 2) on = ii == la && lc == lb;
+    }
+    emask |= on ? (1 << i) : 0;
+  }
+  const double s2a = axis >= 0 ? -g.s2[axis] : 0.0;
+  const double* tes = te + side * m;
+  double pf[PD][NTK];
+  auto fetch = [&](int slot) {
+#pragma unroll
+    for (int s = 0; s < NTK; s++) {
+      pf[slot][s] = *fp[s];
+      fp[s] += inc[s];
+    }
+  };
+  auto stash = [&](int buf, int slot) {
+#pragma unroll
+    for (int s = 0; s < NTK; s++) sm[loff[s] == DISCARD ? DISCARD : buf * BUF + loff[s]] = pf[slot][s];
+  };
+#pragma unroll
+  for (int q = 0; q < PD && q < m; q++) fetch(q);
+  __syncthreads();  // zero fill and tables done
+  stash(0, 0);
+  d4 acc[H];
+#pragma unroll
+  for (int k = 0; k < H; k++) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+  double mxv = 0.0;
+  const double k2 = g.kappa2;
+#pragma unroll
+  for (int q = 0; q < m; q++) {
+    __builtin_amdgcn_sched_barrier(0);  // keep each slab's work (and its registers) in place
+    __syncthreads();                    // slab q visible; the other buffer is free
+    if (q + PD < m) fetch(q % PD);
+    const double* S = sm + (q & 1) * BUF;
+    const double* Sc = S + wc * kRmTile;
+    double bx[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; kb++) bx[kb] = Sc[(lr + 4 * kb) * kRmLd + lc];
+#pragma unroll
+    for (int pt = 0; pt < NW; pt++) {
+      if (part != pt) continue;  // wave-uniform: one static copy per run of slabs
+      if (q >= pt * H && q < (pt + 1) * H) {
+        // x- and y-derivative terms of slab q, the diagonal term and the [A_ib | f] entries
+        const double* Sb = S + CB * kRmTile;
+        const double* Sf = Sb + kRmTile;
+        double ay[4], bv[4], fv[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++) {
+          ay[kb] = Sc[lc * kRmLd + lr + 4 * kb];
+          bv[kb] = Sb[(lr + 4 * kb) * kRmLd + lc];
+          fv[kb] = fcol ? Sf[(lr + 4 * kb) * kRmLd + lc] : 0.0;
+        }
+        d4 a = acc[q - pt * H];
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++)
+          a = __builtin_amdgcn_mfma_f64_16x16x4f64(td[0][(lr + 4 * kb) * 16 + lc], bx[kb], a, 0, 0, 0);
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++)
+          a = __builtin_amdgcn_mfma_f64_16x16x4f64(ay[kb], td[1][(lr + 4 * kb) * 16 + lc], a, 0, 0, 0);
+        const bool eslab = axis == 2 || q == lb;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const double ev = tes[axis == 0 ? lr + 4 * i : (axis == 1 ? lc : q)];
+          double r = k2 * bv[i] * bx[i] + fv[i];
+          r += (eslab && ((emask >> i) & 1)) ? s2a * ev : 0.0;
+          a[i] += r;
+        }
+        acc[q - pt * H] = a;
+#pragma unroll
+        for (int i = 0; i < 4; i++) mxv = fmax(mxv, fabs(bx[i]));
+      }
+      // z-derivative: slab q feeds this wave's slabs kk
+#pragma unroll
+      for (int k = 0; k < H; k++) {
+        const int kk = pt * H + k;
+        if (kk < m) {
+          const double cz = wave_uniform(tz[q * 16 + kk]);
+#pragma unroll
+          for (int i = 0; i < 4; i++) acc[k][i] += cz * bx[i];
+        }
+      }
+    }
+    if (q + 1 < m) stash((q + 1) & 1, (q + 1) % PD);
+  }
+  // max |R| (entries outside the m x m tile are exactly zero), then R32 through LDS,
+  // four slabs at a time
+  double mr = 0.0;
+#pragma unroll
+  for (int k = 0; k < H; k++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) mr = fmax(mr, fabs(acc[k][i]));
+  if (R32_all) {
+    float* O = reinterpret_cast<float*>(sm);  // [4 slabs][m^2 rows][CB]
+    float* R32 = R32_all + (size_t)box * g.n_pad * ldx;
+#pragma unroll
+    for (int k0 = 0; k0 < m; k0 += 4) {
+      __syncthreads();  // LDS free (slab reads or the previous group's stores done)
+#pragma unroll
+      for (int pt = 0; pt < NW; pt++) {
+        if (part != pt) continue;
+#pragma unroll
+        for (int k = 0; k < H; k++) {
+          const int kk = pt * H + k;
+          if (kk >= k0 && kk < k0 + 4 && kk < m) {
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+              const int ii = lr + 4 * i;
+              if (ii < m && lc < m) O[((kk - k0) * mm + ii + m * lc) * CB + wc] = (float)acc[k][i];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      constexpr int V = CB / 4;  // float4 per row segment
+      const int nk = (m - k0) < 4 ? (m - k0) : 4;
+      for (int t = threadIdx.x; t < nk * mm * V; t += kRmThreads) {
+        const int row = t / V, h = t % V;  // row = (slab - k0) * m^2 + r
+        const f4 v = *reinterpret_cast<const f4*>(O + row * CB + 4 * h);
+        *reinterpret_cast<f4*>(R32 + (size_t)(k0 * mm + row) * ldx + c0 + 4 * h) = v;
+      }
+    }
+  }
+  mr = wave_max(mr);
+  mxv = wave_max(mxv);
+  if (lane == 0) {
+    atomic_max_nonneg(maxr + box, mr);
+    atomic_max_nonneg(maxx + box, mxv);
+  }
+}
+
 // Kernel attributes are set once per plan (outside any stream capture).
 hipError_t residual_prepare(const Geom& g) {
   const size_t shm4 = ((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double);
@@ -338,7 +577,25 @@ hipError_t launch_residual(const Geom& g, int nbox, const double* b, const doubl
   if (e == hipSuccess) e = launch_fill_zero(maxx, sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
   const int grid_boxes = 8 * ((nbox + 7) / 8);
-  if (((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double) <= 96 * 1024) {
+  if (g.m >= 4 && g.m <= 16) {
+    // column blocks past the f column hold zeros in X and in R32 (left as the caller wrote them)
+    constexpr int NW = HPS_RES_NW, CB = 16 / NW;
+    const int ncb = (g.nb + 1 + CB - 1) / CB;
+    const dim3 grid(grid_boxes * ncb), block(kRmThreads);
+    switch (g.m) {
+#define HPS_RES_CASE(M)                                                                                   \
+  case M:                                                                                                 \
+    hipLaunchKernelGGL((residual_mfma_kernel<M, NW>), grid, block, 0, st, g, nbox, ncb, b, f, X, R32, maxr, maxx, \
+                       active);                                                                           \
+    break;
+      HPS_RES_CASE(4) HPS_RES_CASE(5) HPS_RES_CASE(6) HPS_RES_CASE(7) HPS_RES_CASE(8) HPS_RES_CASE(9)
+      HPS_RES_CASE(10) HPS_RES_CASE(11) HPS_RES_CASE(12) HPS_RES_CASE(13) HPS_RES_CASE(14) HPS_RES_CASE(15)
+      HPS_RES_CASE(16)
+#undef HPS_RES_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else if (((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double) <= 96 * 1024) {
     const size_t shm = ((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double);
     hipLaunchKernelGGL(residual_kernel<4>, dim3(grid_boxes * (g.ldx / 4)), dim3(kResThreads), shm, st, g, nbox, b, f,
                        X, R32, maxr, maxx, active);
