@@ -33,6 +33,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_gemm_16x16x16_p16_hbm_traffic.md")
+KERNEL_SOURCES = ("paper_2503_04033_amd/csrc/common.h", "paper_2503_04033_amd/csrc/lu.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
+    or None when the summary is missing, is for another kernel, or the kernel's sources
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith(("#", "|", " ")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for src in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+        if kv.get("kernel") != kernel or kv.get("kernel_sources_sha256") != h.hexdigest():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def flops_per_box(n_i: int, n_b: int, passes: int) -> dict:
     """Algorithmic flops of one box: LU 2/3 n^3, each solve pass 2 n^2 (n_b + 1)."""
     return {"lu": 2.0 / 3.0 * n_i ** 3, "solve": passes * 2.0 * n_i ** 2 * (n_b + 1)}
@@ -158,12 +184,27 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=24)
     ap.add_argument("--ir-max-iter", type=int, default=3)
     ap.add_argument("--ir-tol", type=float, default=1e-11)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run three device-to-device copies of MIB MiB (HBM counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the leaf reduction shards by boxes with no exchange, and this "
               "build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if a.copy_calibration:
+        # a plain copy of known size: FETCH_SIZE and WRITE_SIZE of its kernel should each read
+        # MIB * 1024 KiB; the ratio scales the counters of the leaf-reduction kernels
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_mib": a.copy_calibration, "kib_per_copy": a.copy_calibration * 1024}))
+        return
 
     import workloads as W
     prob = W.config3()
@@ -206,7 +247,8 @@ def main():
     berr = fp32.berr.cpu().numpy()
     info_bad = int((fp32.infov.cpu().numpy() != 0).sum())
     log(f"fp32_ir: {ms:.1f} ms/step, {boxes_s:.1f} boxes/s (wall {wall:.1f} s); phases {phases}")
-    passes = 1 + float(np.mean(np.abs(iters)))
+    steps = np.where(iters >= 0, iters, -1 - iters)  # corrections applied per box
+    passes = 1 + float(np.mean(steps))
     fl = flops_per_box(i.n_i, i.n_b, passes)
     tot_flops = nbox * (fl["lu"] + fl["solve"])
     fams = fp32.plan.profile_read()
@@ -215,8 +257,8 @@ def main():
     launched_passes = 1 + a.ir_max_iter
     for k in ("solve_gemm", "solve_leaf"):
         fams[k]["flops"] *= passes / launched_passes
-    KNAMES = {"solve_gemm": "gemm_op_kernel<float,false> (solve-phase tile GEMM)",
-              "lu_gemm": "gemm_op_kernel<float,true> (LU tile GEMM)",
+    KNAMES = {"solve_gemm": "gemm_op_kernel<float, false>",
+              "lu_gemm": "gemm_op_kernel<float, true>",
               "lu_panel": "lu_panel_kernel<float> (pivoted panel)",
               "residual": "residual_kernel (FP64 refinement residual)"}
     dom = max(fams, key=lambda k: fams[k]["ms"])
@@ -240,7 +282,7 @@ def main():
                                      for k, v in fams.items()},
         "roofline": {"kernel": KNAMES.get(dom, dom), "bound": "mfma" if fd["flops"] else "hbm",
                      "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(KNAMES.get(dom, dom)),
                      "per_launch": {"launches": fd["launches"], "avg_ms": round(fd["ms"] / max(fd["launches"], 1), 4),
                                     "avg_algorithmic_flops": fd["flops"] / max(fd["launches"], 1)}},
     }

@@ -132,7 +132,8 @@ hps_status hps_leaf_factor(hps_plan plan, int32_t nbox, void* A, int32_t* perm, 
  *   is formed in FP64 through the tensor-product structure of A_ii (b is needed
  *   for that), the correction is solved in FP32 and added in FP64, until the
  *   backward error is <= ir_tol or ir_max_iter steps; ir_iters[box] = steps
- *   taken (negative if still above ir_tol), berr[box] = final backward error.
+ *   taken, or -1 - steps if still above ir_tol (a NaN counts as above);
+ *   berr[box] = final backward error.
  *   T = A_bb - A_bi X_b: row block a / column block b of box t is written to
  *   T_vals + slot_map[t*36 + 6a + b] * m^4 (row-major m^2 x m^2 block) when the
  *   slot is >= 0; slot -1 drops the block (rows of boundary faces, columns of

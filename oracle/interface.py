@@ -139,15 +139,40 @@ def face_values(prob, boxes, box_faces, u_face):
     return u_b
 
 
-def solve(prob, b_field=None) -> TwoLevelResult:
-    """Two-level solve: all leaf reductions, sparse interface solve, reconstruction."""
-    boxes = [box_setup(prob, t, b_field) for t in range(prob.nbox)]
+def _lean(bd: BoxData) -> BoxData:
+    """Keep only what assembly and reconstruction read (S, v, T, g); drops the dense
+    blocks, X and the LU factors, which dominate memory at large p."""
+    red = leaf.LeafReduction(X=None, S=bd.red.S, T=bd.red.T, v=bd.red.v, g=bd.red.g, lu=None)
+    return BoxData(xi=bd.xi, xb=bd.xb, b_int=bd.b_int, f_int=bd.f_int, blocks=None, red=red)
+
+
+def solve(prob, b_field=None, keep_boxes: bool = True, progress=None, dense: bool = False) -> TwoLevelResult:
+    """Two-level solve: all leaf reductions, sparse interface solve, reconstruction.
+
+    keep_boxes=False keeps per box only S, v, T and g (same arithmetic, less memory);
+    dense=True solves the interface system with dense LAPACK LU instead of SuperLU
+    (the same system; SuperLU's fill makes it far slower once the faces carry
+    hundreds of nodes each); progress(msg) is called after each box and phase.
+    """
+    boxes = []
+    for t in range(prob.nbox):
+        bd = box_setup(prob, t, b_field)
+        boxes.append(bd if keep_boxes else _lean(bd))
+        if progress:
+            progress(f"box {t + 1}/{prob.nbox}")
     T_ff, rhs, box_faces, face_boxes = assemble(prob, boxes)
-    if T_ff.shape[0] > 0:
+    if progress:
+        progress(f"interface matrix {T_ff.shape[0]} unknowns, {T_ff.nnz} nonzeros")
+    if T_ff.shape[0] > 0 and dense:
+        lu = None
+        u_face = np.linalg.solve(T_ff.toarray(), rhs)
+    elif T_ff.shape[0] > 0:
         lu = scipy.sparse.linalg.splu(T_ff.tocsc())
         u_face = lu.solve(rhs)
     else:
         lu, u_face = None, np.zeros(0)
+    if progress:
+        progress("interface solve done")
     u_b = face_values(prob, boxes, box_faces, u_face)
     u_i = np.stack([bd.red.v + bd.red.S @ u_b[t] for t, bd in enumerate(boxes)])
     return TwoLevelResult(boxes=boxes, box_faces=box_faces, face_boxes=face_boxes, T_ff=T_ff, rhs=rhs,

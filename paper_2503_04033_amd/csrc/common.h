@@ -150,16 +150,16 @@ __device__ inline void wg_gemm_sub(typename Mfma<T>::acc (&acc)[RT][CT], ARow ar
 // GM x GN waves; wave (wm, wn) owns rows [wm*WRT*16, +WRT*16) and columns
 // [wn*WCT*16, +WCT*16) of the MT x NT tile.  Both operands are staged through
 // double-buffered LDS in chunks of KC: while the MFMAs of chunk c read LDS, the
-// 16-byte global loads of chunk c+1 sit in a few staging registers and are
-// written to the other buffer afterwards, so each chunk costs one barrier and
-// the global latency overlaps the math.  A fragments are read as 4 consecutive
+// 16-byte global loads of chunks c+1 .. c+PF sit in staging registers (PF sets)
+// and chunk c+1 is written to the other buffer afterwards, so each chunk costs
+// one barrier and a global load has PF chunks of math to arrive.  A fragments are read as 4 consecutive
 // k values per lane (the MFMA k slot g = lane/16 stands for k = 4g + t, t the
 // step); B fragments are the matching rows.
 //   arow(r): pointer to A row r of the tile (r in [0, MT)), nullptr -> zeros;
 //   brow(k): pointer to B[k][tile col 0]; bcols: valid tile columns (rest zero).
 //   (k1 - k0) % KC == 0.  smem: SMEM elements.
 // ---------------------------------------------------------------------------
-template <typename T, int WRT, int WCT, int GM, int GN, int KC>
+template <typename T, int WRT, int WCT, int GM, int GN, int KC, int PF = 1>
 struct TileGemm {
   static constexpr int MT = GM * WRT * 16;
   static constexpr int NT = GN * WCT * 16;
@@ -193,15 +193,15 @@ struct TileGemm {
       asrc[q] = arow(e / KC);
       if (asrc[q]) asrc[q] += e % KC;
     }
-    vec_t ast[ALOADS], bst[BLOADS];
-    auto gload = [&](int kb) {
+    vec_t ast[PF][ALOADS], bst[PF][BLOADS];
+    auto gload = [&](int kb, int set) {
 #pragma unroll
       for (int q = 0; q < ALOADS; q++) {
         if (asrc[q]) {
-          ast[q] = *reinterpret_cast<const vec_t*>(asrc[q] + kb);
+          ast[set][q] = *reinterpret_cast<const vec_t*>(asrc[q] + kb);
         } else {
 #pragma unroll
-          for (int v = 0; v < VEC; v++) ast[q][v] = T(0);
+          for (int v = 0; v < VEC; v++) ast[set][q][v] = T(0);
         }
       }
 #pragma unroll
@@ -209,25 +209,25 @@ struct TileGemm {
         const int e = (tid + q * NTHR) * VEC;
         const int kk = e / NT, c = e - kk * NT;
         if (c < bcols) {
-          bst[q] = *reinterpret_cast<const vec_t*>(brow(kb + kk) + c);
+          bst[set][q] = *reinterpret_cast<const vec_t*>(brow(kb + kk) + c);
         } else {
 #pragma unroll
-          for (int v = 0; v < VEC; v++) bst[q][v] = T(0);
+          for (int v = 0; v < VEC; v++) bst[set][q][v] = T(0);
         }
       }
     };
-    auto lstore = [&](T* buf) {
+    auto lstore = [&](T* buf, int set) {
 #pragma unroll
       for (int q = 0; q < ALOADS; q++) {
         const int e = (tid + q * NTHR) * VEC;
-        *reinterpret_cast<vec_t*>(buf + (e / KC) * LDA + e % KC) = ast[q];
+        *reinterpret_cast<vec_t*>(buf + (e / KC) * LDA + e % KC) = ast[set][q];
       }
       T* bb = buf + ABUF;
 #pragma unroll
       for (int q = 0; q < BLOADS; q++) {
         const int e = (tid + q * NTHR) * VEC;
         const int kk = e / NT, c = e - kk * NT;
-        *reinterpret_cast<vec_t*>(bb + kk * LDB + c) = bst[q];
+        *reinterpret_cast<vec_t*>(bb + kk * LDB + c) = bst[set][q];
       }
     };
     auto compute = [&](const T* buf) {
@@ -250,16 +250,37 @@ struct TileGemm {
         }
       }
     };
-    gload(k0);
+    // Chunk c lives in staging set c % PF; the loop is unrolled by PF so the sets are
+    // static.  Loads are issued unconditionally (past the end they reread the last
+    // chunk) so that the compiler's wait counts keep PF chunks in flight.
+#pragma unroll
+    for (int j = 0; j < PF; j++) gload(k0 + (j < nchunk ? j : nchunk - 1) * KC, j);
     __syncthreads();  // previous users of smem are done
-    lstore(smem);
-    for (int c = 0; c < nchunk; c++) {
-      T* cur = smem + (c & 1) * (ABUF + BBUF);
-      T* nxt = smem + ((c + 1) & 1) * (ABUF + BBUF);
-      __syncthreads();
-      if (c + 1 < nchunk) gload(k0 + (c + 1) * KC);
-      compute(cur);
-      if (c + 1 < nchunk) lstore(nxt);
+    lstore(smem, 0);
+    int c0 = 0;
+    for (; c0 + PF <= nchunk; c0 += PF) {
+#pragma unroll
+      for (int j = 0; j < PF; j++) {
+        const int c = c0 + j;
+        T* cur = smem + (c & 1) * (ABUF + BBUF);
+        T* nxt = smem + ((c + 1) & 1) * (ABUF + BBUF);
+        __syncthreads();
+        const int cl = c + PF < nchunk ? c + PF : nchunk - 1;
+        gload(k0 + cl * KC, j);  // set j held chunk c, already in LDS
+        compute(cur);
+        if (c + 1 < nchunk) lstore(nxt, (j + 1) % PF);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j + 1 < PF; j++) {  // the last nchunk % PF chunks: nothing left to load
+      const int c = c0 + j;
+      if (c < nchunk) {
+        T* cur = smem + (c & 1) * (ABUF + BBUF);
+        T* nxt = smem + ((c + 1) & 1) * (ABUF + BBUF);
+        __syncthreads();
+        compute(cur);
+        if (c + 1 < nchunk) lstore(nxt, (j + 1) % PF);
+      }
     }
   }
 };

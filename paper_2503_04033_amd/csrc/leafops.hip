@@ -619,7 +619,7 @@ __global__ void ir_check_kernel(int nbox, int it, int last, double tol, const do
     if (iters) iters[box] = it;
   } else if (last) {
     active[box] = 0;
-    if (iters) iters[box] = -it;
+    if (iters) iters[box] = -1 - it;  // still above tol after `it` corrections
   }
 }
 

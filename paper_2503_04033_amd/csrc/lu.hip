@@ -354,11 +354,12 @@ __global__ __launch_bounds__(kLuThreads, 1) void lu_panel_kernel(Geom g, T* A_al
 }
 
 template <typename T> struct GemmCfg;
-// 64 x 64 workgroup tiles, 4 waves of 32 x 32: the best or near-best shape for
-// every update size in the recursion on gfx950 (more resident workgroups per CU
-// outweigh the smaller operand reuse).
-template <> struct GemmCfg<float> { typedef TileGemm<float, 2, 2, 2, 2, 32> G; };
-template <> struct GemmCfg<double> { typedef TileGemm<double, 2, 2, 2, 2, 16> G; };
+// 64 x 64 workgroup tiles, 4 waves of 32 x 32, K chunks of 16 with two chunks in
+// flight: the best shape measured for every update size in the recursion on gfx950
+// (more resident workgroups per CU outweigh the smaller operand reuse; the second
+// staging set hides the global-load latency behind one more chunk of MFMAs).
+template <> struct GemmCfg<float> { typedef TileGemm<float, 2, 2, 2, 2, 16, 2> G; };
+template <> struct GemmCfg<double> { typedef TileGemm<double, 2, 2, 2, 2, 16, 2> G; };
 
 // C[row(pos)][n] -= sum_k F[perm[pos]][k] * B[row(k)][n] for pos in [m0,m1),
 // n in [n0,n1), k in [k0,k1).  F is the factor (ld n_pad, rows via perm); B and

@@ -19,6 +19,7 @@ from __future__ import annotations
 from dataclasses import dataclass
 
 import numpy as np
+import scipy.linalg
 import scipy.sparse
 import scipy.sparse.linalg
 
@@ -134,14 +135,34 @@ def boundary_mask(layout: InterfaceLayout) -> np.ndarray:
 
 
 class InterfaceSolver:
-    """Sparse LU of T_FF (SciPy SuperLU), reusable for many right-hand sides."""
+    """LU of T_FF on the host, reusable for many right-hand sides (and transposed solves).
 
-    def __init__(self, layout: InterfaceLayout, T_vals: np.ndarray):
+    method "auto": dense LAPACK LU (multithreaded) up to DENSE_MAX unknowns, where the
+    interface of a few boxes per axis at large p is small but its m^2 x m^2 blocks make
+    SuperLU's supernodes slow; SciPy SuperLU with the minimum-degree ordering of
+    A^T + A above that.  "dense" and "sparse" force one of the two.
+    """
+
+    DENSE_MAX = 48000
+
+    def __init__(self, layout: InterfaceLayout, T_vals: np.ndarray, method: str = "auto"):
         self.layout = layout
-        A = bsr_matrix(layout, T_vals).tocsc()
-        self.lu = scipy.sparse.linalg.splu(A) if A.shape[0] > 0 else None
+        A = bsr_matrix(layout, T_vals)
+        n = A.shape[0]
+        if method not in ("auto", "dense", "sparse"):
+            raise ValueError("method must be 'auto', 'dense' or 'sparse'")
+        self.method = ("dense" if n <= self.DENSE_MAX else "sparse") if method == "auto" else method
+        self.lu = None
+        if n == 0:
+            return
+        if self.method == "dense":
+            self.lu = scipy.linalg.lu_factor(A.toarray(), check_finite=False)
+        else:
+            self.lu = scipy.sparse.linalg.splu(A.tocsc(), permc_spec="MMD_AT_PLUS_A")
 
     def solve(self, rhs: np.ndarray, trans: str = "N") -> np.ndarray:
         if self.lu is None:
             return np.zeros(0)
+        if self.method == "dense":
+            return scipy.linalg.lu_solve(self.lu, rhs, trans=0 if trans == "N" else 1, check_finite=False)
         return self.lu.solve(rhs, trans=trans)

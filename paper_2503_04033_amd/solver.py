@@ -9,6 +9,11 @@ loads, solves for the interface values and reconstructs the interiors on the
 GPU (hps_leaf_reconstruct, a5).  X (the interior solution operator and load
 response) is kept in HBM per box when `keep_X` is set; otherwise the chunk is
 recomputed in the solve stage, as the paper does for large problems.
+
+FP32_IR plans: a box whose refinement ends above ir_tol (ir_iters < 0) is
+factored and solved again with an FP64 plan before the interface matrix is
+reduced; its ir_iters stays negative and its id is listed in
+BuildResult.extra["fp64_fallback"].
 """
 from __future__ import annotations
 
@@ -58,6 +63,8 @@ class TwoLevelSolver:
         self.layout = itf.build_layout(self.nboxes, self.info.m)
         self.chunk = int(chunk) if chunk else self.nbox
         self.keep_X = keep_X
+        self.precision = precision
+        self._plan64 = None
         self.origins = torch.tensor(_box_origins(self.nboxes, self.lo, self.h), device=self.device)
         self.slot_map = torch.tensor(self.layout.slot_map, device=self.device)
         self.bmask = itf.boundary_mask(self.layout)
@@ -109,10 +116,50 @@ class TwoLevelSolver:
             plan.hps_leaf_dtn(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
                               g_dir[sl].contiguous(), self.slot_map[sl].contiguous(), T_vals, g_loads[sl], X,
                               iters[sl], berr[sl], bufs["ws"])
+        redo = self._unconverged(iters)
+        if redo:
+            self._redo_fp64(redo, b, f, g_dir, T_vals, g_loads, berr, X_all)
         pairs = torch.tensor(self.layout.reduce_pairs, device=self.device)
         if pairs.shape[0]:
             hps_interface_reduce(pairs, mm * mm, T_vals)
-        return BuildResult(T_vals=T_vals, g_loads=g_loads, info=info, ir_iters=iters, berr=berr, X=X_all)
+        return BuildResult(T_vals=T_vals, g_loads=g_loads, info=info, ir_iters=iters, berr=berr, X=X_all,
+                           extra={"fp64_fallback": redo})
+
+    # ---- boxes whose FP64 refinement did not converge ----------------------------
+    def _unconverged(self, iters: torch.Tensor, offset: int = 0) -> list:
+        if self.precision != "fp32_ir":
+            return []
+        return [offset + int(t) for t in torch.nonzero(iters < 0).flatten().cpu().tolist()]
+
+    def _redo_fp64(self, ids: list, b, f, g_dir, T_vals, g_loads, berr, X_all=None, X_chunk=None, c0: int = 0):
+        """Factor and solve boxes `ids` again in FP64, overwriting their T blocks, loads,
+        backward errors and X (in X_all, or in X_chunk whose first box is c0)."""
+        if self._plan64 is None:
+            self._plan64 = LeafPlan(self.p, self.h, self.kappa, "fp64")
+        plan, i = self._plan64, self.info
+        xs = i.n_pad * i.ldx
+        C = min(self.chunk, len(ids))
+        bufs = plan.alloc(C, self.device)
+        for k0 in range(0, len(ids), C):
+            part = ids[k0:k0 + C]
+            nb = len(part)
+            idx = torch.tensor(part, dtype=torch.long, device=self.device)
+            bb = b[idx].contiguous()
+            ff = f[idx].contiguous() if f is not None else None
+            gl = torch.empty(nb, i.n_b, dtype=torch.float64, device=self.device)
+            plan.hps_leaf_operators(nb, bb, bufs["A"], bufs["anorm"])
+            plan.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], bufs["info"])
+            plan.hps_leaf_dtn(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
+                              g_dir[idx].contiguous(), self.slot_map[idx].contiguous(), T_vals, gl, bufs["X"],
+                              bufs["ir_iters"], bufs["berr"], bufs["ws"])
+            g_loads[idx] = gl
+            if berr is not None:
+                berr[idx] = bufs["berr"][:nb]
+            Xn = bufs["X"][:nb * xs].view(nb, xs)
+            if X_all is not None:
+                X_all.view(self.nbox, xs)[idx] = Xn
+            elif X_chunk is not None:
+                X_chunk.view(-1, xs)[idx - c0] = Xn
 
     # ---- solve stage (Alg. 2) ---------------------------------------------------
     def solve(self, br: BuildResult, g_dir: torch.Tensor, isolver: Optional[itf.InterfaceSolver] = None,
@@ -152,6 +199,10 @@ class TwoLevelSolver:
             plan.hps_leaf_dtn(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
                               g_dir[sl].contiguous(), self.slot_map[sl].contiguous(), scratch_T, scratch_g[:nb],
                               bufs["X"], bufs["ir_iters"], bufs["berr"], bufs["ws"])
+            redo = self._unconverged(bufs["ir_iters"][:nb], c0)
+            if redo:
+                self._redo_fp64(redo, b, f, g_dir, scratch_T, torch.empty(self.nbox, i.n_b, dtype=torch.float64,
+                                device=self.device), None, X_chunk=bufs["X"], c0=c0)
             plan.hps_leaf_reconstruct(nb, bufs["X"], ub_d[sl].contiguous(), ui[sl])
         return u_face, ub, ui, isolver
 

@@ -141,3 +141,27 @@ def test_interface_rhs_and_face_values():
     mask = itf.boundary_mask(lay)
     assert np.all(ub[mask] == -1)
     assert np.all(ub[~mask] >= 1000)
+
+
+def test_interface_solver_dense_and_sparse_agree():
+    # the host interface LU: dense LAPACK and SuperLU give the same solution and transposed
+    # solution of the same block-sparse system
+    from paper_2503_04033_amd import interface as itf
+    layout = itf.build_layout((3, 2, 2), 4)
+    mm = 16
+    rng = np.random.default_rng(3)
+    T = rng.standard_normal(layout.nslot_total * mm * mm + 1) * 0.1
+    T_primary = T[:layout.nslot * mm * mm].reshape(layout.nslot, mm, mm)
+    for r in range(len(layout.indptr) - 1):
+        for s in range(layout.indptr[r], layout.indptr[r + 1]):
+            if layout.indices[s] == r:
+                T_primary[s] += 4.0 * np.eye(mm)
+    rhs = rng.standard_normal((len(layout.indptr) - 1) * mm)
+    dense = itf.InterfaceSolver(layout, T, method="dense")
+    sparse = itf.InterfaceSolver(layout, T, method="sparse")
+    assert dense.method == "dense" and sparse.method == "sparse"
+    A = itf.bsr_matrix(layout, T).toarray()
+    for trans, M in (("N", A), ("T", A.T)):
+        xd, xs = dense.solve(rhs, trans=trans), sparse.solve(rhs, trans=trans)
+        assert np.allclose(M @ xd, rhs, atol=1e-10)
+        assert np.allclose(xd, xs, atol=1e-10)
