@@ -19,6 +19,9 @@
  *                        the equivalent load g = -A_bi v (v = X_f) lifted by the
  *                        Dirichlet data of boundary faces;
  *   hps_leaf_reconstruct u_i = v + S u_b = X_f - X_b u_b (last step of Alg. 2);
+ *   hps_leaf_interior_solve  the same u_i from the factors, refined in FP64;
+ *   hps_leaf_flux        outward normal derivatives at the faces (interface
+ *                        residual for refining the interface solution);
  *   hps_leaf_adjoint_*   transposed solves for the gradient of a misfit with
  *                        respect to b (transpose of eq. factor2).
  * The sparse interface system itself is assembled and factored by the caller.
@@ -161,10 +164,32 @@ hps_status hps_interface_reduce(int32_t npairs, const int64_t* pairs, int64_t bl
 hps_status hps_leaf_reconstruct(hps_plan plan, int32_t nbox, const double* X, const double* u_b, double* u_i,
                                 hipStream_t stream);
 
+/* a5, solve form (Sec. 2.2 step 4 with the local factors instead of X; the
+ * interior solve of Alg. 2): u_i = A_ii^{-1} (f_i - A_ib u_b) for every box, with
+ * the factors of hps_leaf_factor and FP64 refinement: u = (LU)^{-1} r_0, then
+ * `steps` times r = f_i - A_ib u_b - A_ii u (FP64, tensor structure of the
+ * operator), u += (LU)^{-1} r.  The vector solves run in FP64 arithmetic on the
+ * stored (FP32 or FP64) factors; with FP32 factors each step gains about six
+ * digits on these boxes, so 2 steps reach FP64 rounding.  b, f_i (NULL = 0),
+ * u_i: [nbox][n_i]; u_b: [nbox][n_b]; steps in 0..8.  ws: hps_plan_info.ws_bytes
+ * per box (uses nbox * n_i doubles).  Any precision. */
+hps_status hps_leaf_interior_solve(hps_plan plan, int32_t nbox, const void* LU, const int32_t* perm,
+                                  const void* dinv, const double* b, const double* f, const double* u_b,
+                                  double* u_i, int32_t steps, void* ws, hipStream_t stream);
+
+/* Outward normal derivative at every face node of every box, flux = A_bi u_i +
+ * A_bb u_b (the face rows of eq. Aentries: (2/h_a) D[p-1][.] along the normal line
+ * on + faces, -(2/h_a) D[0][.] on - faces).  Summed over the two boxes of an
+ * internal face it is minus the residual of the interface equations
+ * T_FF u_F = rhs for the exact interiors, which the caller uses to refine u_F.
+ * u_i: [nbox][n_i]; u_b, flux: [nbox][n_b], FP64. */
+hps_status hps_leaf_flux(hps_plan plan, int32_t nbox, const double* u_i, const double* u_b, double* flux,
+                         hipStream_t stream);
+
 /* a6 -- adjoint solves for dJ/db (transpose of eq. factor2):
  * hps_leaf_adjoint_solve:  z = A_ii^{-T} (w_i - A_bi^T lam_b) per box and
- *   y_b = -A_ib^T z; lam_b may be NULL (zero).  Uses the factors of
- *   hps_leaf_factor; FP32_IR plans refine in FP64 like hps_leaf_dtn.
+ *   y_b = -A_ib^T z; lam_b may be NULL (zero).  Uses the FP64 factors of
+ *   hps_leaf_factor: FP64 plans only (HPS_EUNSUPPORTED otherwise).
  *   w_i, z: [nbox][n_i]; lam_b, y_b: [nbox][n_b]; y_b may be NULL.
  * ws: hps_plan_info.ws_bytes per box. */
 hps_status hps_leaf_adjoint_solve(hps_plan plan, int32_t nbox, const void* LU, const int32_t* perm,

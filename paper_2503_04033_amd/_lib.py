@@ -15,6 +15,7 @@ EXPORTS = (
     "hps_plan_create", "hps_plan_destroy", "hps_plan_get_info", "hps_leaf_nodes", "hps_leaf_operators",
     "hps_leaf_factor", "hps_leaf_dtn", "hps_interface_reduce", "hps_leaf_reconstruct", "hps_leaf_adjoint_solve",
     "hps_leaf_adjoint_grad", "hps_status_string", "hps_plan_profile_enable", "hps_plan_profile_read",
+    "hps_leaf_interior_solve", "hps_leaf_flux",
 )
 
 PROFILE_FAMILIES = ("lu_gemm", "lu_panel", "lu_leaf", "solve_gemm", "solve_leaf", "residual", "dtn", "operators")
@@ -65,6 +66,8 @@ def load() -> C.CDLL:
         "hps_leaf_reconstruct": [P, I32, P, P, P, P],
         "hps_leaf_adjoint_solve": [P, I32, P, P, P, P, P, P, P, P, P, P],
         "hps_leaf_adjoint_grad": [P, I32, P, P, P, P],
+        "hps_leaf_interior_solve": [P, I32, P, P, P, P, P, P, P, I32, P, P],
+        "hps_leaf_flux": [P, I32, P, P, P, P],
         "hps_plan_profile_enable": [P, I32],
         "hps_plan_profile_read": [P, C.POINTER(Profile)],
     }

@@ -353,6 +353,35 @@ hps_status hps_leaf_reconstruct(hps_plan pl, int32_t nbox, const double* X, cons
   return dev(hps::launch_reconstruct(pl->g, nbox, X, u_b, u_i, st));
 }
 
+hps_status hps_leaf_interior_solve(hps_plan pl, int32_t nbox, const void* LU, const int32_t* perm,
+                                  const void* dinv, const double* b, const double* f, const double* u_b,
+                                  double* u_i, int32_t steps, void* ws, hipStream_t st) {
+  if (bad_plan(pl) || nbox < 0 || nbox > 65535 || steps < 0 || steps > 8) return HPS_EINVAL;
+  if (nbox == 0) return HPS_OK;
+  if (!LU || !perm || !dinv || !b || !u_b || !u_i || !ws) return HPS_EINVAL;
+  const Geom& g = pl->g;
+  double* r = static_cast<double*>(ws);
+  const bool f32 = pl->desc.precision == HPS_FP32_IR;
+  for (int s = 0; s <= steps; s++) {
+    // r = f - A_ib u_b - A_ii u (u = 0 first), then u += (LU)^{-1} r
+    HPS_TRY(hps::launch_box_residual(g, nbox, b, f, u_b, s == 0 ? nullptr : u_i, r, st));
+    if (f32)
+      HPS_TRY(hps::launch_getrs_vec<float>(g, nbox, static_cast<const float*>(LU), perm,
+                                           static_cast<const float*>(dinv), r, u_i, s > 0, st));
+    else
+      HPS_TRY(hps::launch_getrs_vec<double>(g, nbox, static_cast<const double*>(LU), perm,
+                                            static_cast<const double*>(dinv), r, u_i, s > 0, st));
+  }
+  return HPS_OK;
+}
+
+hps_status hps_leaf_flux(hps_plan pl, int32_t nbox, const double* u_i, const double* u_b, double* flux,
+                         hipStream_t st) {
+  if (bad_plan(pl) || nbox < 0 || nbox > 65535 || (nbox > 0 && (!u_i || !u_b || !flux))) return HPS_EINVAL;
+  if (nbox == 0) return HPS_OK;
+  return dev(hps::launch_flux(pl->g, nbox, u_i, u_b, flux, st));
+}
+
 hps_status hps_leaf_adjoint_solve(hps_plan pl, int32_t nbox, const void* LU, const int32_t* perm,
                                   const void* dinv, const double* b, const double* w_i, const double* lam_b,
                                   double* z, double* y_b, void* ws, hipStream_t st) {

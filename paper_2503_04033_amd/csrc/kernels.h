@@ -114,6 +114,12 @@ hipError_t launch_getrs_t(const Geom& g, int nbox, const double* LU, const int* 
                           const double* rhs, double* z, hipStream_t st);
 hipError_t launch_adjoint_yb(const Geom& g, int nbox, const double* z, double* yb, hipStream_t st);
 hipError_t launch_compact(const Geom& g, int nbox, const double* in, double* out, hipStream_t st);
+hipError_t launch_box_residual(const Geom& g, int nbox, const double* b, const double* f, const double* ub,
+                               const double* u, double* r, hipStream_t st);
+template <typename T>
+hipError_t launch_getrs_vec(const Geom& g, int nbox, const T* LU, const int* perm, const T* dinv, const double* r,
+                            double* x, int accumulate, hipStream_t st);
+hipError_t launch_flux(const Geom& g, int nbox, const double* u, const double* ub, double* flux, hipStream_t st);
 hipError_t launch_grad(const Geom& g, int nbox, const double* lam, const double* u, double* grad, hipStream_t st);
 
 }  // namespace hps

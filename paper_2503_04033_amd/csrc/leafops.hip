@@ -872,6 +872,152 @@ hipError_t launch_getrs_t(const Geom& g, int nbox, const double* LU, const int* 
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------
+// a5 in solve form: u_i = A_ii^{-1} (f_i - A_ib u_b), refined in FP64.
+// ----------------------------------------------------------------------------
+// r = f - A_ib u_b - A_ii u for one vector per box: with the face values u_b at the
+// two ends of every line, -(A_ii u + A_ib u_b) is s2x, s2y, s2z times D2 applied
+// along the full x-, y- and z-lines, plus kappa^2 b u.  One workgroup per box.
+__global__ __launch_bounds__(256) void box_residual_kernel(Geom g, int nbox, const double* b, const double* f,
+                                                           const double* ub_all, const double* u_all, double* r_all) {
+  extern __shared__ double us[];  // u [n], then D2 [p][p]
+  const int box = blockIdx.x;
+  const int m = g.m, mm = m * m, n = g.n, p = g.p;
+  double* d2 = us + n;
+  const double* u = u_all ? u_all + (size_t)box * n : nullptr;
+  const double* ub = ub_all + (size_t)box * g.nb;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) us[i] = u ? u[i] : 0.0;
+  for (int i = threadIdx.x; i < p * p; i += blockDim.x) d2[i] = g.D2[i];
+  __syncthreads();
+  for (int node = threadIdx.x; node < n; node += blockDim.x) {
+    const int cd = g.coords[node];
+    const int ii = cd & 255, jj = (cd >> 8) & 255, kk = cd >> 16;
+    double lx = d2[(ii + 1) * p] * ub[0 * mm + jj + m * kk] + d2[(ii + 1) * p + p - 1] * ub[1 * mm + jj + m * kk];
+    double ly = d2[(jj + 1) * p] * ub[2 * mm + ii + m * kk] + d2[(jj + 1) * p + p - 1] * ub[3 * mm + ii + m * kk];
+    double lz = d2[(kk + 1) * p] * ub[4 * mm + ii + m * jj] + d2[(kk + 1) * p + p - 1] * ub[5 * mm + ii + m * jj];
+    for (int l = 0; l < m; l++) {
+      lx += d2[(ii + 1) * p + l + 1] * us[node - ii + l];
+      ly += d2[(jj + 1) * p + l + 1] * us[node + m * (l - jj)];
+      lz += d2[(kk + 1) * p + l + 1] * us[node + mm * (l - kk)];
+    }
+    const double fv = f ? f[(size_t)box * n + node] : 0.0;
+    r_all[(size_t)box * n + node] = fv + g.s2[0] * lx + g.s2[1] * ly + g.s2[2] * lz +
+                                    g.kappa2 * b[(size_t)box * n + node] * us[node];
+  }
+}
+
+// x = (P^T L U)^{-1} r for one vector per box with the stored factors: positions hold
+// physical rows perm[pos]; each 64-block is solved with its stored diagonal inverse and
+// the rows below (forward) or above (backward) are updated, 16 lanes per row.  The
+// factors may be FP32; the vector is carried in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void getrs_vec_kernel(Geom g, int nbox, const T* LU_all, const int* perm_all,
+                                                        const T* dinv_all, const double* r_all, double* x_all,
+                                                        int accumulate) {
+  extern __shared__ double vec[];  // [n_pad], then 64 of scratch
+  double* tmp = vec + g.n_pad;
+  const int box = blockIdx.x;
+  const int N = g.n_pad, n = g.n;
+  const T* LU = LU_all + (size_t)box * N * N;
+  const int* perm = perm_all + (size_t)box * N;
+  const T* dinv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64;
+  const double* r = r_all + (size_t)box * n;
+  const int lane16 = threadIdx.x & 15, grp = threadIdx.x >> 4, ngrp = blockDim.x >> 4;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const int pr = perm[i];
+    vec[i] = pr < n ? r[pr] : 0.0;
+  }
+  __syncthreads();
+  auto block_inverse = [&](const T* Inv, int s, int w) {
+    if (threadIdx.x < w) {
+      double acc = 0.0;
+      for (int k = 0; k < w; k++) acc += (double)Inv[threadIdx.x * 64 + k] * vec[s + k];
+      tmp[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
+    __syncthreads();
+  };
+  // rows [j0, j1) -= LU[perm[row]][s .. s+w) . vec[s .. s+w)
+  auto update = [&](int j0, int j1, int s, int w) {
+    for (int j = j0 + grp; j < j1; j += ngrp) {
+      const T* row = LU + (size_t)perm[j] * N + s;
+      double acc = 0.0;
+      for (int c = lane16; c < w; c += 16) acc += (double)row[c] * vec[s + c];
+      for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+      if (lane16 == 0) vec[j] -= acc;
+    }
+    __syncthreads();
+  };
+  for (int bk = 0; bk < g.npanel; bk++) {  // L y = P r
+    const int s = bk * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
+    block_inverse(dinv + (size_t)(2 * bk) * 64 * 64, s, w);
+    update(s + w, N, s, w);
+  }
+  for (int bk = g.npanel - 1; bk >= 0; bk--) {  // U x = y
+    const int s = bk * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
+    block_inverse(dinv + (size_t)(2 * bk + 1) * 64 * 64, s, w);
+    update(0, s, s, w);
+  }
+  double* x = x_all + (size_t)box * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = accumulate ? x[i] + vec[i] : vec[i];
+}
+
+hipError_t launch_box_residual(const Geom& g, int nbox, const double* b, const double* f, const double* ub,
+                               const double* u, double* r, hipStream_t st) {
+  const size_t shm = sizeof(double) * ((size_t)g.n + (size_t)g.p * g.p);
+  hipLaunchKernelGGL(box_residual_kernel, dim3(nbox), dim3(256), shm, st, g, nbox, b, f, ub, u, r);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_getrs_vec(const Geom& g, int nbox, const T* LU, const int* perm, const T* dinv, const double* r,
+                            double* x, int accumulate, hipStream_t st) {
+  const size_t shm = sizeof(double) * (g.n_pad + 64);
+  hipLaunchKernelGGL(getrs_vec_kernel<T>, dim3(nbox), dim3(256), shm, st, g, nbox, LU, perm, dinv, r, x, accumulate);
+  return hipGetLastError();
+}
+template hipError_t launch_getrs_vec<float>(const Geom&, int, const float*, const int*, const float*, const double*,
+                                            double*, int, hipStream_t);
+template hipError_t launch_getrs_vec<double>(const Geom&, int, const double*, const int*, const double*,
+                                             const double*, double*, int, hipStream_t);
+
+// Outward normal derivative at the face nodes, A_bi u_i + A_bb u_b: the face rows of
+// the interface equations (eq. Aentries).  One thread per line and box; both ends.
+__global__ void flux_kernel(Geom g, int nbox, const double* u_all, const double* ub_all, double* flux_all) {
+  const int box = blockIdx.y;
+  const int m = g.m, mm = m * m, p = g.p;
+  const int line = blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= 3 * mm) return;
+  const int axis = line / mm, q = line % mm;
+  const int t0 = q % m, t1 = q / m;
+  int base, stride;
+  if (axis == 0) { base = m * t0 + mm * t1; stride = 1; }
+  else if (axis == 1) { base = t0 + mm * t1; stride = m; }
+  else { base = t0 + m * t1; stride = mm; }
+  const double* u = u_all + (size_t)box * g.n;
+  const double* ub = ub_all + (size_t)box * g.nb;
+  const double* D0 = g.D;                        // D[0][.]
+  const double* D1 = g.D + (size_t)(p - 1) * p;  // D[p-1][.]
+  const double um = ub[(2 * axis) * mm + q], up = ub[(2 * axis + 1) * mm + q];
+  double dm = D0[0] * um + D0[p - 1] * up, dp = D1[0] * um + D1[p - 1] * up;
+  for (int l = 0; l < m; l++) {
+    const double v = u[base + l * stride];
+    dm += D0[l + 1] * v;
+    dp += D1[l + 1] * v;
+  }
+  const double s1 = g.s1[axis];
+  double* flux = flux_all + (size_t)box * g.nb;
+  flux[(2 * axis) * mm + q] = -s1 * dm;
+  flux[(2 * axis + 1) * mm + q] = s1 * dp;
+}
+
+hipError_t launch_flux(const Geom& g, int nbox, const double* u, const double* ub, double* flux, hipStream_t st) {
+  const int lines = 3 * g.m * g.m;
+  hipLaunchKernelGGL(flux_kernel, dim3((lines + 255) / 256, nbox), dim3(256), 0, st, g, nbox, u, ub, flux);
+  return hipGetLastError();
+}
+
 // y_b = -A_ib^T z: face node (a, q) collects +(2/h_a)^2 D2[c+1][e] z over its line.
 __global__ void adjoint_yb_kernel(Geom g, int nbox, const double* z, double* yb) {
   const int box = blockIdx.y;

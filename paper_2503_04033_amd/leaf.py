@@ -155,6 +155,22 @@ class LeafPlan:
                                             _ptr(u_i, torch.float64, nbox * i.n_i, "u_i"), _stream()),
               "hps_leaf_reconstruct")
 
+    def hps_leaf_interior_solve(self, nbox: int, LU, perm, dinv, b, f, u_b, u_i, steps: int, ws):
+        i = self.info
+        check(self.lib.hps_leaf_interior_solve(
+            self.handle, nbox, _ptr(LU, self.elem, nbox * i.n_pad * i.n_pad, "LU"),
+            _ptr(perm, torch.int32, nbox * i.n_pad, "perm"),
+            _ptr(dinv, self.elem, nbox * i.dinv_bytes // i.elem_bytes, "dinv"),
+            _ptr(b, torch.float64, nbox * i.n_i, "b"), _ptr(f, torch.float64, nbox * i.n_i, "f"),
+            _ptr(u_b, torch.float64, nbox * i.n_b, "u_b"), _ptr(u_i, torch.float64, nbox * i.n_i, "u_i"),
+            int(steps), _ptr(ws, torch.uint8, nbox * i.ws_bytes, "ws"), _stream()), "hps_leaf_interior_solve")
+
+    def hps_leaf_flux(self, nbox: int, u_i, u_b, flux):
+        i = self.info
+        check(self.lib.hps_leaf_flux(self.handle, nbox, _ptr(u_i, torch.float64, nbox * i.n_i, "u_i"),
+                                     _ptr(u_b, torch.float64, nbox * i.n_b, "u_b"),
+                                     _ptr(flux, torch.float64, nbox * i.n_b, "flux"), _stream()), "hps_leaf_flux")
+
     def hps_leaf_adjoint_solve(self, nbox: int, LU, perm, dinv, b, w_i, lam_b, z, y_b, ws):
         i = self.info
         check(self.lib.hps_leaf_adjoint_solve(

@@ -10,6 +10,15 @@ GPU (hps_leaf_reconstruct, a5).  X (the interior solution operator and load
 response) is kept in HBM per box when `keep_X` is set; otherwise the chunk is
 recomputed in the solve stage, as the paper does for large problems.
 
+Outer refinement of the solve stage (`refine` rounds; default 1 for FP32_IR,
+0 for FP64): the interface system amplifies the rounding left in the DtN maps
+(FP32_IR maps agree with FP64 to ~1e-13, and at kappa h ~ 10 the amplification
+reaches ~5e5).  Each round recomputes every interior from the box factors in FP64
+(hps_leaf_interior_solve), takes the flux mismatch on the interfaces as the exact
+residual of T_FF u_F = rhs (hps_leaf_flux), and corrects u_F with the existing
+interface factorization; each round shrinks the error by that amplification times
+the maps' relative error.  The final interiors come from the factors as well.
+
 FP32_IR plans: a box whose refinement ends above ir_tol (ir_iters < 0) is
 factored and solved again with an FP64 plan before the interface matrix is
 reduced; its ir_iters stays negative and its id is listed in
@@ -43,6 +52,7 @@ class BuildResult:
     ir_iters: torch.Tensor
     berr: torch.Tensor
     X: Optional[torch.Tensor] = None  # [nbox * n_pad * ldx] when kept
+    factors: Optional[dict] = None    # LU, perm, dinv of every box when kept
     extra: dict = field(default_factory=dict)
 
 
@@ -50,7 +60,8 @@ class TwoLevelSolver:
     """Solve -Lap u - kappa^2 b u = f on a box grid with Dirichlet data g."""
 
     def __init__(self, nboxes, lo, hi, p: int, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
-                 ir_tol: float = 1e-11, chunk: Optional[int] = None, keep_X: bool = True, device="cuda"):
+                 ir_tol: float = 1e-11, chunk: Optional[int] = None, keep_X: bool = True, device="cuda",
+                 refine: Optional[int] = None, refine_steps: int = 2):
         self.nboxes = tuple(int(v) for v in nboxes)
         self.nbox = int(np.prod(self.nboxes))
         self.lo = tuple(float(v) for v in lo)
@@ -63,6 +74,9 @@ class TwoLevelSolver:
         self.layout = itf.build_layout(self.nboxes, self.info.m)
         self.chunk = int(chunk) if chunk else self.nbox
         self.keep_X = keep_X
+        self.refine = (1 if precision == "fp32_ir" else 0) if refine is None else int(refine)
+        self.refine_steps = int(refine_steps)
+        self.keep_factors = keep_X and self.refine > 0
         self.precision = precision
         self._plan64 = None
         self.origins = torch.tensor(_box_origins(self.nboxes, self.lo, self.h), device=self.device)
@@ -105,15 +119,26 @@ class TwoLevelSolver:
         C = min(self.chunk, nbox)
         bufs = plan.alloc(C, self.device)
         xs = i.n_pad * i.ldx
+        a_el, d_el = i.a_bytes // i.elem_bytes, i.dinv_bytes // i.elem_bytes
+        factors = None
+        if self.keep_factors:
+            factors = {"LU": torch.empty(nbox * a_el, dtype=plan.elem, device=self.device),
+                       "perm": torch.empty(nbox * i.n_pad, dtype=torch.int32, device=self.device),
+                       "dinv": torch.empty(nbox * d_el, dtype=plan.elem, device=self.device)}
         for c0 in range(0, nbox, C):
             nb = min(C, nbox - c0)
             sl = slice(c0, c0 + nb)
             bb = b[sl].contiguous()
             ff = f[sl].contiguous() if f is not None else None
             X = X_all[c0 * xs:(c0 + nb) * xs] if X_all is not None else bufs["X"]
-            plan.hps_leaf_operators(nb, bb, bufs["A"], bufs["anorm"])
-            plan.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], info[sl])
-            plan.hps_leaf_dtn(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
+            A, perm, dinv = bufs["A"], bufs["perm"], bufs["dinv"]
+            if factors is not None:
+                A = factors["LU"][c0 * a_el:(c0 + nb) * a_el]
+                perm = factors["perm"][c0 * i.n_pad:(c0 + nb) * i.n_pad]
+                dinv = factors["dinv"][c0 * d_el:(c0 + nb) * d_el]
+            plan.hps_leaf_operators(nb, bb, A, bufs["anorm"])
+            plan.hps_leaf_factor(nb, A, perm, dinv, info[sl])
+            plan.hps_leaf_dtn(nb, A, perm, dinv, bb, bufs["anorm"], ff,
                               g_dir[sl].contiguous(), self.slot_map[sl].contiguous(), T_vals, g_loads[sl], X,
                               iters[sl], berr[sl], bufs["ws"])
         redo = self._unconverged(iters)
@@ -123,7 +148,7 @@ class TwoLevelSolver:
         if pairs.shape[0]:
             hps_interface_reduce(pairs, mm * mm, T_vals)
         return BuildResult(T_vals=T_vals, g_loads=g_loads, info=info, ir_iters=iters, berr=berr, X=X_all,
-                           extra={"fp64_fallback": redo})
+                           factors=factors, extra={"fp64_fallback": redo})
 
     # ---- boxes whose FP64 refinement did not converge ----------------------------
     def _unconverged(self, iters: torch.Tensor, offset: int = 0) -> list:
@@ -175,8 +200,22 @@ class TwoLevelSolver:
             isolver = itf.InterfaceSolver(self.layout, br.T_vals.cpu().numpy())
         rhs = itf.interface_rhs(self.layout, br.g_loads.cpu().numpy())
         u_face = isolver.solve(rhs)
-        ub = itf.box_face_values(self.layout, u_face, g_dir.cpu().numpy())
+        gd = g_dir.cpu().numpy()
+        ub = itf.box_face_values(self.layout, u_face, gd)
         ub_d = torch.tensor(ub, device=self.device)
+        self.refine_history = []
+        if self.refine > 0 and u_face.size:
+            if b is None:
+                raise ValueError("the outer refinement needs b (and f) again")
+            for _ in range(self.refine):
+                _, flux = self._interiors(br, ub_d, b, f, want_flux=True)
+                du = isolver.solve(itf.interface_rhs(self.layout, -flux.cpu().numpy()))
+                self.refine_history.append(float(np.linalg.norm(du) / max(np.linalg.norm(u_face), 1e-300)))
+                u_face = u_face + du
+                ub = itf.box_face_values(self.layout, u_face, gd)
+                ub_d = torch.tensor(ub, device=self.device)
+            ui, _ = self._interiors(br, ub_d, b, f, want_flux=False)
+            return u_face, ub, ui, isolver
         ui = torch.empty(self.nbox, self.info.n_i, dtype=torch.float64, device=self.device)
         if br.X is not None:
             self.plan.hps_leaf_reconstruct(self.nbox, br.X, ub_d, ui)
@@ -206,9 +245,38 @@ class TwoLevelSolver:
             plan.hps_leaf_reconstruct(nb, bufs["X"], ub_d[sl].contiguous(), ui[sl])
         return u_face, ub, ui, isolver
 
+    def _interiors(self, br: BuildResult, ub_d: torch.Tensor, b, f, want_flux: bool):
+        """u_i = A_ii^{-1} (f_i - A_ib u_b) of every box from its factors, refined in FP64
+        (hps_leaf_interior_solve), and optionally the outward face fluxes (hps_leaf_flux).
+        Factors come from the build when kept, else each chunk is factored again."""
+        i, plan, nbox = self.info, self.plan, self.nbox
+        ui = torch.empty(nbox, i.n_i, dtype=torch.float64, device=self.device)
+        flux = torch.empty(nbox, i.n_b, dtype=torch.float64, device=self.device) if want_flux else None
+        C = min(self.chunk, nbox)
+        bufs = plan.alloc(C, self.device)
+        a_el, d_el = i.a_bytes // i.elem_bytes, i.dinv_bytes // i.elem_bytes
+        for c0 in range(0, nbox, C):
+            nb = min(C, nbox - c0)
+            sl = slice(c0, c0 + nb)
+            bb = b[sl].contiguous()
+            ff = f[sl].contiguous() if f is not None else None
+            if br.factors is not None:
+                A = br.factors["LU"][c0 * a_el:(c0 + nb) * a_el]
+                perm = br.factors["perm"][c0 * i.n_pad:(c0 + nb) * i.n_pad]
+                dinv = br.factors["dinv"][c0 * d_el:(c0 + nb) * d_el]
+            else:
+                A, perm, dinv = bufs["A"], bufs["perm"], bufs["dinv"]
+                plan.hps_leaf_operators(nb, bb, A, bufs["anorm"])
+                plan.hps_leaf_factor(nb, A, perm, dinv, bufs["info"])
+            ubs = ub_d[sl].contiguous()
+            plan.hps_leaf_interior_solve(nb, A, perm, dinv, bb, ff, ubs, ui[sl], self.refine_steps, bufs["ws"])
+            if want_flux:
+                plan.hps_leaf_flux(nb, ui[sl], ubs, flux[sl])
+        return ui, flux
+
     def solve_problem(self, prob):
         bv, fv, gv, xi, xb = self.sample(prob.b, prob.f, prob.g)
         br = self.build(bv, fv, gv)
         u_face, ub, ui, isolver = self.solve(br, gv, b=bv, f=fv)
         return {"build": br, "u_face": u_face, "u_b": ub, "u_i": ui, "xi": xi, "xb": xb, "b": bv, "f": fv,
-                "g_dir": gv, "isolver": isolver}
+                "g_dir": gv, "isolver": isolver, "refine_history": list(self.refine_history)}
