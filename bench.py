@@ -33,7 +33,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_gemm_16x16x16_p16_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_fwd_16x16x16_p16_hbm_traffic.md")
 KERNEL_SOURCES = ("paper_2503_04033_amd/csrc/common.h", "paper_2503_04033_amd/csrc/lu.hip")
 
 
@@ -255,12 +255,11 @@ def main():
     # The library records the flops of every box a launch covers, but in the correction passes
     # boxes that have already converged exit at once: count only the passes that ran.
     launched_passes = 1 + a.ir_max_iter
-    for k in ("solve_gemm", "solve_leaf"):
+    for k in ("solve_fwd", "solve_bwd"):
         fams[k]["flops"] *= passes / launched_passes
-    KNAMES = {"solve_gemm": "gemm_op_kernel<float, false>",
-              "lu_gemm": "gemm_op_kernel<float, true>",
-              "lu_panel": "lu_panel_kernel<float> (pivoted panel)",
-              "residual": "residual_kernel (FP64 refinement residual)"}
+    KNAMES = {"solve_fwd": "trsm_row_kernel<float, false>", "solve_bwd": "trsm_row_kernel<float, true>",
+              "lu_gemm": "gemm_op_kernel<float, true>", "lu_panel": "lu_panel_kernel<float, 6, 8, 64>",
+              "residual": "residual_mfma_kernel<14, 2>"}
     dom = max(fams, key=lambda k: fams[k]["ms"])
     fd = fams[dom]
     achieved = fd["flops"] / (fd["ms"] / 1e3) if fd["ms"] > 0 else 0.0

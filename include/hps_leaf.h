@@ -210,7 +210,7 @@ const char* hps_status_string(hps_status s);
  * and returns, per family, launches, total milliseconds and the algorithmic
  * flops of those launches (2*M*N*K for tile GEMMs, 2*w*w*ncols for leaves, 0
  * for bandwidth kernels).  Families: 0 LU GEMM, 1 LU panel, 2 LU leaf,
- * 3 solve GEMM, 4 solve leaf, 5 residual, 6 DtN, 7 operators.  Enabling clears
+ * 3 forward solve (L), 4 backward solve (U), 5 residual, 6 DtN, 7 operators.  Enabling clears
  * the counters.  Event recording adds launch overhead; leave it off in
  * production. */
 #define HPS_PROFILE_FAMILIES 8

@@ -18,7 +18,7 @@ EXPORTS = (
     "hps_leaf_interior_solve", "hps_leaf_flux",
 )
 
-PROFILE_FAMILIES = ("lu_gemm", "lu_panel", "lu_leaf", "solve_gemm", "solve_leaf", "residual", "dtn", "operators")
+PROFILE_FAMILIES = ("lu_gemm", "lu_panel", "lu_leaf", "solve_fwd", "solve_bwd", "residual", "dtn", "operators")
 
 
 class LeafDesc(C.Structure):

@@ -15,7 +15,7 @@ struct hps_plan_s {
   int device;
   double* tables;  // device: t[p], D[p*p], D2[p*p]
   int* coords;     // device: interior node coordinates (packed)
-  std::vector<int> lu_ops, fwd_ops, bwd_ops;  // schedules (records of 8 ints)
+  std::vector<int> lu_ops;  // LU schedule (records of 8 ints)
   hps::Profiler prof;                          // optional kernel timing
   const double* t;
 };
@@ -77,19 +77,6 @@ void sched_trsm(std::vector<int>& ops, int r0, int r1, int cA, int cB) {
   sched_trsm(ops, r0, mid, cA, cB);
   ops.insert(ops.end(), {hps::kOpGemm, mid, r1, cA, cB, r0, mid, 0});
   sched_trsm(ops, mid, r1, cA, cB);
-}
-
-// Backward substitution with U: trsm_up(r0, r1): leaf if small, else trsm_up(mid, r1);
-// gemm(rows [r0, mid), cols, k [mid, r1)); trsm_up(r0, mid).
-void sched_trsm_up(std::vector<int>& ops, int r0, int r1, int cA, int cB) {
-  if (r1 - r0 <= 64) {
-    ops.insert(ops.end(), {hps::kOpLeaf, r0, r1 - r0, cA, cB, 0, 0, 0});
-    return;
-  }
-  const int mid = r0 + (int)round_up((r1 - r0) / 2, 64);
-  sched_trsm_up(ops, mid, r1, cA, cB);
-  ops.insert(ops.end(), {hps::kOpGemm, r0, mid, cA, cB, mid, r1, 0});
-  sched_trsm_up(ops, r0, mid, cA, cB);
 }
 
 void sched_lu(std::vector<int>& ops, int c0, int c1, int N) {
@@ -220,8 +207,6 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
   }
   g.coords = pl->coords;
   sched_lu(pl->lu_ops, 0, g.n_pad, g.n_pad);
-  sched_trsm(pl->fwd_ops, 0, g.n_pad, 0, g.ldx);
-  sched_trsm_up(pl->bwd_ops, 0, g.n_pad, 0, g.ldx);
   if (hps::residual_prepare(g) != hipSuccess) {
     (void)hipFree(pl->coords);
     (void)hipFree(pl->tables);
@@ -301,7 +286,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
   if (!ir) {
     double* B = static_cast<double*>(L.B);
     HPS_TRY(hps::launch_rhs<double>(g, nbox, f, B, L.maxb, st));
-    HPS_TRY(hps::getrs_run<double>(g, pl->fwd_ops, pl->bwd_ops, static_cast<const double*>(LU), perm,
+    HPS_TRY(hps::getrs_run<double>(g, static_cast<const double*>(LU), perm,
                                    static_cast<const double*>(dinv), B, X, nbox, nullptr, st, &pl->prof));
     if (ir_iters) HPS_TRY(hps::launch_fill_int(ir_iters, 0, nbox, st));
     if (berr) {
@@ -316,7 +301,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     const float* LUf = static_cast<const float*>(LU);
     const float* Dinv = static_cast<const float*>(dinv);
     HPS_TRY(hps::launch_rhs<float>(g, nbox, f, B, L.maxb, st));
-    HPS_TRY(hps::getrs_run<float>(g, pl->fwd_ops, pl->bwd_ops, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st,
+    HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st,
                                   &pl->prof));
     HPS_TRY(hps::launch_ir_add(g, nbox, L.Y32, X, 1, nullptr, st));
     HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
@@ -331,7 +316,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
       HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
                                    st));
       if (last) break;
-      HPS_TRY(hps::getrs_run<float>(g, pl->fwd_ops, pl->bwd_ops, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st,
+      HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st,
                                     &pl->prof));
       HPS_TRY(hps::launch_ir_add(g, nbox, L.Y32, X, 0, L.active, st));
     }

@@ -11,7 +11,7 @@ namespace hps {
 
 // Optional per-family kernel timing (see hps_plan_profile_enable).
 struct Profiler {
-  enum { kLuGemm = 0, kLuPanel, kLuLeaf, kSolveGemm, kSolveLeaf, kResidual, kDtn, kOperators, kFamilies };
+  enum { kLuGemm = 0, kLuPanel, kLuLeaf, kSolveFwd, kSolveBwd, kResidual, kDtn, kOperators, kFamilies };
   struct Rec {
     int fam;
     double flops;
@@ -82,9 +82,8 @@ template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
                      hipStream_t st, Profiler* prof);
 template <typename T>
-hipError_t getrs_run(const Geom& g, const std::vector<int>& fwd, const std::vector<int>& bwd, const T* F,
-                     const int* perm, const T* dinv, const T* B, T* Y, int nbox, const int* active, hipStream_t st,
-                     Profiler* prof);
+hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
+                     const int* active, hipStream_t st, Profiler* prof);
 
 // leafops.hip
 hipError_t launch_nodes(const Geom& g, const double* t, const double* h, int nbox, const double* origin, double* xi,

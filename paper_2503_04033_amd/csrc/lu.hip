@@ -456,20 +456,88 @@ __global__ __launch_bounds__(256) void leaf_op_kernel(Geom g, const int* perm_al
 }
 
 // Y[box][i][:] = B[box][perm[i]][:]
-template <typename T>
-__global__ void gather_rows_kernel(Geom g, const int* perm_all, const T* B_all, T* Y_all, int nbox,
-                                   const int* active) {
-  const int box = blockIdx.y;
+// One block row of the solves, left-looking: Z = R_j - F[j rows][k range] Y[k range]
+// over the finished rows, then Y_j = Inv_j Z with the stored inverse of the diagonal
+// block.  Forward (L, unit diagonal): R_j = B[perm[s + i]], k in [0, s).  Backward (U):
+// R_j = Y_j itself, k in [s + w, N).  One 64 x 64 output tile per workgroup: the K loop
+// is the tile GEMM, the 64 x 64 x 64 inverse product reads Z from LDS.
+constexpr int kTrsmSeg = 512;
+
+template <typename T, bool UPPER>
+__global__ __launch_bounds__(256, 4) void trsm_row_kernel(Geom g, const T* F_all, const int* perm_all,
+                                                          const T* dinv_all, const T* B_all, T* Y_all, int s, int w,
+                                                          int nbox, int ntn, const int* active) {
+  typedef typename GemmCfg<T>::G G;
+  static_assert(G::MT == 64 && G::NT == 64, "one 64 x 64 tile per workgroup");
+  static_assert(G::SMEM >= 64 * kLeafLd, "Z must fit the GEMM staging buffer");
+  constexpr int WRT = 2, WCT = 2;
+  __shared__ T smem[G::SMEM];
+  int box, tn;
+  if (!map_box_tile(nbox, ntn, box, tn)) return;
   if (active && active[box] == 0) return;
-  const int N = g.n_pad, ldx = g.ldx;
+  const int N = g.n_pad, ld = g.ldx;
+  const T* F = F_all + (size_t)box * N * N;
   const int* perm = perm_all + (size_t)box * N;
-  const T* B = B_all + (size_t)box * N * ldx;
-  T* Y = Y_all + (size_t)box * N * ldx;
-  for (int r = blockIdx.x; r < N; r += gridDim.x) {
-    const T* src = B + (size_t)perm[r] * ldx;
-    for (int c = threadIdx.x; c < ldx; c += blockDim.x) Y[(size_t)r * ldx + c] = src[c];
+  const size_t xs = (size_t)N * ld;
+  T* Y = Y_all + (size_t)box * xs;
+  const T* B = B_all + (size_t)box * xs;
+  const int nt = tn * 64;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = wave % 2, wn = wave / 2;
+  typename G::acc_t acc[WRT][WCT];
+#pragma unroll
+  for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+    for (int ct = 0; ct < WCT; ct++) acc[rt][ct] = Mfma<T>::zero();
+  auto arow = [&](int r) -> const T* { return r < w ? F + (size_t)perm[s + r] * N : nullptr; };
+  auto brow = [&](int k) -> const T* { return Y + (size_t)k * ld + nt; };
+  // acc = -F Y; in FP32 summed over K segments of kTrsmSeg so that no accumulator adds
+  // more than kTrsmSeg products in sequence (K reaches n_pad)
+  const int k0 = UPPER ? s + w : 0, k1 = UPPER ? N : s;
+  if constexpr (sizeof(T) == 8) G::run(acc, arow, brow, 64, k0, k1, smem);
+  else for (int ks = k0; ks < k1; ks += kTrsmSeg) {
+    typename G::acc_t part[WRT][WCT];
+#pragma unroll
+    for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < WCT; ct++) part[rt][ct] = Mfma<T>::zero();
+    G::run(part, arow, brow, 64, ks, (k1 - ks) < kTrsmSeg ? k1 : ks + kTrsmSeg, smem);
+#pragma unroll
+    for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < WCT; ct++) acc[rt][ct] += part[rt][ct];
   }
+  __syncthreads();  // every wave is done with the staging buffer
+  T* zs = smem;     // Z [64][kLeafLd]
+#pragma unroll
+  for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int r = (wm * WRT + rt) * 16 + Mfma<T>::row(lane, i);
+      const T* rr = r < w ? (UPPER ? Y + (size_t)(s + r) * ld : B + (size_t)perm[s + r] * ld) + nt : nullptr;
+#pragma unroll
+      for (int ct = 0; ct < WCT; ct++) {
+        const int c = (wn * WCT + ct) * 16 + (lane & 15);
+        zs[r * kLeafLd + c] = rr ? rr[c] + acc[rt][ct][i] : T(0);
+      }
+    }
+  __syncthreads();
+  const T* Inv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(s / kPanel) * 2 * 64 * 64 +
+                 (UPPER ? 64 * 64 : 0);
+  typename Mfma<T>::acc out[1][4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++) out[0][ct] = Mfma<T>::zero();
+  auto irow = [&](int) -> const T* { return Inv + (wave * 16 + (lane & 15)) * 64; };
+  wg_gemm_lds_add<T, 1, 4>(out, irow, zs, kLeafLd, w, 0);
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int r = wave * 16 + Mfma<T>::row(lane, i);
+      if (r < w) Y[(size_t)(s + r) * ld + nt + ct * 16 + (lane & 15)] = out[0][ct][i];
+    }
 }
+
 
 // ---------------------------------------------------------------------------
 // host-side sequencing
@@ -558,44 +626,35 @@ hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm
 // X = A^{-1} B for every active box: Y = P B (gather), forward ops with L, backward
 // ops with U, in place in Y (B and Y must not alias).
 template <typename T>
-hipError_t getrs_run(const Geom& g, const std::vector<int>& fwd, const std::vector<int>& bwd, const T* F,
-                     const int* perm, const T* dinv, const T* B, T* Y, int nbox, const int* active, hipStream_t st,
-                     Profiler* prof) {
-  const size_t xs = (size_t)g.n_pad * g.ldx;
-  hipLaunchKernelGGL((gather_rows_kernel<T>), dim3(g.n_pad < 512 ? g.n_pad : 512, nbox), dim3(256), 0, st, g, perm, B,
-                     Y, nbox, active);
-  hipError_t e = hipGetLastError();
-  for (size_t q = 0; q + 8 <= fwd.size() && e == hipSuccess; q += 8) {
-    const int* op = fwd.data() + q;
-    if (op[0] == kOpLeaf) {
-      ProfScope ps(prof, Profiler::kSolveLeaf, leaf_flops(op, nbox), st);
-      e = launch_leaf<T, false, false>(g, perm, dinv, Y, g.ldx, xs, op, nbox, active, st);
-    } else {
-      ProfScope ps(prof, Profiler::kSolveGemm, gemm_flops(op, nbox), st);
-      e = launch_gemm<T, false>(g, F, perm, Y, g.ldx, xs, op, nbox, active, st);
-    }
+hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
+                     const int* active, hipStream_t st, Profiler* prof) {
+  const int N = g.n_pad, ntn = g.ldx / 64;
+  const double nrhs = g.nb + 1;
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < N && e == hipSuccess; s += kPanel) {  // L Y = P B, block rows top down
+    const int w = (N - s) < kPanel ? (N - s) : kPanel;
+    ProfScope ps(prof, Profiler::kSolveFwd, (2.0 * w * s + (double)w * w) * nrhs * nbox, st);
+    hipLaunchKernelGGL((trsm_row_kernel<T, false>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm, dinv, B,
+                       Y, s, w, nbox, ntn, active);
+    e = hipGetLastError();
   }
-  for (size_t q = 0; q + 8 <= bwd.size() && e == hipSuccess; q += 8) {
-    const int* op = bwd.data() + q;
-    if (op[0] == kOpLeaf) {
-      ProfScope ps(prof, Profiler::kSolveLeaf, leaf_flops(op, nbox), st);
-      e = launch_leaf<T, true, false>(g, perm, dinv, Y, g.ldx, xs, op, nbox, active, st);
-    } else {
-      ProfScope ps(prof, Profiler::kSolveGemm, gemm_flops(op, nbox), st);
-      e = launch_gemm<T, false>(g, F, perm, Y, g.ldx, xs, op, nbox, active, st);
-    }
+  for (int s = (N - 1) / kPanel * kPanel; s >= 0 && e == hipSuccess; s -= kPanel) {  // U X = Y, bottom up
+    const int w = (N - s) < kPanel ? (N - s) : kPanel;
+    ProfScope ps(prof, Profiler::kSolveBwd, (2.0 * w * (N - s - w) + (double)w * w) * nrhs * nbox, st);
+    hipLaunchKernelGGL((trsm_row_kernel<T, true>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm, dinv, Y,
+                       Y, s, w, nbox, ntn, active);
+    e = hipGetLastError();
   }
   return e;
 }
-
 template hipError_t getrf_run<float>(const Geom&, const std::vector<int>&, float*, int*, float*, int*, int, hipStream_t,
                                      Profiler*);
 template hipError_t getrf_run<double>(const Geom&, const std::vector<int>&, double*, int*, double*, int*, int,
                                       hipStream_t, Profiler*);
-template hipError_t getrs_run<float>(const Geom&, const std::vector<int>&, const std::vector<int>&, const float*,
+template hipError_t getrs_run<float>(const Geom&, const float*,
                                      const int*, const float*, const float*, float*, int, const int*, hipStream_t,
                                      Profiler*);
-template hipError_t getrs_run<double>(const Geom&, const std::vector<int>&, const std::vector<int>&, const double*,
+template hipError_t getrs_run<double>(const Geom&, const double*,
                                       const int*, const double*, const double*, double*, int, const int*,
                                       hipStream_t, Profiler*);
 
