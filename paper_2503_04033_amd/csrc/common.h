@@ -161,6 +161,7 @@ __device__ inline void wg_gemm_sub(typename Mfma<T>::acc (&acc)[RT][CT], ARow ar
 // ---------------------------------------------------------------------------
 template <typename T, int WRT, int WCT, int GM, int GN, int KC, int PF = 1>
 struct TileGemm {
+  static constexpr int KCHUNK = KC;
   static constexpr int MT = GM * WRT * 16;
   static constexpr int NT = GN * WCT * 16;
   static constexpr int NTHR = GM * GN * 64;
@@ -176,8 +177,15 @@ struct TileGemm {
   typedef typename Mfma<T>::acc acc_t;
   typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
 
-  template <typename ARow, typename BRow>
-  __device__ static void run(acc_t (&acc)[WRT][WCT], ARow arow, BRow brow, int bcols, int k0, int k1, T* smem) {
+  struct NoHook {
+    __device__ void operator()(int) const {}
+  };
+
+  // after_chunk(c) runs after the MFMAs of chunk c (every wave, uniform): a caller can
+  // fold acc into a second accumulator there without restarting the pipeline.
+  template <typename ARow, typename BRow, typename Hook = NoHook>
+  __device__ static void run(acc_t (&acc)[WRT][WCT], ARow arow, BRow brow, int bcols, int k0, int k1, T* smem,
+                             Hook after_chunk = Hook()) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -268,6 +276,7 @@ struct TileGemm {
         const int cl = c + PF < nchunk ? c + PF : nchunk - 1;
         gload(k0 + cl * KC, j);  // set j held chunk c, already in LDS
         compute(cur);
+        after_chunk(c);
         if (c + 1 < nchunk) lstore(nxt, (j + 1) % PF);
       }
     }
@@ -279,6 +288,7 @@ struct TileGemm {
         T* nxt = smem + ((c + 1) & 1) * (ABUF + BBUF);
         __syncthreads();
         compute(cur);
+        after_chunk(c);
         if (c + 1 < nchunk) lstore(nxt, (j + 1) % PF);
       }
     }

@@ -491,21 +491,31 @@ __global__ __launch_bounds__(256, 4) void trsm_row_kernel(Geom g, const T* F_all
     for (int ct = 0; ct < WCT; ct++) acc[rt][ct] = Mfma<T>::zero();
   auto arow = [&](int r) -> const T* { return r < w ? F + (size_t)perm[s + r] * N : nullptr; };
   auto brow = [&](int k) -> const T* { return Y + (size_t)k * ld + nt; };
-  // acc = -F Y; in FP32 summed over K segments of kTrsmSeg so that no accumulator adds
-  // more than kTrsmSeg products in sequence (K reaches n_pad)
+  // acc = -F Y.  In FP32 the running sum `part` is folded into acc every kTrsmSeg values
+  // of k, so that no accumulator adds more than kTrsmSeg products in sequence (K reaches
+  // n_pad); the fold runs inside the K loop and keeps its pipeline going.
   const int k0 = UPPER ? s + w : 0, k1 = UPPER ? N : s;
-  if constexpr (sizeof(T) == 8) G::run(acc, arow, brow, 64, k0, k1, smem);
-  else for (int ks = k0; ks < k1; ks += kTrsmSeg) {
+  if constexpr (sizeof(T) == 8) {
+    G::run(acc, arow, brow, 64, k0, k1, smem);
+  } else {
     typename G::acc_t part[WRT][WCT];
 #pragma unroll
     for (int rt = 0; rt < WRT; rt++)
 #pragma unroll
       for (int ct = 0; ct < WCT; ct++) part[rt][ct] = Mfma<T>::zero();
-    G::run(part, arow, brow, 64, ks, (k1 - ks) < kTrsmSeg ? k1 : ks + kTrsmSeg, smem);
+    const int nchunk = (k1 - k0) / G::KCHUNK;
+    auto fold = [&](int c) {
+      if ((c + 1) % (kTrsmSeg / G::KCHUNK) == 0 || c + 1 == nchunk) {
 #pragma unroll
-    for (int rt = 0; rt < WRT; rt++)
+        for (int rt = 0; rt < WRT; rt++)
 #pragma unroll
-      for (int ct = 0; ct < WCT; ct++) acc[rt][ct] += part[rt][ct];
+          for (int ct = 0; ct < WCT; ct++) {
+            acc[rt][ct] += part[rt][ct];
+            part[rt][ct] = Mfma<T>::zero();
+          }
+      }
+    };
+    G::run(part, arow, brow, 64, k0, k1, smem, fold);
   }
   __syncthreads();  // every wave is done with the staging buffer
   T* zs = smem;     // Z [64][kLeafLd]
