@@ -260,6 +260,11 @@ def main():
     KNAMES = {"solve_fwd": "trsm_row_kernel<float, false>", "solve_bwd": "trsm_row_kernel<float, true>",
               "lu_gemm": "gemm_op_kernel<float, true>", "lu_panel": "lu_panel_kernel<float, 6, 8, 64>",
               "residual": "residual_mfma_kernel<14, 2>"}
+    # the LU/TRSM phase: device time of the factorization and solve kernels (events around
+    # each launch) against the algorithmic LU and solve flops of the step
+    ph_ms = sum(fams[k]["ms"] for k in ("lu_gemm", "lu_panel", "lu_leaf", "solve_fwd", "solve_bwd")) / a.steps
+    lu_trsm = {"ms_per_step": round(ph_ms, 3), "tflops": round(tot_flops / (ph_ms / 1e3) / 1e12, 2),
+               "frac_fp32_mfma_peak": round(tot_flops / (ph_ms / 1e3) / PEAK_FP32_MFMA, 4)}
     dom = max(fams, key=lambda k: fams[k]["ms"])
     fd = fams[dom]
     achieved = fd["flops"] / (fd["ms"] / 1e3) if fd["ms"] > 0 else 0.0
@@ -273,6 +278,7 @@ def main():
                    "ir_tol": a.ir_tol, "ir_max_iter": a.ir_max_iter},
         "mfma_frac_lu_solve": round(tot_flops / (ms / 1e3) / PEAK_FP32_MFMA, 4),
         "tflops_lu_solve": round(tot_flops / (ms / 1e3) / 1e12, 2),
+        "lu_trsm_phase": lu_trsm,
         "ir": {"iters_hist": {int(k): int(v) for k, v in zip(*np.unique(iters, return_counts=True))},
                "berr_max": float(berr.max()), "lu_info_nonzero": info_bad},
         "phase_ms_per_step": {k: round(v["ms_total"] / a.steps, 3) for k, v in phases.items()},

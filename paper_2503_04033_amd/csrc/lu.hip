@@ -394,7 +394,14 @@ __global__ __launch_bounds__(256, 4) void gemm_op_kernel(Geom g, const T* F_all,
     const int pos = mt + r;
     return pos < m1 ? F + (size_t)perm[pos] * N : nullptr;
   };
-  auto brow = [&](int k) -> const T* { return X + (size_t)(PERM ? perm[k] : k) * ld + nt; };
+  // B rows through perm: the K range of perm is staged in LDS once, so that no global
+  // load of a row index sits in front of each row load of the K loop
+  extern __shared__ int kperm[];  // [k1 - k0] when PERM
+  if (PERM) {
+    for (int i = threadIdx.x; i < k1 - k0; i += blockDim.x) kperm[i] = perm[k0 + i];
+    __syncthreads();
+  }
+  auto brow = [&](int k) -> const T* { return X + (size_t)(PERM ? kperm[k - k0] : k) * ld + nt; };
   const int bcols = (n1 - nt) < G::NT ? (n1 - nt) : G::NT;
   G::run(acc, arow, brow, bcols, k0, k1, smem);
 #pragma unroll
@@ -566,8 +573,9 @@ static hipError_t launch_gemm(const Geom& g, const T* F, const int* perm, T* X, 
   typedef typename GemmCfg<T>::G G;
   const int m0 = op[1], m1 = op[2], n0 = op[3], n1 = op[4], k0 = op[5], k1 = op[6];
   const int ntm = (m1 - m0 + G::MT - 1) / G::MT, ntn = (n1 - n0 + G::NT - 1) / G::NT;
-  hipLaunchKernelGGL((gemm_op_kernel<T, PERM>), dim3(grid_for(nbox, ntm * ntn)), dim3(256), 0, st, g, F, perm, X, ld,
-                     xstride, m0, m1, n0, n1, k0, k1, nbox, ntm, ntn, active);
+  const size_t shm = PERM ? sizeof(int) * (size_t)(k1 - k0) : 0;
+  hipLaunchKernelGGL((gemm_op_kernel<T, PERM>), dim3(grid_for(nbox, ntm * ntn)), dim3(256), shm, st, g, F, perm, X,
+                     ld, xstride, m0, m1, n0, n1, k0, k1, nbox, ntm, ntn, active);
   return hipGetLastError();
 }
 
