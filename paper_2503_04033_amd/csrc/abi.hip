@@ -301,9 +301,8 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     const float* LUf = static_cast<const float*>(LU);
     const float* Dinv = static_cast<const float*>(dinv);
     HPS_TRY(hps::launch_rhs<float>(g, nbox, f, B, L.maxb, st));
-    HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st,
-                                  &pl->prof));
-    HPS_TRY(hps::launch_ir_add(g, nbox, L.Y32, X, 1, nullptr, st));
+    // the first solve also writes X = Y in FP64; each correction below adds into X
+    HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st, &pl->prof, X, 1));
     HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
     const int kmax = pl->desc.ir_max_iter;
     const double tol = pl->desc.ir_tol;
@@ -316,9 +315,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
       HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
                                    st));
       if (last) break;
-      HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st,
-                                    &pl->prof));
-      HPS_TRY(hps::launch_ir_add(g, nbox, L.Y32, X, 0, L.active, st));
+      HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st, &pl->prof, X, 2));
     }
   }
   hps::ProfScope ps(&pl->prof, hps::Profiler::kDtn, 0.0, st);

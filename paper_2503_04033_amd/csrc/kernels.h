@@ -81,9 +81,11 @@ struct ProfScope {
 template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
                      hipStream_t st, Profiler* prof);
+// xmode 1: X = Y, xmode 2: X += Y (FP64 X: the refinement's solution and corrections),
+// written by the backward block-row launches as they finish each tile
 template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
-                     const int* active, hipStream_t st, Profiler* prof);
+                     const int* active, hipStream_t st, Profiler* prof, double* X = nullptr, int xmode = 0);
 
 // leafops.hip
 hipError_t launch_nodes(const Geom& g, const double* t, const double* h, int nbox, const double* origin, double* xi,
@@ -98,8 +100,6 @@ hipError_t launch_residual(const Geom& g, int nbox, const double* b, const doubl
 hipError_t launch_ir_check(int nbox, int it, int last, double tol, const double* anorm, const double* maxb,
                            const double* maxr, const double* maxx, int* active, int* iters, double* berr,
                            hipStream_t st);
-hipError_t launch_ir_add(const Geom& g, int nbox, const float* Y, double* X, int first, const int* active,
-                         hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_fill_int(int* p, int value, size_t count, hipStream_t st);
 hipError_t launch_dtn(const Geom& g, int nbox, const double* X, const double* gdir, const int* slot_map,

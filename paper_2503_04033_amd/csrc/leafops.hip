@@ -383,32 +383,25 @@ __global__ __launch_bounds__(kRmThreads) void residual_mfma_kernel(Geom g, int n
     td[0][e] = g.s2[0] * d;
     td[1][e] = g.s2[1] * d;
   }
-  // staging task t of a slab: t < CB m^2 is X[row t / CB][c0 + t % CB], then b, then f,
-  // stored at tile [ii][jj] of their plane; other tasks reread one element and discard it
-  const double* fp[NTK];
-  int inc[NTK], loff[NTK];
+  // Staging task t of a slab: t < CB m^2 is X[row t / CB][c0 + t % CB], then b, then f,
+  // stored at tile [ii][jj] of their plane; other tasks reread X[0] and discard it.  Only
+  // the element offset is kept per task; kind, slab address and LDS slot are recomputed
+  // (cheap integer work) to leave the registers to the accumulators.
+  auto task_kind = [&](int s) {
+    const int t = threadIdx.x + s * kRmThreads;
+    return t < CB * mm ? 0 : (t < (CB + 1) * mm ? 1 : ((t < (CB + 2) * mm && f) ? 2 : 3));
+  };
+  auto task_loff = [&](int s) {
+    const int t = threadIdx.x + s * kRmThreads, k = task_kind(s);
+    const int r = k == 0 ? t / CB : t - (k == 1 ? CB : CB + 1) * mm;
+    const int plane = k == 0 ? t % CB : (k == 1 ? CB : CB + 1);
+    return k == 3 ? DISCARD : plane * kRmTile + (r % m) * kRmLd + r / m;
+  };
+  int off[NTK];
 #pragma unroll
   for (int s = 0; s < NTK; s++) {
-    const int t = threadIdx.x + s * kRmThreads;
-    fp[s] = X;
-    inc[s] = 0;
-    loff[s] = DISCARD;
-    if (t < CB * mm) {
-      const int r = t / CB, c = t % CB;
-      fp[s] = X + (size_t)r * ldx + c0 + c;
-      inc[s] = mm * ldx;
-      loff[s] = c * kRmTile + (r % m) * kRmLd + r / m;
-    } else if (t < (CB + 1) * mm) {
-      const int r = t - CB * mm;
-      fp[s] = bb + r;
-      inc[s] = mm;
-      loff[s] = CB * kRmTile + (r % m) * kRmLd + r / m;
-    } else if (t < (CB + 2) * mm && f) {
-      const int r = t - (CB + 1) * mm;
-      fp[s] = fb + r;
-      inc[s] = mm;
-      loff[s] = (CB + 1) * kRmTile + (r % m) * kRmLd + r / m;
-    }
+    const int t = threadIdx.x + s * kRmThreads, k = task_kind(s);
+    off[s] = k == 0 ? (t / CB) * ldx + c0 + t % CB : (k == 1 ? t - CB * mm : (k == 2 ? t - (CB + 1) * mm : 0));
   }
   // This wave's column of [A_ib | f].  A_ib column col is nonzero on the normal line of
   // face node (la, lb); bit i of emask marks this lane's node (lr + 4i, lc) on it, whose
@@ -437,19 +430,24 @@ __global__ __launch_bounds__(kRmThreads) void residual_mfma_kernel(Geom g, int n
   const double s2a = axis >= 0 ? -g.s2[axis] : 0.0;
   const double* tes = te + side * m;
   double pf[PD][NTK];
-  auto fetch = [&](int slot) {
+  auto fetch = [&](int q, int slot) {
+    const size_t xq = (size_t)q * mm * ldx;
 #pragma unroll
     for (int s = 0; s < NTK; s++) {
-      pf[slot][s] = *fp[s];
-      fp[s] += inc[s];
+      const int k = task_kind(s);
+      const double* base = k == 0 ? X + xq : (k == 1 ? bb + q * mm : (k == 2 ? fb + q * mm : X));
+      pf[slot][s] = base[k == 3 ? 0 : off[s]];
     }
   };
   auto stash = [&](int buf, int slot) {
 #pragma unroll
-    for (int s = 0; s < NTK; s++) sm[loff[s] == DISCARD ? DISCARD : buf * BUF + loff[s]] = pf[slot][s];
+    for (int s = 0; s < NTK; s++) {
+      const int lo = task_loff(s);
+      sm[lo == DISCARD ? DISCARD : buf * BUF + lo] = pf[slot][s];
+    }
   };
 #pragma unroll
-  for (int q = 0; q < PD && q < m; q++) fetch(q);
+  for (int q = 0; q < PD && q < m; q++) fetch(q, q);
   __syncthreads();  // zero fill and tables done
   stash(0, 0);
   d4 acc[H];
@@ -461,7 +459,7 @@ __global__ __launch_bounds__(kRmThreads) void residual_mfma_kernel(Geom g, int n
   for (int q = 0; q < m; q++) {
     __builtin_amdgcn_sched_barrier(0);  // keep each slab's work (and its registers) in place
     __syncthreads();                    // slab q visible; the other buffer is free
-    if (q + PD < m) fetch(q % PD);
+    if (q + PD < m) fetch(q + PD, q % PD);
     const double* S = sm + (q & 1) * BUF;
     const double* Sc = S + wc * kRmTile;
     double bx[4];
@@ -631,23 +629,6 @@ hipError_t launch_ir_check(int nbox, int it, int last, double tol, const double*
   return hipGetLastError();
 }
 
-// X (FP64) = Y (first) or X += Y, rows < n only.
-__global__ __launch_bounds__(256) void ir_add_kernel(Geom g, int nbox, const float* Y_all, double* X_all, int first,
-                                                     const int* active) {
-  const int box = blockIdx.y;
-  if (active && active[box] == 0) return;
-  const size_t sz = (size_t)g.n_pad * g.ldx;
-  const float* Y = Y_all + box * sz;
-  double* X = X_all + box * sz;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < sz; i += (size_t)gridDim.x * blockDim.x)
-    X[i] = first ? (double)Y[i] : X[i] + (double)Y[i];
-}
-
-hipError_t launch_ir_add(const Geom& g, int nbox, const float* Y, double* X, int first, const int* active,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(ir_add_kernel, dim3(512, nbox), dim3(256), 0, st, g, nbox, Y, X, first, active);
-  return hipGetLastError();
-}
 
 // ----------------------------------------------------------------------------
 // a4: DtN rows and loads (Sec. 3.1 eq. t-block, Alg. 1; Alg. 2 load loop).

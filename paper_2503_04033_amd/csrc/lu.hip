@@ -473,7 +473,8 @@ constexpr int kTrsmSeg = 512;
 template <typename T, bool UPPER>
 __global__ __launch_bounds__(256, 4) void trsm_row_kernel(Geom g, const T* F_all, const int* perm_all,
                                                           const T* dinv_all, const T* B_all, T* Y_all, int s, int w,
-                                                          int nbox, int ntn, const int* active) {
+                                                          int nbox, int ntn, const int* active, double* X_all,
+                                                          int xmode) {
   typedef typename GemmCfg<T>::G G;
   static_assert(G::MT == 64 && G::NT == 64, "one 64 x 64 tile per workgroup");
   static_assert(G::SMEM >= 64 * kLeafLd, "Z must fit the GEMM staging buffer");
@@ -546,12 +547,19 @@ __global__ __launch_bounds__(256, 4) void trsm_row_kernel(Geom g, const T* F_all
   for (int ct = 0; ct < 4; ct++) out[0][ct] = Mfma<T>::zero();
   auto irow = [&](int) -> const T* { return Inv + (wave * 16 + (lane & 15)) * 64; };
   wg_gemm_lds_add<T, 1, 4>(out, irow, zs, kLeafLd, w, 0);
+  // the finished rows; backward launches may also write them to the FP64 X (xmode 1:
+  // X = Y, xmode 2: X += Y)
+  double* Xb = X_all ? X_all + (size_t)box * xs : nullptr;
 #pragma unroll
   for (int ct = 0; ct < 4; ct++)
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const int r = wave * 16 + Mfma<T>::row(lane, i);
-      if (r < w) Y[(size_t)(s + r) * ld + nt + ct * 16 + (lane & 15)] = out[0][ct][i];
+      if (r < w) {
+        const size_t e = (size_t)(s + r) * ld + nt + ct * 16 + (lane & 15);
+        Y[e] = out[0][ct][i];
+        if (Xb) Xb[e] = xmode == 1 ? (double)out[0][ct][i] : Xb[e] + (double)out[0][ct][i];
+      }
     }
 }
 
@@ -645,7 +653,7 @@ hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm
 // ops with U, in place in Y (B and Y must not alias).
 template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
-                     const int* active, hipStream_t st, Profiler* prof) {
+                     const int* active, hipStream_t st, Profiler* prof, double* X, int xmode) {
   const int N = g.n_pad, ntn = g.ldx / 64;
   const double nrhs = g.nb + 1;
   hipError_t e = hipSuccess;
@@ -653,14 +661,14 @@ hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, 
     const int w = (N - s) < kPanel ? (N - s) : kPanel;
     ProfScope ps(prof, Profiler::kSolveFwd, (2.0 * w * s + (double)w * w) * nrhs * nbox, st);
     hipLaunchKernelGGL((trsm_row_kernel<T, false>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm, dinv, B,
-                       Y, s, w, nbox, ntn, active);
+                       Y, s, w, nbox, ntn, active, nullptr, 0);
     e = hipGetLastError();
   }
   for (int s = (N - 1) / kPanel * kPanel; s >= 0 && e == hipSuccess; s -= kPanel) {  // U X = Y, bottom up
     const int w = (N - s) < kPanel ? (N - s) : kPanel;
     ProfScope ps(prof, Profiler::kSolveBwd, (2.0 * w * (N - s - w) + (double)w * w) * nrhs * nbox, st);
     hipLaunchKernelGGL((trsm_row_kernel<T, true>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm, dinv, Y,
-                       Y, s, w, nbox, ntn, active);
+                       Y, s, w, nbox, ntn, active, xmode ? X : nullptr, xmode);
     e = hipGetLastError();
   }
   return e;
@@ -671,9 +679,9 @@ template hipError_t getrf_run<double>(const Geom&, const std::vector<int>&, doub
                                       hipStream_t, Profiler*);
 template hipError_t getrs_run<float>(const Geom&, const float*,
                                      const int*, const float*, const float*, float*, int, const int*, hipStream_t,
-                                     Profiler*);
+                                     Profiler*, double*, int);
 template hipError_t getrs_run<double>(const Geom&, const double*,
                                       const int*, const double*, const double*, double*, int, const int*,
-                                      hipStream_t, Profiler*);
+                                      hipStream_t, Profiler*, double*, int);
 
 }  // namespace hps
