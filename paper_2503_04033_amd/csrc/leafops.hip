@@ -109,58 +109,67 @@ template <> struct Store4<double> {
   }
 };
 
+// A_ii has 3m - 2 nonzeros per row (the three D2 lines through the node; the identity
+// on the padding rows), so each workgroup first writes zero rows with 16-byte stores and,
+// after one barrier, the nonzeros of its rows.
+constexpr int kOpRows = 8;
+
 template <typename T>
 __global__ __launch_bounds__(256) void operators_kernel(Geom g, int nbox, const double* b, T* A_all, double* anorm) {
   const int box = blockIdx.y;
-  const int N = g.n_pad, n = g.n, m = g.m, p = g.p;
+  const int N = g.n_pad, n = g.n, m = g.m, mm = m * m, p = g.p;
   T* A = A_all + (size_t)box * N * N;
-  for (int r = blockIdx.x; r < N; r += gridDim.x) {
-    T* row = A + (size_t)r * N;
+  const int r0 = blockIdx.x * kOpRows;
+  const int nr = (N - r0) < kOpRows ? (N - r0) : kOpRows;
+  const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+  const int q4 = N / 4;
+  for (int e = threadIdx.x; e < nr * q4; e += blockDim.x) {
+    const int rr = e / q4, c = (e - rr * q4) * 4;
+    Store4<T>::st(A + (size_t)(r0 + rr) * N + c, zero);
+  }
+  __syncthreads();
+  const double* D2 = g.D2;
+  for (int e = threadIdx.x; e < nr * 3 * m; e += blockDim.x) {
+    const int rr = e / (3 * m), t = e - rr * 3 * m, line = t / m, q = t - line * m;
+    const int r = r0 + rr;
     if (r >= n) {
-      for (int c = 4 * threadIdx.x; c < N; c += 4 * blockDim.x) {
-        double v[4] = {0, 0, 0, 0};
-        for (int q = 0; q < 4; q++) v[q] = (c + q == r) ? 1.0 : 0.0;
-        Store4<T>::st(row + c, v);
-      }
+      if (t == 0) A[(size_t)r * N + r] = T(1);
       continue;
     }
-    const int ii = r % m, jj = (r / m) % m, kk = r / (m * m);
-    const double* D2 = g.D2;
-    const int xbase = m * jj + m * m * kk;  // x-line: columns xbase + ii'
-    const int ybase = ii + m * m * kk;      // y-line: ybase + m jj'
-    const int zbase = ii + m * jj;          // z-line: zbase + m^2 kk'
-    const double diag_b = -g.kappa2 * b[(size_t)box * n + r];
-    for (int c = 4 * threadIdx.x; c < N; c += 4 * blockDim.x) {
-      double v[4];
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const int cc = c + q;
-        double s = 0.0;
-        if (cc < n) {
-          const int dx = cc - xbase;
-          if (dx >= 0 && dx < m) s -= g.s2[0] * D2[(ii + 1) * p + dx + 1];
-          const int dy = cc - ybase;
-          if (dy >= 0 && dy < m * m && dy % m == 0) s -= g.s2[1] * D2[(jj + 1) * p + dy / m + 1];
-          const int dz = cc - zbase;
-          if (dz >= 0 && dz % (m * m) == 0) s -= g.s2[2] * D2[(kk + 1) * p + dz / (m * m) + 1];
-          if (cc == r) s += diag_b;
-        }
-        v[q] = s;
-      }
-      Store4<T>::st(row + c, v);
+    const int cd = g.coords[r];
+    const int ii = cd & 255, jj = (cd >> 8) & 255, kk = cd >> 16;
+    int col;
+    double v;
+    if (line == 0) {  // x-line, carries the whole diagonal
+      col = r - ii + q;
+      v = -g.s2[0] * D2[(ii + 1) * p + q + 1];
+      if (q == ii)
+        v += -g.s2[1] * D2[(jj + 1) * p + jj + 1] - g.s2[2] * D2[(kk + 1) * p + kk + 1] -
+             g.kappa2 * b[(size_t)box * n + r];
+    } else if (line == 1) {
+      if (q == jj) continue;
+      col = r + m * (q - jj);
+      v = -g.s2[1] * D2[(jj + 1) * p + q + 1];
+    } else {
+      if (q == kk) continue;
+      col = r + mm * (q - kk);
+      v = -g.s2[2] * D2[(kk + 1) * p + q + 1];
     }
-    if (threadIdx.x == 0) {
-      // exact |row| sum of A_ii (FP64)
-      double sum = 0.0;
-      for (int q = 0; q < m; q++) {
-        if (q != ii) sum += g.s2[0] * fabs(D2[(ii + 1) * p + q + 1]);
-        if (q != jj) sum += g.s2[1] * fabs(D2[(jj + 1) * p + q + 1]);
-        if (q != kk) sum += g.s2[2] * fabs(D2[(kk + 1) * p + q + 1]);
-      }
-      const double d = -(g.s2[0] * D2[(ii + 1) * p + ii + 1] + g.s2[1] * D2[(jj + 1) * p + jj + 1] +
-                         g.s2[2] * D2[(kk + 1) * p + kk + 1]) + diag_b;
-      atomic_max_nonneg(anorm + box, sum + fabs(d));
+    A[(size_t)r * N + col] = (T)v;
+  }
+  if (threadIdx.x < nr && r0 + threadIdx.x < n) {  // exact |row| sum of A_ii (FP64)
+    const int r = r0 + threadIdx.x;
+    const int cd = g.coords[r];
+    const int ii = cd & 255, jj = (cd >> 8) & 255, kk = cd >> 16;
+    double sum = 0.0;
+    for (int q = 0; q < m; q++) {
+      if (q != ii) sum += g.s2[0] * fabs(D2[(ii + 1) * p + q + 1]);
+      if (q != jj) sum += g.s2[1] * fabs(D2[(jj + 1) * p + q + 1]);
+      if (q != kk) sum += g.s2[2] * fabs(D2[(kk + 1) * p + q + 1]);
     }
+    const double d = -(g.s2[0] * D2[(ii + 1) * p + ii + 1] + g.s2[1] * D2[(jj + 1) * p + jj + 1] +
+                       g.s2[2] * D2[(kk + 1) * p + kk + 1]) - g.kappa2 * b[(size_t)box * n + r];
+    atomic_max_nonneg(anorm + box, sum + fabs(d));
   }
 }
 
@@ -168,8 +177,8 @@ template <typename T>
 hipError_t launch_operators(const Geom& g, int nbox, const double* b, T* A, double* anorm, hipStream_t st) {
   hipError_t e = launch_fill_zero(anorm, sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
-  const int rows = g.n_pad < 1024 ? g.n_pad : 1024;
-  hipLaunchKernelGGL((operators_kernel<T>), dim3(rows, nbox), dim3(256), 0, st, g, nbox, b, A, anorm);
+  hipLaunchKernelGGL((operators_kernel<T>), dim3((g.n_pad + kOpRows - 1) / kOpRows, nbox), dim3(256), 0, st, g, nbox,
+                     b, A, anorm);
   return hipGetLastError();
 }
 template hipError_t launch_operators<float>(const Geom&, int, const double*, float*, double*, hipStream_t);
@@ -192,25 +201,43 @@ __device__ inline double aib_entry(const Geom& g, int ii, int jj, int kk, int co
   return -g.s2[axis] * g.D2[(along + 1) * g.p + (side ? g.p - 1 : 0)];
 }
 
+// B has at most 7 nonzeros per row (A_ib: the two face nodes at the ends of each of the
+// node's three lines; the load f): zero rows with 16-byte stores, then the nonzeros.
 template <typename T>
 __global__ __launch_bounds__(256) void rhs_kernel(Geom g, int nbox, const double* f, T* B_all, double* maxb) {
   const int box = blockIdx.y;
-  const int N = g.n_pad, ldx = g.ldx, n = g.n, m = g.m;
+  const int N = g.n_pad, ldx = g.ldx, n = g.n, m = g.m, mm = m * m, p = g.p;
   T* B = B_all + (size_t)box * N * ldx;
+  const int r0 = blockIdx.x * kOpRows;
+  const int nr = (N - r0) < kOpRows ? (N - r0) : kOpRows;
+  const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+  const int q4 = ldx / 4;
+  for (int e = threadIdx.x; e < nr * q4; e += blockDim.x) {
+    const int rr = e / q4, c = (e - rr * q4) * 4;
+    Store4<T>::st(B + (size_t)(r0 + rr) * ldx + c, zero);
+  }
+  __syncthreads();
   double mx = 0.0;
-  for (int r = blockIdx.x; r < N; r += gridDim.x) {
-    T* row = B + (size_t)r * ldx;
-    const int ii = r % m, jj = (r / m) % m, kk = r / (m * m);
-    const double fr = (r < n && f) ? f[(size_t)box * n + r] : 0.0;
-    for (int c = threadIdx.x; c < ldx; c += blockDim.x) {
-      double v = 0.0;
-      if (r < n) {
-        if (c < g.nb) v = aib_entry(g, ii, jj, kk, c);
-        else if (c == g.nb) v = fr;
-      }
-      mx = fmax(mx, fabs(v));
-      row[c] = (T)v;
+  for (int e = threadIdx.x; e < nr * 7; e += blockDim.x) {
+    const int rr = e / 7, t = e - rr * 7, r = r0 + rr;
+    if (r >= n) continue;
+    double v;
+    int col;
+    if (t == 6) {
+      if (!f) continue;
+      v = f[(size_t)box * n + r];
+      col = g.nb;
+    } else {
+      const int cd = g.coords[r];
+      const int ii = cd & 255, jj = (cd >> 8) & 255, kk = cd >> 16;
+      const int axis = t >> 1, side = t & 1;
+      const int along = axis == 0 ? ii : (axis == 1 ? jj : kk);
+      const int tq = axis == 0 ? jj + m * kk : (axis == 1 ? ii + m * kk : ii + m * jj);
+      col = t * mm + tq;
+      v = -g.s2[axis] * g.D2[(along + 1) * p + (side ? p - 1 : 0)];
     }
+    B[(size_t)r * ldx + col] = (T)v;
+    mx = fmax(mx, fabs(v));
   }
   mx = wave_max(mx);
   if ((threadIdx.x & 63) == 0) atomic_max_nonneg(maxb + box, mx);
@@ -220,8 +247,8 @@ template <typename T>
 hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* maxb, hipStream_t st) {
   hipError_t e = launch_fill_zero(maxb, sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
-  const int rows = g.n_pad < 1024 ? g.n_pad : 1024;
-  hipLaunchKernelGGL((rhs_kernel<T>), dim3(rows, nbox), dim3(256), 0, st, g, nbox, f, B, maxb);
+  hipLaunchKernelGGL((rhs_kernel<T>), dim3((g.n_pad + kOpRows - 1) / kOpRows, nbox), dim3(256), 0, st, g, nbox, f, B,
+                     maxb);
   return hipGetLastError();
 }
 template hipError_t launch_rhs<float>(const Geom&, int, const double*, float*, double*, hipStream_t);
