@@ -469,8 +469,9 @@ __global__ __launch_bounds__(256) void leaf_op_kernel(Geom g, const int* perm_al
 // R_j = Y_j itself, k in [s + w, N).  One 64 x 64 output tile per workgroup: the K loop
 // is the tile GEMM, the 64 x 64 x 64 inverse product reads Z from LDS.
 constexpr int kTrsmSeg = 512;
+constexpr int kTrsmSegAbove = 4096;
 
-template <typename T, bool UPPER>
+template <typename T, bool UPPER, bool SEG>
 __global__ __launch_bounds__(256, 4) void trsm_row_kernel(Geom g, const T* F_all, const int* perm_all,
                                                           const T* dinv_all, const T* B_all, T* Y_all, int s, int w,
                                                           int nbox, int ntn, const int* active, double* X_all,
@@ -499,11 +500,11 @@ __global__ __launch_bounds__(256, 4) void trsm_row_kernel(Geom g, const T* F_all
     for (int ct = 0; ct < WCT; ct++) acc[rt][ct] = Mfma<T>::zero();
   auto arow = [&](int r) -> const T* { return r < w ? F + (size_t)perm[s + r] * N : nullptr; };
   auto brow = [&](int k) -> const T* { return Y + (size_t)k * ld + nt; };
-  // acc = -F Y.  In FP32 the running sum `part` is folded into acc every kTrsmSeg values
-  // of k, so that no accumulator adds more than kTrsmSeg products in sequence (K reaches
-  // n_pad); the fold runs inside the K loop and keeps its pipeline going.
+  // acc = -F Y.  With SEG (FP32, long K) the running sum `part` is folded into acc every
+  // kTrsmSeg values of k, so that no accumulator adds more than kTrsmSeg products in
+  // sequence; the fold runs inside the K loop and keeps its pipeline going.
   const int k0 = UPPER ? s + w : 0, k1 = UPPER ? N : s;
-  if constexpr (sizeof(T) == 8) {
+  if constexpr (!SEG) {
     G::run(acc, arow, brow, 64, k0, k1, smem);
   } else {
     typename G::acc_t part[WRT][WCT];
@@ -657,18 +658,34 @@ hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, 
   const int N = g.n_pad, ntn = g.ldx / 64;
   const double nrhs = g.nb + 1;
   hipError_t e = hipSuccess;
+  // FP32 sums over K > kTrsmSegAbove are split into segments (accuracy at p >= 19)
+  const bool seg = sizeof(T) == 4 && N > kTrsmSegAbove;
   for (int s = 0; s < N && e == hipSuccess; s += kPanel) {  // L Y = P B, block rows top down
     const int w = (N - s) < kPanel ? (N - s) : kPanel;
     ProfScope ps(prof, Profiler::kSolveFwd, (2.0 * w * s + (double)w * w) * nrhs * nbox, st);
-    hipLaunchKernelGGL((trsm_row_kernel<T, false>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm, dinv, B,
-                       Y, s, w, nbox, ntn, active, nullptr, 0);
+    if constexpr (sizeof(T) == 4)
+      if (seg) {
+        hipLaunchKernelGGL((trsm_row_kernel<T, false, true>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm,
+                           dinv, B, Y, s, w, nbox, ntn, active, nullptr, 0);
+        e = hipGetLastError();
+        continue;
+      }
+    hipLaunchKernelGGL((trsm_row_kernel<T, false, false>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm,
+                       dinv, B, Y, s, w, nbox, ntn, active, nullptr, 0);
     e = hipGetLastError();
   }
   for (int s = (N - 1) / kPanel * kPanel; s >= 0 && e == hipSuccess; s -= kPanel) {  // U X = Y, bottom up
     const int w = (N - s) < kPanel ? (N - s) : kPanel;
     ProfScope ps(prof, Profiler::kSolveBwd, (2.0 * w * (N - s - w) + (double)w * w) * nrhs * nbox, st);
-    hipLaunchKernelGGL((trsm_row_kernel<T, true>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm, dinv, Y,
-                       Y, s, w, nbox, ntn, active, xmode ? X : nullptr, xmode);
+    if constexpr (sizeof(T) == 4)
+      if (seg) {
+        hipLaunchKernelGGL((trsm_row_kernel<T, true, true>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm,
+                           dinv, Y, Y, s, w, nbox, ntn, active, xmode ? X : nullptr, xmode);
+        e = hipGetLastError();
+        continue;
+      }
+    hipLaunchKernelGGL((trsm_row_kernel<T, true, false>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm,
+                       dinv, Y, Y, s, w, nbox, ntn, active, xmode ? X : nullptr, xmode);
     e = hipGetLastError();
   }
   return e;
