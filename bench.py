@@ -33,14 +33,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_fwd_16x16x16_p16_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_16x16x16_p16.md")
 KERNEL_SOURCES = ("paper_2503_04033_amd/csrc/common.h", "paper_2503_04033_amd/csrc/lu.hip")
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
-    or None when the summary is missing, is for another kernel, or the kernel's sources
-    changed since the counters were taken."""
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE/WRITE_SIZE summary
+    (lines `traffic_bytes_per_launch[<kernel>]: <bytes>`), or None when the summary is
+    missing, does not list the kernel, or the kernel sources changed since the counters
+    were taken (`kernel_sources_sha256`)."""
     import hashlib
     try:
         kv = {}
@@ -52,9 +53,9 @@ def measured_traffic(kernel: str):
         for src in KERNEL_SOURCES:
             with open(os.path.join(ROOT, src), "rb") as fh:
                 h.update(fh.read())
-        if kv.get("kernel") != kernel or kv.get("kernel_sources_sha256") != h.hexdigest():
+        if kv.get("kernel_sources_sha256") != h.hexdigest():
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[f"traffic_bytes_per_launch[{kernel}]"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -257,7 +258,7 @@ def main():
     launched_passes = 1 + a.ir_max_iter
     for k in ("solve_fwd", "solve_bwd"):
         fams[k]["flops"] *= passes / launched_passes
-    KNAMES = {"solve_fwd": "trsm_row_kernel<float, false>", "solve_bwd": "trsm_row_kernel<float, true>",
+    KNAMES = {"solve_fwd": "trsm_row_kernel<float, false, false>", "solve_bwd": "trsm_row_kernel<float, true, false>",
               "lu_gemm": "gemm_op_kernel<float, true>", "lu_panel": "lu_panel_kernel<float, 6, 8, 64>",
               "residual": "residual_mfma_kernel<14, 2>"}
     # the LU/TRSM phase: device time of the factorization and solve kernels (events around
