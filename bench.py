@@ -258,7 +258,7 @@ def main():
     launched_passes = 1 + a.ir_max_iter
     for k in ("solve_fwd", "solve_bwd"):
         fams[k]["flops"] *= passes / launched_passes
-    KNAMES = {"solve_fwd": "trsm_row_kernel<float, false, false>", "solve_bwd": "trsm_row_kernel<float, true, false>",
+    KNAMES = {"solve_fwd": "trsm_row_kernel<float, false, false, 4>", "solve_bwd": "trsm_row_kernel<float, true, false, 4>",
               "lu_gemm": "gemm_op_kernel<float, true>", "lu_panel": "lu_panel_kernel<float, 6, 8, 64>",
               "residual": "residual_mfma_kernel<14, 2>"}
     # the LU/TRSM phase: device time of the factorization and solve kernels (events around

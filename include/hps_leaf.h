@@ -201,6 +201,22 @@ hps_status hps_leaf_adjoint_solve(hps_plan plan, int32_t nbox, const void* LU, c
 hps_status hps_leaf_adjoint_grad(hps_plan plan, int32_t nbox, const double* lam_i, const double* u_i,
                                  double* grad, hipStream_t stream);
 
+/* Run-time tuning of a plan.  A knob changes how the work is scheduled, never
+ * what is computed: every setting gives bitwise the same results.
+ *   HPS_TUNE_TRSM_SCHEDULE: the interior solves of hps_leaf_dtn (Alg. 1, the
+ *     triangular solves with the LU factors) as 0 = one launch per 64-row block
+ *     row (default) or 1 = one launch per forward / backward sweep, each
+ *     workgroup running every block row of its (box, 64-column) tile.
+ *   HPS_TUNE_TRSM_WAVES: FP32_IR plans, p <= 18: the waves per SIMD (4, 6 or 8;
+ *     default 4) the solve kernels are register-allocated for, i.e. how many of
+ *     their workgroups one CU keeps resident.  FP64 plans and p >= 19 always run
+ *     at 4; the value is accepted and ignored there.
+ * set: HPS_EINVAL for an unknown key or value (the plan is left unchanged);
+ * get: writes the current value to *value. */
+typedef enum { HPS_TUNE_TRSM_SCHEDULE = 0, HPS_TUNE_TRSM_WAVES = 1 } hps_tuning_key;
+hps_status hps_plan_set_tuning(hps_plan plan, int32_t key, int32_t value);
+hps_status hps_plan_get_tuning(hps_plan plan, int32_t key, int32_t* value);
+
 /* Human-readable message for a status code (static storage). */
 const char* hps_status_string(hps_status s);
 

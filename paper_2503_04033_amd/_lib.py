@@ -15,8 +15,11 @@ EXPORTS = (
     "hps_plan_create", "hps_plan_destroy", "hps_plan_get_info", "hps_leaf_nodes", "hps_leaf_operators",
     "hps_leaf_factor", "hps_leaf_dtn", "hps_interface_reduce", "hps_leaf_reconstruct", "hps_leaf_adjoint_solve",
     "hps_leaf_adjoint_grad", "hps_status_string", "hps_plan_profile_enable", "hps_plan_profile_read",
-    "hps_leaf_interior_solve", "hps_leaf_flux",
+    "hps_leaf_interior_solve", "hps_leaf_flux", "hps_plan_set_tuning", "hps_plan_get_tuning",
 )
+
+HPS_TUNE_TRSM_SCHEDULE, HPS_TUNE_TRSM_WAVES = 0, 1
+TUNING_KEYS = {"trsm_schedule": HPS_TUNE_TRSM_SCHEDULE, "trsm_waves": HPS_TUNE_TRSM_WAVES}
 
 PROFILE_FAMILIES = ("lu_gemm", "lu_panel", "lu_leaf", "solve_fwd", "solve_bwd", "residual", "dtn", "operators")
 
@@ -70,6 +73,8 @@ def load() -> C.CDLL:
         "hps_leaf_flux": [P, I32, P, P, P, P],
         "hps_plan_profile_enable": [P, I32],
         "hps_plan_profile_read": [P, C.POINTER(Profile)],
+        "hps_plan_set_tuning": [P, I32, I32],
+        "hps_plan_get_tuning": [P, I32, C.POINTER(C.c_int32)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

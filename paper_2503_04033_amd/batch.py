@@ -7,8 +7,10 @@ size group with its own plan and buffers; each group is cut into chunks that
 fit an HBM budget, and every chunk runs operators -> LU -> solves/refinement ->
 DtN scatter as kernel launches that cover all boxes of the chunk.  The whole
 sequence of launches can be captured once in a HIP graph and replayed (no host
-work, no allocation, no memset nodes inside), and the chunk size per group can
-be picked by timing candidates (`autotune`).
+work, no allocation, no memset nodes inside).  `autotune` picks, per group, the
+chunk size and the plan's scheduling knobs (triangular-solve schedule and the
+occupancy its kernels are built for) by timing candidates; none of these
+choices changes a single bit of the results.
 """
 from __future__ import annotations
 
@@ -65,13 +67,18 @@ class BatchedLeafReduction:
     """Build stage (Alg. 1 loop) for several problems, one stream, optional graph."""
 
     def __init__(self, problems, precision: str = "fp32_ir", hbm_budget: float = 64e9, ir_max_iter: int = 3,
-                 ir_tol: float = 1e-11, chunks: Optional[List[int]] = None, device="cuda"):
+                 ir_tol: float = 1e-11, chunks: Optional[List[int]] = None, device="cuda",
+                 tuning: Optional[List[dict]] = None):
+        """chunks[q]: boxes per chunk of problem q (default: as many as fit hbm_budget).
+        tuning[q]: plan knobs {name: value} for problem q (see LeafPlan.hps_plan_set_tuning)."""
         self.device = torch.device(device)
         self.precision = precision
         self.groups: List[Group] = []
         for q, pr in enumerate(problems):
             gr = Group(nboxes=tuple(pr.nboxes), lo=tuple(pr.lo), hi=tuple(pr.hi), p=int(pr.p), kappa=float(pr.kappa))
             gr.plan = LeafPlan(gr.p, gr.h, gr.kappa, precision, ir_max_iter, ir_tol)
+            for k, v in ((tuning[q] if tuning else None) or {}).items():
+                gr.plan.hps_plan_set_tuning(k, v)
             gr.layout = itf.build_layout(gr.nboxes, gr.plan.info.m)
             per_box = bytes_per_box(gr.plan.info)
             fit = max(1, int(hbm_budget // max(per_box, 1)))
@@ -148,11 +155,36 @@ class BatchedLeafReduction:
             self.enqueue()
 
 
-def autotune(problems, precision="fp32_ir", candidates=(128, 256, 512, 1024), hbm_budget=64e9, cache=None,
-             reps=1):
-    """Pick a chunk size per problem by timing the build stage; results cached as JSON.
+TRSM_KNOBS = ({"trsm_schedule": 0, "trsm_waves": 4}, {"trsm_schedule": 0, "trsm_waves": 6},
+              {"trsm_schedule": 0, "trsm_waves": 8}, {"trsm_schedule": 1, "trsm_waves": 4})
 
-    Returns a list of chunk sizes.  The cache key is (p, nbox, precision, GPU name).
+
+def _time_build(pr, precision, hbm_budget, chunk, knobs, reps):
+    br = BatchedLeafReduction([pr], precision, hbm_budget, chunks=[chunk], tuning=[knobs])
+    br.sample_inputs(0, pr)
+    br.allocate()
+    br.run()  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        br.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del br
+    torch.cuda.empty_cache()
+    return ms
+
+
+def autotune(problems, precision="fp32_ir", candidates=(128, 256, 512, 1024), hbm_budget=64e9, cache=None,
+             reps=1, knobs=TRSM_KNOBS):
+    """Pick, per problem, the chunk size and the solve knobs by timing the build stage.
+
+    Two passes: every knob setting at the largest chunk that fits hbm_budget, then every
+    candidate chunk with the fastest setting.  Returns a list of
+    {"chunk": c, "tuning": {knob: value}}; results are cached as JSON under the key
+    (GPU name, p, nbox, precision).
     """
     name = torch.cuda.get_device_name(0)
     table = {}
@@ -164,34 +196,23 @@ def autotune(problems, precision="fp32_ir", candidates=(128, 256, 512, 1024), hb
         nbox = int(np.prod(pr.nboxes))
         key = f"{name}|p={pr.p}|nbox={nbox}|{precision}"
         if key in table:
-            out.append(int(table[key]["chunk"]))
+            out.append({"chunk": int(table[key]["chunk"]), "tuning": dict(table[key]["tuning"])})
             continue
-        best, best_ms, trials = None, float("inf"), {}
-        for c in candidates:
-            c = min(c, nbox)
-            if c in trials:
-                continue
-            br = BatchedLeafReduction([pr], precision, hbm_budget, chunks=[c])
-            if bytes_per_box(br.groups[0].plan.info) * c > hbm_budget:
-                continue
-            br.sample_inputs(0, pr)
-            br.allocate()
-            br.run()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                br.run()
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            trials[c] = ms
-            if ms < best_ms:
-                best, best_ms = c, ms
-            del br
-            torch.cuda.empty_cache()
-        table[key] = {"chunk": best, "ms": best_ms, "trials": trials}
-        out.append(int(best))
+        per_box = bytes_per_box(LeafPlan(pr.p, pr.h, pr.kappa, precision).info)
+        fits = [min(c, nbox) for c in candidates if per_box * min(c, nbox) <= hbm_budget]
+        if not fits:
+            raise ValueError(f"no candidate chunk of p={pr.p} fits {hbm_budget:.3g} bytes")
+        c0 = max(fits)
+        ktrials = [(kn, _time_build(pr, precision, hbm_budget, c0, kn, reps)) for kn in knobs]
+        best_kn = min(ktrials, key=lambda t: t[1])[0]
+        ctrials = {}
+        for c in sorted(set(fits)):
+            ctrials[c] = _time_build(pr, precision, hbm_budget, c, best_kn, reps)
+        best_c = min(ctrials, key=ctrials.get)
+        table[key] = {"chunk": best_c, "tuning": best_kn, "ms": ctrials[best_c],
+                      "knob_trials": [[kn, ms] for kn, ms in ktrials],
+                      "chunk_trials": {str(c): ms for c, ms in ctrials.items()}}
+        out.append({"chunk": int(best_c), "tuning": dict(best_kn)})
     if cache:
         with open(cache, "w") as fh:
             json.dump(table, fh, indent=1)

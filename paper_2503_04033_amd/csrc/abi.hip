@@ -18,6 +18,8 @@ struct hps_plan_s {
   std::vector<int> lu_ops;  // LU schedule (records of 8 ints)
   hps::Profiler prof;                          // optional kernel timing
   const double* t;
+  int trsm_sched = hps::kTrsmRows;             // HPS_TUNE_TRSM_SCHEDULE
+  int trsm_waves = 4;                          // HPS_TUNE_TRSM_WAVES
 };
 
 namespace {
@@ -287,7 +289,8 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     double* B = static_cast<double*>(L.B);
     HPS_TRY(hps::launch_rhs<double>(g, nbox, f, B, L.maxb, st));
     HPS_TRY(hps::getrs_run<double>(g, static_cast<const double*>(LU), perm,
-                                   static_cast<const double*>(dinv), B, X, nbox, nullptr, st, &pl->prof));
+                                   static_cast<const double*>(dinv), B, X, nbox, nullptr, st, &pl->prof, nullptr, 0,
+                                   pl->trsm_sched, pl->trsm_waves));
     if (ir_iters) HPS_TRY(hps::launch_fill_int(ir_iters, 0, nbox, st));
     if (berr) {
       HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
@@ -302,7 +305,8 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     const float* Dinv = static_cast<const float*>(dinv);
     HPS_TRY(hps::launch_rhs<float>(g, nbox, f, B, L.maxb, st));
     // the first solve also writes X = Y in FP64; each correction below adds into X
-    HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st, &pl->prof, X, 1));
+    HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st, &pl->prof, X, 1,
+                                  pl->trsm_sched, pl->trsm_waves));
     HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
     const int kmax = pl->desc.ir_max_iter;
     const double tol = pl->desc.ir_tol;
@@ -315,7 +319,8 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
       HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
                                    st));
       if (last) break;
-      HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st, &pl->prof, X, 2));
+      HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st, &pl->prof, X, 2,
+                                    pl->trsm_sched, pl->trsm_waves));
     }
   }
   hps::ProfScope ps(&pl->prof, hps::Profiler::kDtn, 0.0, st);
@@ -381,6 +386,32 @@ hps_status hps_leaf_adjoint_solve(hps_plan pl, int32_t nbox, const void* LU, con
   HPS_TRY(hps::launch_compact(g, nbox, zt, z, st));
   if (y_b) HPS_TRY(hps::launch_adjoint_yb(g, nbox, zt, y_b, st));
   return HPS_OK;
+}
+
+hps_status hps_plan_set_tuning(hps_plan pl, int32_t key, int32_t value) {
+  if (bad_plan(pl)) return HPS_EINVAL;
+  if (key == HPS_TUNE_TRSM_SCHEDULE && (value == hps::kTrsmRows || value == hps::kTrsmSweep)) {
+    pl->trsm_sched = value;
+    return HPS_OK;
+  }
+  if (key == HPS_TUNE_TRSM_WAVES && (value == 4 || value == 6 || value == 8)) {
+    pl->trsm_waves = value;
+    return HPS_OK;
+  }
+  return HPS_EINVAL;
+}
+
+hps_status hps_plan_get_tuning(hps_plan pl, int32_t key, int32_t* value) {
+  if (bad_plan(pl) || !value) return HPS_EINVAL;
+  if (key == HPS_TUNE_TRSM_SCHEDULE) {
+    *value = pl->trsm_sched;
+    return HPS_OK;
+  }
+  if (key == HPS_TUNE_TRSM_WAVES) {
+    *value = pl->trsm_waves;
+    return HPS_OK;
+  }
+  return HPS_EINVAL;
 }
 
 hps_status hps_plan_profile_enable(hps_plan pl, int32_t enable) {

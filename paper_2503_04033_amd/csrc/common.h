@@ -19,6 +19,9 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 
 constexpr int kWave = 64;
 constexpr int kPanel = 64;  // LU panel width == row block of the triangular solves
+// schedules of the triangular solves: one launch per 64-row block row, or one launch
+// per sweep with every block row of a (box, column tile) in one workgroup
+constexpr int kTrsmRows = 0, kTrsmSweep = 1;
 
 // ---------------------------------------------------------------------------
 // MFMA 16x16x4 wrappers.  Operand layout (both precisions): lane l supplies

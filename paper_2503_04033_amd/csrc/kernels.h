@@ -85,7 +85,8 @@ hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm
 // written by the backward block-row launches as they finish each tile
 template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
-                     const int* active, hipStream_t st, Profiler* prof, double* X = nullptr, int xmode = 0);
+                     const int* active, hipStream_t st, Profiler* prof, double* X = nullptr, int xmode = 0,
+                     int sched = kTrsmRows, int waves = 4);
 
 // leafops.hip
 hipError_t launch_nodes(const Geom& g, const double* t, const double* h, int nbox, const double* origin, double* xi,

@@ -462,7 +462,6 @@ __global__ __launch_bounds__(256) void leaf_op_kernel(Geom g, const int* perm_al
     }
 }
 
-// Y[box][i][:] = B[box][perm[i]][:]
 // One block row of the solves, left-looking: Z = R_j - F[j rows][k range] Y[k range]
 // over the finished rows, then Y_j = Inv_j Z with the stored inverse of the diagonal
 // block.  Forward (L, unit diagonal): R_j = B[perm[s + i]], k in [0, s).  Backward (U):
@@ -472,35 +471,30 @@ constexpr int kTrsmSeg = 512;
 constexpr int kTrsmSegAbove = 4096;
 
 template <typename T, bool UPPER, bool SEG>
-__global__ __launch_bounds__(256, 4) void trsm_row_kernel(Geom g, const T* F_all, const int* perm_all,
-                                                          const T* dinv_all, const T* B_all, T* Y_all, int s, int w,
-                                                          int nbox, int ntn, const int* active, double* X_all,
-                                                          int xmode) {
+__device__ __attribute__((always_inline)) inline void solve_block_row(const Geom& g, const T* F, const int* perm, const T* Inv, const T* B, T* Y,
+                                       double* Xb, int xmode, int s, int w, int nt, T* smem) {
   typedef typename GemmCfg<T>::G G;
   static_assert(G::MT == 64 && G::NT == 64, "one 64 x 64 tile per workgroup");
   static_assert(G::SMEM >= 64 * kLeafLd, "Z must fit the GEMM staging buffer");
   constexpr int WRT = 2, WCT = 2;
-  __shared__ T smem[G::SMEM];
-  int box, tn;
-  if (!map_box_tile(nbox, ntn, box, tn)) return;
-  if (active && active[box] == 0) return;
   const int N = g.n_pad, ld = g.ldx;
-  const T* F = F_all + (size_t)box * N * N;
-  const int* perm = perm_all + (size_t)box * N;
-  const size_t xs = (size_t)N * ld;
-  T* Y = Y_all + (size_t)box * xs;
-  const T* B = B_all + (size_t)box * xs;
-  const int nt = tn * 64;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave % 2, wn = wave / 2;
+  const int g4 = lane >> 4, c16 = lane & 15;
+  // The accumulator starts at R_j (rows past w: 0), so that no load waits after the K loop.
   typename G::acc_t acc[WRT][WCT];
 #pragma unroll
   for (int rt = 0; rt < WRT; rt++)
 #pragma unroll
-    for (int ct = 0; ct < WCT; ct++) acc[rt][ct] = Mfma<T>::zero();
+    for (int i = 0; i < 4; i++) {
+      const int r = (wm * WRT + rt) * 16 + Mfma<T>::row(lane, i);
+      const T* rr = r < w ? (UPPER ? Y + (size_t)(s + r) * ld : B + (size_t)perm[s + r] * ld) + nt : nullptr;
+#pragma unroll
+      for (int ct = 0; ct < WCT; ct++) acc[rt][ct][i] = rr ? rr[(wn * WCT + ct) * 16 + c16] : T(0);
+    }
   auto arow = [&](int r) -> const T* { return r < w ? F + (size_t)perm[s + r] * N : nullptr; };
   auto brow = [&](int k) -> const T* { return Y + (size_t)k * ld + nt; };
-  // acc = -F Y.  With SEG (FP32, long K) the running sum `part` is folded into acc every
+  // acc -= F Y.  With SEG (FP32, long K) the running sum `part` is folded into acc every
   // kTrsmSeg values of k, so that no accumulator adds more than kTrsmSeg products in
   // sequence; the fold runs inside the K loop and keeps its pipeline going.
   const int k0 = UPPER ? s + w : 0, k1 = UPPER ? N : s;
@@ -533,35 +527,115 @@ __global__ __launch_bounds__(256, 4) void trsm_row_kernel(Geom g, const T* F_all
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const int r = (wm * WRT + rt) * 16 + Mfma<T>::row(lane, i);
-      const T* rr = r < w ? (UPPER ? Y + (size_t)(s + r) * ld : B + (size_t)perm[s + r] * ld) + nt : nullptr;
 #pragma unroll
-      for (int ct = 0; ct < WCT; ct++) {
-        const int c = (wn * WCT + ct) * 16 + (lane & 15);
-        zs[r * kLeafLd + c] = rr ? rr[c] + acc[rt][ct][i] : T(0);
-      }
+      for (int ct = 0; ct < WCT; ct++) zs[r * kLeafLd + (wn * WCT + ct) * 16 + c16] = acc[rt][ct][i];
     }
-  __syncthreads();
-  const T* Inv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(s / kPanel) * 2 * 64 * 64 +
-                 (UPPER ? 64 * 64 : 0);
-  typename Mfma<T>::acc out[1][4];
+  // Y_j = Inv_j Z: the wave's 16 rows of the inverse (columns past w zeroed) times all 64
+  // columns of Z, the inverse read one 16-column chunk ahead; for X += Y (xmode 2) the
+  // old X is loaded first, in flight during the product
+  const T* irow = Inv + (wave * 16 + c16) * 64 + 4 * g4;
+  T ia[4];
+  Vec4<T>::load(irow, ia);
+  const bool xadd = Xb && xmode == 2;
+  double xo[4][4];
+  if (xadd) {
 #pragma unroll
-  for (int ct = 0; ct < 4; ct++) out[0][ct] = Mfma<T>::zero();
-  auto irow = [&](int) -> const T* { return Inv + (wave * 16 + (lane & 15)) * 64; };
-  wg_gemm_lds_add<T, 1, 4>(out, irow, zs, kLeafLd, w, 0);
-  // the finished rows; backward launches may also write them to the FP64 X (xmode 1:
+    for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int r = wave * 16 + Mfma<T>::row(lane, i);
+        xo[ct][i] = r < w ? Xb[(size_t)(s + r) * ld + nt + ct * 16 + c16] : 0.0;
+      }
+  }
+  __syncthreads();
+  typename Mfma<T>::acc out[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++) out[ct] = Mfma<T>::zero();
+#pragma unroll
+  for (int kc = 0; kc < 4; kc++) {
+    T ib[4];
+    if (kc + 1 < 4) Vec4<T>::load(irow + (kc + 1) * 16, ib);
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int k = kc * 16 + 4 * g4 + t;
+      const T a = k < w ? ia[t] : T(0);
+      const T* zr = zs + k * kLeafLd + c16;
+#pragma unroll
+      for (int ct = 0; ct < 4; ct++) out[ct] = Mfma<T>::op(a, zr[ct * 16], out[ct]);
+    }
+    if (kc + 1 < 4)
+#pragma unroll
+      for (int t = 0; t < 4; t++) ia[t] = ib[t];
+  }
+  // the finished rows; the backward sweep may also write them to the FP64 X (xmode 1:
   // X = Y, xmode 2: X += Y)
-  double* Xb = X_all ? X_all + (size_t)box * xs : nullptr;
 #pragma unroll
   for (int ct = 0; ct < 4; ct++)
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const int r = wave * 16 + Mfma<T>::row(lane, i);
       if (r < w) {
-        const size_t e = (size_t)(s + r) * ld + nt + ct * 16 + (lane & 15);
-        Y[e] = out[0][ct][i];
-        if (Xb) Xb[e] = xmode == 1 ? (double)out[0][ct][i] : Xb[e] + (double)out[0][ct][i];
+        const size_t e = (size_t)(s + r) * ld + nt + ct * 16 + c16;
+        Y[e] = out[ct][i];
+        if (Xb) Xb[e] = xadd ? xo[ct][i] + (double)out[ct][i] : (double)out[ct][i];
       }
     }
+}
+
+// One block row per launch: workgroup (box, 64-column tile).  OCC: waves per SIMD the
+// register allocation must allow (workgroups resident per CU, LDS permitting).
+template <typename T, bool UPPER, bool SEG, int OCC>
+__global__ __launch_bounds__(256, OCC) void trsm_row_kernel(Geom g, const T* F_all, const int* perm_all,
+                                                          const T* dinv_all, const T* B_all, T* Y_all, int s, int w,
+                                                          int nbox, int ntn, const int* active, double* X_all,
+                                                          int xmode) {
+  typedef typename GemmCfg<T>::G G;
+  __shared__ T smem[G::SMEM];
+  int box, tn;
+  if (!map_box_tile(nbox, ntn, box, tn)) return;
+  if (active && active[box] == 0) return;
+  const int N = g.n_pad;
+  const size_t xs = (size_t)N * g.ldx;
+  const T* Inv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(s / kPanel) * 2 * 64 * 64 +
+                 (UPPER ? 64 * 64 : 0);
+  solve_block_row<T, UPPER, SEG>(g, F_all + (size_t)box * N * N, perm_all + (size_t)box * N, Inv,
+                                 B_all + (size_t)box * xs, Y_all + (size_t)box * xs,
+                                 X_all ? X_all + (size_t)box * xs : nullptr, xmode, s, w, tn * 64, smem);
+}
+
+// One whole triangular sweep per workgroup: the right-hand-side columns of a box are
+// independent, so the workgroup of (box, 64-column tile) runs every block row of its
+// tile in order (top down for L, bottom up for U) with no other workgroup involved.
+// One launch per sweep: no drain between block rows, and the epilogue of one block row
+// overlaps the K loops of the other workgroups resident on the CU.  The block row just
+// stored is the first or last K chunk of the next one; the barrier after the stores
+// makes it visible to every wave of the workgroup (one CU, one vector L1).
+template <typename T, bool UPPER, bool SEG, int OCC>
+__global__ __launch_bounds__(256, OCC) void trsm_sweep_kernel(Geom g, const T* F_all, const int* perm_all,
+                                                            const T* dinv_all, const T* B_all, T* Y_all, int nbox,
+                                                            int ntn, const int* active, double* X_all, int xmode) {
+  typedef typename GemmCfg<T>::G G;
+  __shared__ T smem[G::SMEM];
+  int box, tn;
+  if (!map_box_tile(nbox, ntn, box, tn)) return;
+  if (active && active[box] == 0) return;
+  const int N = g.n_pad;
+  const size_t xs = (size_t)N * g.ldx;
+  const T* F = F_all + (size_t)box * N * N;
+  const int* perm = perm_all + (size_t)box * N;
+  const T* dinv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (UPPER ? 64 * 64 : 0);
+  T* Y = Y_all + (size_t)box * xs;
+  const T* B = B_all + (size_t)box * xs;
+  double* Xb = X_all ? X_all + (size_t)box * xs : nullptr;
+  const int nblk = (N + kPanel - 1) / kPanel;
+#pragma unroll 1
+  for (int q = 0; q < nblk; q++) {
+    const int jb = UPPER ? nblk - 1 - q : q;
+    const int s = jb * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
+    solve_block_row<T, UPPER, SEG>(g, F, perm, dinv + (size_t)jb * 2 * 64 * 64, B, Y, Xb, xmode, s, w, tn * 64,
+                                   smem);
+    __syncthreads();  // Y_j stored before the next block row loads it
+  }
 }
 
 
@@ -650,43 +724,61 @@ hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm
   return hipErrorInvalidValue;
 }
 
-// X = A^{-1} B for every active box: Y = P B (gather), forward ops with L, backward
-// ops with U, in place in Y (B and Y must not alias).
+template <typename T, bool UPPER, bool SEG, int OCC>
+static hipError_t launch_sweep(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
+                               const int* active, hipStream_t st, double* X, int xmode, int sched) {
+  const int ntn = g.ldx / 64, N = g.n_pad;
+  if (sched == kTrsmSweep) {
+    hipLaunchKernelGGL((trsm_sweep_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F,
+                       perm, dinv, B, Y, nbox, ntn, active, X, xmode);
+    return hipGetLastError();
+  }
+  const int nblk = (N + kPanel - 1) / kPanel;
+  for (int q = 0; q < nblk; q++) {
+    const int s = (UPPER ? nblk - 1 - q : q) * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
+    hipLaunchKernelGGL((trsm_row_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F,
+                       perm, dinv, B, Y, s, w, nbox, ntn, active, X, xmode);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// FP32: segmented sums for long K (accuracy at p >= 19), and the occupancy the kernels are
+// built for (4, 6 or 8 waves per SIMD; the 64 x 64 tile's 18.5 KB of LDS allows 8
+// workgroups per CU).  FP64: 4 (its 34.5 KB of LDS allows 4).
+template <typename T, bool UPPER>
+static hipError_t dispatch_sweep(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y,
+                                 int nbox, const int* active, hipStream_t st, double* X, int xmode, int sched,
+                                 int waves) {
+  if constexpr (sizeof(T) == 4) {
+    if (g.n_pad > kTrsmSegAbove)
+      return launch_sweep<T, UPPER, true, 4>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched);
+    if (waves == 8) return launch_sweep<T, UPPER, false, 8>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched);
+    if (waves == 6) return launch_sweep<T, UPPER, false, 6>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched);
+  }
+  return launch_sweep<T, UPPER, false, 4>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched);
+}
+
+// X = A^{-1} B for every active box: the forward sweep L Y = P B reads the rows of B
+// through perm, the backward sweep U X = Y works in place in Y (B and Y must not alias).
+// sched: kTrsmRows (one launch per block row) or kTrsmSweep (one launch per sweep);
+// waves: FP32 occupancy target (see dispatch_sweep).
 template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
-                     const int* active, hipStream_t st, Profiler* prof, double* X, int xmode) {
-  const int N = g.n_pad, ntn = g.ldx / 64;
-  const double nrhs = g.nb + 1;
-  hipError_t e = hipSuccess;
-  // FP32 sums over K > kTrsmSegAbove are split into segments (accuracy at p >= 19)
-  const bool seg = sizeof(T) == 4 && N > kTrsmSegAbove;
-  for (int s = 0; s < N && e == hipSuccess; s += kPanel) {  // L Y = P B, block rows top down
-    const int w = (N - s) < kPanel ? (N - s) : kPanel;
-    ProfScope ps(prof, Profiler::kSolveFwd, (2.0 * w * s + (double)w * w) * nrhs * nbox, st);
-    if constexpr (sizeof(T) == 4)
-      if (seg) {
-        hipLaunchKernelGGL((trsm_row_kernel<T, false, true>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm,
-                           dinv, B, Y, s, w, nbox, ntn, active, nullptr, 0);
-        e = hipGetLastError();
-        continue;
-      }
-    hipLaunchKernelGGL((trsm_row_kernel<T, false, false>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm,
-                       dinv, B, Y, s, w, nbox, ntn, active, nullptr, 0);
-    e = hipGetLastError();
+                     const int* active, hipStream_t st, Profiler* prof, double* X, int xmode, int sched, int waves) {
+  const double N = g.n_pad, nrhs = g.nb + 1;
+  // per sweep: sum over block rows of 2 w K + w^2 = N^2 per right-hand side
+  const double flops = N * N * nrhs * nbox;
+  hipError_t e;
+  {
+    ProfScope ps(prof, Profiler::kSolveFwd, flops, st);
+    e = dispatch_sweep<T, false>(g, F, perm, dinv, B, Y, nbox, active, st, nullptr, 0, sched, waves);
   }
-  for (int s = (N - 1) / kPanel * kPanel; s >= 0 && e == hipSuccess; s -= kPanel) {  // U X = Y, bottom up
-    const int w = (N - s) < kPanel ? (N - s) : kPanel;
-    ProfScope ps(prof, Profiler::kSolveBwd, (2.0 * w * (N - s - w) + (double)w * w) * nrhs * nbox, st);
-    if constexpr (sizeof(T) == 4)
-      if (seg) {
-        hipLaunchKernelGGL((trsm_row_kernel<T, true, true>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm,
-                           dinv, Y, Y, s, w, nbox, ntn, active, xmode ? X : nullptr, xmode);
-        e = hipGetLastError();
-        continue;
-      }
-    hipLaunchKernelGGL((trsm_row_kernel<T, true, false>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F, perm,
-                       dinv, Y, Y, s, w, nbox, ntn, active, xmode ? X : nullptr, xmode);
-    e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  {
+    ProfScope ps(prof, Profiler::kSolveBwd, flops, st);
+    e = dispatch_sweep<T, true>(g, F, perm, dinv, Y, Y, nbox, active, st, xmode ? X : nullptr, xmode, sched, waves);
   }
   return e;
 }
@@ -696,9 +788,9 @@ template hipError_t getrf_run<double>(const Geom&, const std::vector<int>&, doub
                                       hipStream_t, Profiler*);
 template hipError_t getrs_run<float>(const Geom&, const float*,
                                      const int*, const float*, const float*, float*, int, const int*, hipStream_t,
-                                     Profiler*, double*, int);
+                                     Profiler*, double*, int, int, int);
 template hipError_t getrs_run<double>(const Geom&, const double*,
                                       const int*, const double*, const double*, double*, int, const int*,
-                                      hipStream_t, Profiler*, double*, int);
+                                      hipStream_t, Profiler*, double*, int, int, int);
 
 }  // namespace hps

@@ -84,6 +84,15 @@ class LeafPlan:
             self.lib.hps_plan_destroy(h)
             self.handle = None
 
+    # ---- run-time tuning (scheduling only; results are bitwise the same) -------
+    def hps_plan_set_tuning(self, key: str, value: int) -> None:
+        check(self.lib.hps_plan_set_tuning(self.handle, _lib.TUNING_KEYS[key], int(value)), "hps_plan_set_tuning")
+
+    def hps_plan_get_tuning(self, key: str) -> int:
+        v = C.c_int32(0)
+        check(self.lib.hps_plan_get_tuning(self.handle, _lib.TUNING_KEYS[key], C.byref(v)), "hps_plan_get_tuning")
+        return int(v.value)
+
     # ---- kernel timing ---------------------------------------------------------
     def profile_enable(self, on: bool = True) -> None:
         check(self.lib.hps_plan_profile_enable(self.handle, 1 if on else 0), "hps_plan_profile_enable")

@@ -16,13 +16,18 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_leaf_boxes(prob, box_ids, precision="fp64", ir_max_iter=3, ir_tol=1e-11, f_on=True):
+def gpu_leaf_boxes(prob, box_ids, precision="fp64", ir_max_iter=3, ir_tol=1e-11, f_on=True, tuning=None):
     """Run a1..a4 on the listed boxes with a slot map that keeps every DtN block.
+
+    tuning: optional {knob: value} set on the plan (hps_plan_set_tuning) first.
 
     Returns dict with X [nb, n_i, nrhs], T [nb, n_b, n_b], g [nb, n_b], info, iters, berr.
     """
     dev = torch.device("cuda")
     plan = LeafPlan(prob.p, prob.h, prob.kappa, precision, ir_max_iter, ir_tol)
+    for k, v in (tuning or {}).items():
+        plan.hps_plan_set_tuning(k, v)
+        assert plan.hps_plan_get_tuning(k) == v
     i = plan.info
     nb = len(box_ids)
     org = prob.box_origins()[box_ids]

@@ -90,3 +90,29 @@ def test_three_problem_batch(gpu):
             assert torch.equal(g.T_vals, eager[q][0]), f"replay {rep} group {q}: T differs"
             assert torch.equal(g.g_loads, eager[q][1]), f"replay {rep} group {q}: g differs"
         say(f"  graph replay {rep}: bitwise equal to the eager run")
+
+
+def test_autotune_config4(gpu, tmp_path):
+    # the autotuner's choices (chunk, solve schedule, occupancy) per size group: valid,
+    # cached, and bitwise the same results as the untuned run
+    from paper_2503_04033_amd.batch import TRSM_KNOBS, BatchedLeafReduction, autotune
+    probs = W.config4()
+    cache = str(tmp_path / "tune.json")
+    tuned = autotune(probs, "fp32_ir", candidates=(256, 4096), hbm_budget=24e9, cache=cache)
+    for pr, t in zip(probs, tuned):
+        say(f"  autotune p={pr.p} nbox={pr.nbox}: chunk {t['chunk']}, {t['tuning']}")
+        assert t["chunk"] in (256, min(4096, pr.nbox)) and t["tuning"] in TRSM_KNOBS
+    assert autotune(probs, "fp32_ir", candidates=(256, 4096), hbm_budget=24e9, cache=cache) == tuned
+    runs = []
+    for kw in ({}, {"chunks": [t["chunk"] for t in tuned], "tuning": [t["tuning"] for t in tuned]}):
+        br = BatchedLeafReduction(probs, "fp32_ir", hbm_budget=24e9, **kw)
+        for q, pr in enumerate(probs):
+            br.sample_inputs(q, pr)
+        br.allocate()
+        br.run()
+        torch.cuda.synchronize()
+        runs.append([(g.T_vals.clone(), g.g_loads.clone(), g.iters.clone()) for g in br.groups])
+        del br
+    for q in range(len(probs)):
+        for a, b in zip(runs[0][q], runs[1][q]):
+            assert torch.equal(a, b), f"group {q}: tuned run differs"

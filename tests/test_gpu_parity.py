@@ -20,9 +20,9 @@ FP64_TOL = 1e-10
 IR_TOL = 1e-9
 
 
-def _check_leaf(prob, box_ids, precision, tol, f_on=True):
-    say(f"case {prob.name} p={prob.p} boxes={list(box_ids)} {precision}")
-    gout = gpu_leaf_boxes(prob, box_ids, precision, f_on=f_on)
+def _check_leaf(prob, box_ids, precision, tol, f_on=True, tuning=None):
+    say(f"case {prob.name} p={prob.p} boxes={list(box_ids)} {precision} tuning={tuning}")
+    gout = gpu_leaf_boxes(prob, box_ids, precision, f_on=f_on, tuning=tuning)
     ored = oracle_leaf_boxes(prob, box_ids, f_on=f_on)
     assert np.all(gout["info"] == 0)
     Xo = [np.concatenate([-r.S, r.v[:, None]], axis=1) for _, r in ored]
@@ -48,6 +48,30 @@ def test_leaf_fp32_ir_small(gpu, p):
     prob = W.multi_bump((2, 2, 2), p, 6.0, 12, gaussian_source=True, name=f"bump_p{p}")
     out = _check_leaf(prob, range(8), "fp32_ir", IR_TOL)
     assert np.all(out["iters"] >= 0)
+
+
+@pytest.mark.parametrize("precision,case", [("fp64", "p9"), ("fp32_ir", "p9"), ("fp32_ir", "p20")])
+def test_trsm_schedules(gpu, precision, case):
+    # every schedule and occupancy of the interior solves: parity with the oracle, and
+    # bitwise the same results (same tiles, same order of every sum); p = 20 takes the
+    # segmented FP32 sums
+    if case == "p9":
+        prob, boxes = W.multi_bump((2, 2, 2), 9, 6.0, 14, gaussian_source=True, name="sched_p9"), range(8)
+    else:
+        prob, boxes = W.config3_p20(), [5]
+    tol = FP64_TOL if precision == "fp64" else IR_TOL
+    sweep = _check_leaf(prob, boxes, precision, tol, tuning={"trsm_schedule": 1})
+    for waves in (4, 6, 8):
+        rows = gpu_leaf_boxes(prob, boxes, precision, tuning={"trsm_schedule": 0, "trsm_waves": waves})
+        for k in ("X", "T", "g", "iters"):
+            assert np.array_equal(sweep[k], rows[k]), (waves, k)
+    plan = rows["plan"]
+    from paper_2503_04033_amd._lib import HpsError
+    with pytest.raises(HpsError):
+        plan.hps_plan_set_tuning("trsm_schedule", 2)
+    with pytest.raises(HpsError):
+        plan.hps_plan_set_tuning("trsm_waves", 5)
+    assert plan.hps_plan_get_tuning("trsm_schedule") == 0 and plan.hps_plan_get_tuning("trsm_waves") == 8
 
 
 def test_factorization_property(gpu):
