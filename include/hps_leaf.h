@@ -221,13 +221,16 @@ hps_status hps_plan_get_tuning(hps_plan plan, int32_t key, int32_t* value);
 const char* hps_status_string(hps_status s);
 
 /* Kernel timing (tracing aid, not part of the method).  While enabled, every
- * launch the plan makes is bracketed by HIP events on its stream and counted
- * per kernel family; hps_plan_profile_read synchronizes on the recorded events
- * and returns, per family, launches, total milliseconds and the algorithmic
- * flops of those launches (2*M*N*K for tile GEMMs, 2*w*w*ncols for leaves, 0
- * for bandwidth kernels).  Families: 0 LU GEMM, 1 LU panel, 2 LU leaf,
- * 3 forward solve (L), 4 backward solve (U), 5 residual, 6 DtN, 7 operators.  Enabling clears
- * the counters.  Event recording adds launch overhead; leave it off in
+ * launch the plan makes (or run of consecutive launches of one family, such as
+ * the block rows of one triangular sweep) is bracketed by HIP events on its
+ * stream; hps_plan_profile_read synchronizes on the recorded events and
+ * returns, per kernel family, the number of kernel launches, total
+ * milliseconds and the algorithmic flops of those launches (2*M*N*K for tile
+ * GEMMs, 2*w*w*ncols for leaves, n_pad^2 * (n_b + 1) per box for a triangular
+ * sweep even where structurally zero blocks are skipped, 0 for bandwidth
+ * kernels).  Families: 0 LU GEMM, 1 LU panel, 2 LU leaf, 3 forward solve (L),
+ * 4 backward solve (U), 5 residual, 6 DtN, 7 operators.  Enabling clears the
+ * counters.  Event recording adds launch overhead; leave it off in
  * production. */
 #define HPS_PROFILE_FAMILIES 8
 typedef struct {

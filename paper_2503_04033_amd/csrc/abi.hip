@@ -107,8 +107,8 @@ Sizes sizes_of(const hps_plan_s* pl) {
   s.x = 8 * (size_t)g.n_pad * g.ldx;
   const size_t elems = (size_t)g.n_pad * g.ldx;
   // FP32_IR: B32 (right-hand side, later the FP32 residual) and Y32; FP64: B64.
-  // Plus per-box scalars.
-  s.ws = 8 * elems + 64;
+  // Plus per-box scalars and the first nonzero row of each right-hand-side tile.
+  s.ws = 8 * elems + 64 + 4 * round_up(g.ldx / 64, 16);
   return s;
 }
 
@@ -117,6 +117,7 @@ struct WsLayout {
   float* Y32;
   double *maxb, *maxr, *maxx;
   int* active;
+  int* kstart;  // [nbox][ldx/64]
 };
 
 WsLayout ws_layout(const hps_plan_s* pl, int nbox, void* ws) {
@@ -131,6 +132,7 @@ WsLayout ws_layout(const hps_plan_s* pl, int nbox, void* ws) {
   L.maxr = L.maxb + nbox;
   L.maxx = L.maxr + nbox;
   L.active = reinterpret_cast<int*>(L.maxx + nbox);
+  L.kstart = reinterpret_cast<int*>(p + 64 * (size_t)nbox);
   return L;
 }
 
@@ -288,9 +290,10 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
   if (!ir) {
     double* B = static_cast<double*>(L.B);
     HPS_TRY(hps::launch_rhs<double>(g, nbox, f, B, L.maxb, st));
+    HPS_TRY(hps::launch_rhs_first_row(g, nbox, perm, f != nullptr, L.kstart, st));
     HPS_TRY(hps::getrs_run<double>(g, static_cast<const double*>(LU), perm,
                                    static_cast<const double*>(dinv), B, X, nbox, nullptr, st, &pl->prof, nullptr, 0,
-                                   pl->trsm_sched, pl->trsm_waves));
+                                   pl->trsm_sched, pl->trsm_waves, L.kstart));
     if (ir_iters) HPS_TRY(hps::launch_fill_int(ir_iters, 0, nbox, st));
     if (berr) {
       HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
@@ -304,9 +307,10 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     const float* LUf = static_cast<const float*>(LU);
     const float* Dinv = static_cast<const float*>(dinv);
     HPS_TRY(hps::launch_rhs<float>(g, nbox, f, B, L.maxb, st));
+    HPS_TRY(hps::launch_rhs_first_row(g, nbox, perm, f != nullptr, L.kstart, st));
     // the first solve also writes X = Y in FP64; each correction below adds into X
     HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st, &pl->prof, X, 1,
-                                  pl->trsm_sched, pl->trsm_waves));
+                                  pl->trsm_sched, pl->trsm_waves, L.kstart));
     HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
     const int kmax = pl->desc.ir_max_iter;
     const double tol = pl->desc.ir_tol;

@@ -14,6 +14,7 @@ struct Profiler {
   enum { kLuGemm = 0, kLuPanel, kLuLeaf, kSolveFwd, kSolveBwd, kResidual, kDtn, kOperators, kFamilies };
   struct Rec {
     int fam;
+    int n;  // kernel launches between the two events
     double flops;
     hipEvent_t a, b;
   };
@@ -42,7 +43,7 @@ struct Profiler {
     for (auto& r : pending) {
       float t = 0.f;
       if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
-        launches[r.fam] += 1;
+        launches[r.fam] += r.n;
         ms[r.fam] += t;
         flops[r.fam] += r.flops;
       }
@@ -57,14 +58,16 @@ struct Profiler {
   }
 };
 
-// Brackets one launch with events when profiling is on.
+// Brackets `launches` kernel launches of one family with events when profiling is on.
 struct ProfScope {
   Profiler* p;
   hipStream_t st;
   Profiler::Rec r;
-  ProfScope(Profiler* prof, int fam, double flops, hipStream_t s) : p(prof && prof->on ? prof : nullptr), st(s) {
+  ProfScope(Profiler* prof, int fam, double flops, hipStream_t s, int launches = 1)
+      : p(prof && prof->on ? prof : nullptr), st(s) {
     if (!p) return;
     r.fam = fam;
+    r.n = launches;
     r.flops = flops;
     r.a = p->get();
     r.b = p->get();
@@ -86,7 +89,7 @@ hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm
 template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
                      const int* active, hipStream_t st, Profiler* prof, double* X = nullptr, int xmode = 0,
-                     int sched = kTrsmRows, int waves = 4);
+                     int sched = kTrsmRows, int waves = 4, const int* kstart = nullptr);
 
 // leafops.hip
 hipError_t launch_nodes(const Geom& g, const double* t, const double* h, int nbox, const double* origin, double* xi,
@@ -95,6 +98,9 @@ template <typename T>
 hipError_t launch_operators(const Geom& g, int nbox, const double* b, T* A, double* anorm, hipStream_t st);
 template <typename T>
 hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* maxb, hipStream_t st);
+// kstart [nbox][ldx/64]: first pivoted row at which each 64-column tile of [A_ib | f]
+// can be nonzero, rounded down to 64 (for the forward sweep of the first solve)
+hipError_t launch_rhs_first_row(const Geom& g, int nbox, const int* perm, int has_f, int* kstart, hipStream_t st);
 hipError_t residual_prepare(const Geom& g);
 hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const double* X, float* R32,
                            double* maxr, double* maxx, const int* active, hipStream_t st);

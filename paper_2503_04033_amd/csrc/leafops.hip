@@ -254,6 +254,50 @@ hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* ma
 template hipError_t launch_rhs<float>(const Geom&, int, const double*, float*, double*, hipStream_t);
 template hipError_t launch_rhs<double>(const Geom&, int, const double*, double*, double*, hipStream_t);
 
+// First pivoted row at which each 64-column tile of B = [A_ib | f] can be nonzero.
+// Column c < n_b belongs to face node c; its nonzeros in A_ib sit on the m interior
+// nodes of the grid line through that node normal to its face (the D2 coupling along
+// the line, Sec. 2.1), so after the row permutation its first nonzero is at
+// min over the line of pos[node], pos = perm^-1.  The f column counts as dense when f
+// is given; padding columns are zero.  The forward sweep L Y = P B leaves every row
+// of Y above this one exactly zero for the tile.  Rounded down to a multiple of 64.
+// One workgroup per box; pos lives in LDS.
+constexpr int kMaxPad = 5888;  // n_pad at p = 20 is 5856
+
+__global__ __launch_bounds__(256) void rhs_first_row_kernel(Geom g, int nbox, const int* perm_all, int has_f, int ntn,
+                                                            int* kstart) {
+  __shared__ int pos[kMaxPad];
+  __shared__ int tmin[64];
+  const int box = blockIdx.x;
+  const int N = g.n_pad, m = g.m, mm = m * m;
+  const int* perm = perm_all + (size_t)box * N;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) pos[perm[k]] = k;
+  for (int t = threadIdx.x; t < ntn; t += blockDim.x) tmin[t] = N;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ntn * 64; c += blockDim.x) {
+    int v = N;
+    if (c < g.nb) {
+      const int axis = c / (2 * mm), tq = c % mm;
+      const int t0 = tq % m, t1 = tq / m;
+      const int base = axis == 0 ? m * t0 + mm * t1 : (axis == 1 ? t0 + mm * t1 : t0 + m * t1);
+      const int stride = axis == 0 ? 1 : (axis == 1 ? m : mm);
+      for (int l = 0; l < m; l++) v = min(v, pos[base + l * stride]);
+    } else if (c == g.nb && has_f) {
+      v = 0;
+    }
+    atomicMin(&tmin[c >> 6], v);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntn; t += blockDim.x) kstart[(size_t)box * ntn + t] = tmin[t] / 64 * 64;
+}
+
+hipError_t launch_rhs_first_row(const Geom& g, int nbox, const int* perm, int has_f, int* kstart, hipStream_t st) {
+  const int ntn = g.ldx / 64;
+  if (g.n_pad > kMaxPad || ntn > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rhs_first_row_kernel, dim3(nbox), dim3(256), 0, st, g, nbox, perm, has_f, ntn, kstart);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------------------------
 // FP64 residual R = B - A_ii X through the tensor structure of A_ii (never a
 // dense FP64 A_ii): -A_ii X = s2x D2 X (along x) + s2y (along y) + s2z (along z)

@@ -471,8 +471,10 @@ constexpr int kTrsmSeg = 512;
 constexpr int kTrsmSegAbove = 4096;
 
 template <typename T, bool UPPER, bool SEG>
-__device__ __attribute__((always_inline)) inline void solve_block_row(const Geom& g, const T* F, const int* perm, const T* Inv, const T* B, T* Y,
-                                       double* Xb, int xmode, int s, int w, int nt, T* smem) {
+__device__ __attribute__((always_inline)) inline void solve_block_row(const Geom& g, const T* F, const int* perm,
+                                                                      const T* Inv, const T* B, T* Y, double* Xb,
+                                                                      int xmode, int s, int w, int nt, int ks,
+                                                                      T* smem) {
   typedef typename GemmCfg<T>::G G;
   static_assert(G::MT == 64 && G::NT == 64, "one 64 x 64 tile per workgroup");
   static_assert(G::SMEM >= 64 * kLeafLd, "Z must fit the GEMM staging buffer");
@@ -481,6 +483,18 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave % 2, wn = wave / 2;
   const int g4 = lane >> 4, c16 = lane & 15;
+  // Forward sweep: rows of the tile above ks (a multiple of 64) are exactly zero, so a
+  // block row that ends there is stored as zeros and the K range starts at ks.
+  if (!UPPER && s + w <= ks) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int r = wave * 16 + Mfma<T>::row(lane, i);
+        if (r < w) Y[(size_t)(s + r) * ld + nt + ct * 16 + c16] = T(0);
+      }
+    return;
+  }
   // The accumulator starts at R_j (rows past w: 0), so that no load waits after the K loop.
   typename G::acc_t acc[WRT][WCT];
 #pragma unroll
@@ -497,7 +511,7 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
   // acc -= F Y.  With SEG (FP32, long K) the running sum `part` is folded into acc every
   // kTrsmSeg values of k, so that no accumulator adds more than kTrsmSeg products in
   // sequence; the fold runs inside the K loop and keeps its pipeline going.
-  const int k0 = UPPER ? s + w : 0, k1 = UPPER ? N : s;
+  const int k0 = UPPER ? s + w : ks, k1 = UPPER ? N : s;
   if constexpr (!SEG) {
     G::run(acc, arow, brow, 64, k0, k1, smem);
   } else {
@@ -588,7 +602,7 @@ template <typename T, bool UPPER, bool SEG, int OCC>
 __global__ __launch_bounds__(256, OCC) void trsm_row_kernel(Geom g, const T* F_all, const int* perm_all,
                                                           const T* dinv_all, const T* B_all, T* Y_all, int s, int w,
                                                           int nbox, int ntn, const int* active, double* X_all,
-                                                          int xmode) {
+                                                          int xmode, const int* kstart) {
   typedef typename GemmCfg<T>::G G;
   __shared__ T smem[G::SMEM];
   int box, tn;
@@ -600,7 +614,8 @@ __global__ __launch_bounds__(256, OCC) void trsm_row_kernel(Geom g, const T* F_a
                  (UPPER ? 64 * 64 : 0);
   solve_block_row<T, UPPER, SEG>(g, F_all + (size_t)box * N * N, perm_all + (size_t)box * N, Inv,
                                  B_all + (size_t)box * xs, Y_all + (size_t)box * xs,
-                                 X_all ? X_all + (size_t)box * xs : nullptr, xmode, s, w, tn * 64, smem);
+                                 X_all ? X_all + (size_t)box * xs : nullptr, xmode, s, w, tn * 64,
+                                 kstart ? kstart[(size_t)box * ntn + tn] : 0, smem);
 }
 
 // One whole triangular sweep per workgroup: the right-hand-side columns of a box are
@@ -613,7 +628,8 @@ __global__ __launch_bounds__(256, OCC) void trsm_row_kernel(Geom g, const T* F_a
 template <typename T, bool UPPER, bool SEG, int OCC>
 __global__ __launch_bounds__(256, OCC) void trsm_sweep_kernel(Geom g, const T* F_all, const int* perm_all,
                                                             const T* dinv_all, const T* B_all, T* Y_all, int nbox,
-                                                            int ntn, const int* active, double* X_all, int xmode) {
+                                                            int ntn, const int* active, double* X_all, int xmode,
+                                                            const int* kstart) {
   typedef typename GemmCfg<T>::G G;
   __shared__ T smem[G::SMEM];
   int box, tn;
@@ -628,11 +644,12 @@ __global__ __launch_bounds__(256, OCC) void trsm_sweep_kernel(Geom g, const T* F
   const T* B = B_all + (size_t)box * xs;
   double* Xb = X_all ? X_all + (size_t)box * xs : nullptr;
   const int nblk = (N + kPanel - 1) / kPanel;
+  const int ks = kstart ? kstart[(size_t)box * ntn + tn] : 0;
 #pragma unroll 1
   for (int q = 0; q < nblk; q++) {
     const int jb = UPPER ? nblk - 1 - q : q;
     const int s = jb * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
-    solve_block_row<T, UPPER, SEG>(g, F, perm, dinv + (size_t)jb * 2 * 64 * 64, B, Y, Xb, xmode, s, w, tn * 64,
+    solve_block_row<T, UPPER, SEG>(g, F, perm, dinv + (size_t)jb * 2 * 64 * 64, B, Y, Xb, xmode, s, w, tn * 64, ks,
                                    smem);
     __syncthreads();  // Y_j stored before the next block row loads it
   }
@@ -726,18 +743,19 @@ hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm
 
 template <typename T, bool UPPER, bool SEG, int OCC>
 static hipError_t launch_sweep(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
-                               const int* active, hipStream_t st, double* X, int xmode, int sched) {
+                               const int* active, hipStream_t st, double* X, int xmode, int sched,
+                               const int* kstart) {
   const int ntn = g.ldx / 64, N = g.n_pad;
   if (sched == kTrsmSweep) {
     hipLaunchKernelGGL((trsm_sweep_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F,
-                       perm, dinv, B, Y, nbox, ntn, active, X, xmode);
+                       perm, dinv, B, Y, nbox, ntn, active, X, xmode, kstart);
     return hipGetLastError();
   }
   const int nblk = (N + kPanel - 1) / kPanel;
   for (int q = 0; q < nblk; q++) {
     const int s = (UPPER ? nblk - 1 - q : q) * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
     hipLaunchKernelGGL((trsm_row_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F,
-                       perm, dinv, B, Y, s, w, nbox, ntn, active, X, xmode);
+                       perm, dinv, B, Y, s, w, nbox, ntn, active, X, xmode, kstart);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -750,35 +768,42 @@ static hipError_t launch_sweep(const Geom& g, const T* F, const int* perm, const
 template <typename T, bool UPPER>
 static hipError_t dispatch_sweep(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y,
                                  int nbox, const int* active, hipStream_t st, double* X, int xmode, int sched,
-                                 int waves) {
+                                 int waves, const int* kstart) {
   if constexpr (sizeof(T) == 4) {
     if (g.n_pad > kTrsmSegAbove)
-      return launch_sweep<T, UPPER, true, 4>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched);
-    if (waves == 8) return launch_sweep<T, UPPER, false, 8>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched);
-    if (waves == 6) return launch_sweep<T, UPPER, false, 6>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched);
+      return launch_sweep<T, UPPER, true, 4>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched, kstart);
+    if (waves == 8)
+      return launch_sweep<T, UPPER, false, 8>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched, kstart);
+    if (waves == 6)
+      return launch_sweep<T, UPPER, false, 6>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched, kstart);
   }
-  return launch_sweep<T, UPPER, false, 4>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched);
+  return launch_sweep<T, UPPER, false, 4>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched, kstart);
 }
 
 // X = A^{-1} B for every active box: the forward sweep L Y = P B reads the rows of B
 // through perm, the backward sweep U X = Y works in place in Y (B and Y must not alias).
 // sched: kTrsmRows (one launch per block row) or kTrsmSweep (one launch per sweep);
-// waves: FP32 occupancy target (see dispatch_sweep).
+// waves: FP32 occupancy target (see dispatch_sweep).  kstart (may be null): per (box,
+// 64-column tile), a multiple of 64 above which every row of P B is zero (the forward
+// sweep skips those rows; the flops recorded stay the dense count).
 template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
-                     const int* active, hipStream_t st, Profiler* prof, double* X, int xmode, int sched, int waves) {
+                     const int* active, hipStream_t st, Profiler* prof, double* X, int xmode, int sched, int waves,
+                     const int* kstart) {
   const double N = g.n_pad, nrhs = g.nb + 1;
   // per sweep: sum over block rows of 2 w K + w^2 = N^2 per right-hand side
   const double flops = N * N * nrhs * nbox;
+  const int nlaunch = sched == kTrsmSweep ? 1 : (g.n_pad + kPanel - 1) / kPanel;
   hipError_t e;
   {
-    ProfScope ps(prof, Profiler::kSolveFwd, flops, st);
-    e = dispatch_sweep<T, false>(g, F, perm, dinv, B, Y, nbox, active, st, nullptr, 0, sched, waves);
+    ProfScope ps(prof, Profiler::kSolveFwd, flops, st, nlaunch);
+    e = dispatch_sweep<T, false>(g, F, perm, dinv, B, Y, nbox, active, st, nullptr, 0, sched, waves, kstart);
   }
   if (e != hipSuccess) return e;
   {
-    ProfScope ps(prof, Profiler::kSolveBwd, flops, st);
-    e = dispatch_sweep<T, true>(g, F, perm, dinv, Y, Y, nbox, active, st, xmode ? X : nullptr, xmode, sched, waves);
+    ProfScope ps(prof, Profiler::kSolveBwd, flops, st, nlaunch);
+    e = dispatch_sweep<T, true>(g, F, perm, dinv, Y, Y, nbox, active, st, xmode ? X : nullptr, xmode, sched, waves,
+                                nullptr);
   }
   return e;
 }
@@ -788,9 +813,9 @@ template hipError_t getrf_run<double>(const Geom&, const std::vector<int>&, doub
                                       hipStream_t, Profiler*);
 template hipError_t getrs_run<float>(const Geom&, const float*,
                                      const int*, const float*, const float*, float*, int, const int*, hipStream_t,
-                                     Profiler*, double*, int, int, int);
+                                     Profiler*, double*, int, int, int, const int*);
 template hipError_t getrs_run<double>(const Geom&, const double*,
                                       const int*, const double*, const double*, double*, int, const int*,
-                                      hipStream_t, Profiler*, double*, int, int, int);
+                                      hipStream_t, Profiler*, double*, int, int, int, const int*);
 
 }  // namespace hps

@@ -54,7 +54,7 @@ def gpu_leaf_boxes(prob, box_ids, precision="fp64", ir_max_iter=3, ir_tol=1e-11,
             "iters": bufs["ir_iters"].cpu().numpy(), "berr": bufs["berr"].cpu().numpy(),
             "A0": A0.view(nb, i.n_pad, i.n_pad).cpu().numpy(),
             "LU": bufs["A"].view(nb, i.n_pad, i.n_pad).cpu().numpy(),
-            "perm": bufs["perm"].view(nb, i.n_pad).cpu().numpy(), "plan": plan, "xi": xi}
+            "perm": bufs["perm"].view(nb, i.n_pad).cpu().numpy(), "plan": plan, "xi": xi, "ws": bufs["ws"]}
 
 
 def oracle_leaf_boxes(prob, box_ids, f_on=True):

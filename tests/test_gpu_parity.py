@@ -74,6 +74,31 @@ def test_trsm_schedules(gpu, precision, case):
     assert plan.hps_plan_get_tuning("trsm_schedule") == 0 and plan.hps_plan_get_tuning("trsm_waves") == 8
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_first_nonzero_rows_of_rhs(gpu, precision):
+    # The forward sweep of the first solve skips, per 64-column tile of B = [A_ib | f],
+    # the leading rows of P B that are zero.  The tile starts the library computed
+    # (white box: they sit in the workspace after the per-box scalars) must equal the
+    # structure of the oracle's A_ib under the factor's row permutation (the f column
+    # counts as dense), rounded down to 64.
+    prob = W.multi_bump((1, 1, 2), 12, 8.0, 13, gaussian_source=True, name="skip_p12")
+    out = _check_leaf(prob, [0, 1], precision, FP64_TOL if precision == "fp64" else IR_TOL)
+    i = out["plan"].info
+    nb, ntn = 2, i.ldx // 64
+    off = 8 * i.n_pad * i.ldx * nb + 64 * nb
+    ks = out["ws"].view(torch.uint8)[off:off + 4 * ntn * nb].view(torch.int32).view(nb, ntn).cpu().numpy()
+    for k, (blk, _) in enumerate(oracle_leaf_boxes(prob, [0, 1])):
+        B = np.zeros((i.n_pad, i.ldx))
+        B[:i.n_i, :i.n_b] = blk.A_ib
+        PB = B[out["perm"][k]] != 0
+        first = np.where(PB.any(axis=0), PB.argmax(axis=0), i.n_pad)
+        first[i.n_b] = 0
+        want = first.reshape(ntn, 64).min(axis=1) // 64 * 64
+        say(f"  box {k}: tile starts {ks[k].tolist()}")
+        assert np.array_equal(ks[k], want)
+        assert ks[k].max() > 0  # at p = 12 some tiles start below the top
+
+
 def test_factorization_property(gpu):
     # P A = L U for the stored factors (any valid pivot sequence), FP64, ragged last panel
     prob = W.multi_bump((1, 1, 2), 9, 8.0, 13, name="lu_p9")
