@@ -328,7 +328,9 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     }
   }
   hps::ProfScope ps(&pl->prof, hps::Profiler::kDtn, 0.0, st);
-  return dev(hps::launch_dtn(g, nbox, X, g_dir, slot_map, T_vals, gload, st));
+  // the right-hand-side region of the workspace is free again: the column-block sums of
+  // the loads go there
+  return dev(hps::launch_dtn(g, nbox, X, g_dir, slot_map, T_vals, gload, static_cast<double*>(L.B), st));
 }
 
 hps_status hps_interface_reduce(int32_t npairs, const int64_t* pairs, int64_t block_elems, double* T_vals,

@@ -109,8 +109,10 @@ hipError_t launch_ir_check(int nbox, int it, int last, double tol, const double*
                            hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_fill_int(int* p, int value, size_t count, hipStream_t st);
+// a4: T and the lifted loads; part: scratch of dtn_part_bytes(g, nbox) bytes
 hipError_t launch_dtn(const Geom& g, int nbox, const double* X, const double* gdir, const int* slot_map,
-                      double* T_vals, double* gload, hipStream_t st);
+                      double* T_vals, double* gload, double* part, hipStream_t st);
+size_t dtn_part_bytes(const Geom& g, int nbox);
 hipError_t launch_reduce(int npairs, const long long* pairs, long long block_elems, double* T_vals, hipStream_t st);
 hipError_t launch_reconstruct(const Geom& g, int nbox, const double* X, const double* ub, double* ui,
                               hipStream_t st);

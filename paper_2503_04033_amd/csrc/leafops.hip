@@ -703,86 +703,199 @@ hipError_t launch_ir_check(int nbox, int it, int last, double tol, const double*
 
 // ----------------------------------------------------------------------------
 // a4: DtN rows and loads (Sec. 3.1 eq. t-block, Alg. 1; Alg. 2 load loop).
-// One wave per normal line (axis, tangential q): the two face rows at its ends.
-//   face x- row: outward derivative -(2/h) sum_l D[0][l] u_l
-//   face x+ row: +(2/h) sum_l D[p-1][l] u_l
-//   T = A_bb - A_bi X_b,  g = -A_bi X_f - sum_{boundary faces b} T[:, b] g_dir[b].
+// Face row (face a of axis d, tangential q) is the outward normal derivative along the
+// line through its node:
+//   face d- row: -(2/h_d) sum_l D[0][l] u_l,    face d+ row: +(2/h_d) sum_l D[p-1][l] u_l
+// so  T = A_bb - A_bi X_b  and  g = -A_bi X_f - sum_{Dirichlet faces b} T[:, b] g_dir[b].
+// One workgroup per (box, block of kDtnCols columns of X) streams X one z-plane at a
+// time through LDS, so every element of X is read from HBM once: the x- and y-lines of
+// a plane are summed from LDS, the z-lines accumulate in registers over the planes.
+// The Dirichlet and load columns of a face row are summed per column block into
+// `part` [nbox][ncb][n_b]; dtn_lift_kernel adds the blocks in a fixed order.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void dtn_kernel(Geom g, int nbox, const double* X_all, const double* gdir,
-                                                  const int* slot_map, double* T_vals, double* gload) {
-  const int box = blockIdx.y;
-  const int m = g.m, mm = m * m, p = g.p, nb = g.nb, ldx = g.ldx;
-  const int line = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (line >= 3 * mm) return;
-  const int axis = line / mm, q = line % mm;
-  const int a_minus = 2 * axis, a_plus = 2 * axis + 1;
-  const int* smap = slot_map + box * 36;
-  const bool do_minus = smap[a_minus * 6 + a_minus] >= 0;
-  const bool do_plus = smap[a_plus * 6 + a_plus] >= 0;
-  const int row_m = a_minus * mm + q, row_p = a_plus * mm + q;
-  if (!do_minus && !do_plus) {
-    if (lane == 0) { gload[(size_t)box * nb + row_m] = 0.0; gload[(size_t)box * nb + row_p] = 0.0; }
-    return;
-  }
-  // interior nodes on the line
-  const int t0 = q % m, t1 = q / m;
-  int base, stride;
-  if (axis == 0) { base = m * t0 + mm * t1; stride = 1; }
-  else if (axis == 1) { base = t0 + mm * t1; stride = m; }
-  else { base = t0 + m * t1; stride = mm; }
-  const double* X = X_all + (size_t)box * g.n_pad * ldx;
+constexpr int kDtnCols = 16;
+constexpr int kDtnLd = kDtnCols + 1;       // LDS row stride (doubles)
+
+struct DtnCtx {
+  Geom g;
+  const double* gdir;
+  const int* smap;  // this box's 36 slots
+  double* T_vals;
+  int c, box_nb;    // this lane's column (c < nb + 1 valid), n_b
+  bool valid;
+};
+
+// Value of face row (face a, tangential q) at this lane's column from the line sum
+// xs_ = sum_l D[end][l+1] X[line node l][c]; returns the lane's contribution to the
+// row's lift (load column or Dirichlet column), and writes T where it is stored.
+__device__ inline double dtn_entry(const DtnCtx& k, int a, int q, double xs_, int mm) {
+  if (!k.valid) return 0.0;
+  const Geom& g = k.g;
+  const int axis = a >> 1, side = a & 1, p = g.p;
   const double s1 = g.s1[axis];
-  const double* D0 = g.D;                  // D[0][.]
-  const double* D1 = g.D + (size_t)(p - 1) * p;  // D[p-1][.]
-  const size_t m4 = (size_t)mm * mm;
-  double lift_m = 0.0, lift_p = 0.0;
-  for (int c = lane; c < nb + 1; c += 64) {
-    double xm = 0.0, xp = 0.0;
-    for (int l = 0; l < m; l++) {
-      const double xv = X[(size_t)(base + l * stride) * ldx + c];
-      xm += D0[l + 1] * xv;
-      xp += D1[l + 1] * xv;
+  const double* Dend = g.D + (size_t)(side ? p - 1 : 0) * p;
+  const int row_m = 2 * axis * mm + q, row_p = row_m + mm;
+  if (k.c == k.box_nb) return side ? -s1 * xs_ : s1 * xs_;  // g = -A_bi v
+  double t = side ? -s1 * xs_ : s1 * xs_;                   // -A_bi X_b
+  const double sg = side ? s1 : -s1;                        // A_bb: outward derivative ends
+  if (k.c == row_m) t += sg * Dend[0];
+  if (k.c == row_p) t += sg * Dend[p - 1];
+  const int b = k.c / mm, qc = k.c - b * mm;
+  if (k.smap[b * 6 + b] < 0) {  // Dirichlet column: moves to the load
+    const double gd = k.gdir ? k.gdir[k.c] : 0.0;
+    return -t * gd;
+  }
+  if (k.smap[a * 6 + a] >= 0) {
+    const int sl = k.smap[a * 6 + b];
+    if (sl >= 0) k.T_vals[(size_t)sl * mm * mm + (size_t)q * mm + qc] = t;
+  }
+  return 0.0;
+}
+
+// Sum over the 16 lanes of a column group (lanes 16j .. 16j+15 of a wave).
+__device__ inline double group16_sum(double v) {
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void dtn_kernel(Geom g, int nbox, int ncb, const double* X_all, const double* gdir,
+                                                  const int* slot_map, double* T_vals, double* part) {
+  constexpr int mm = M * M;
+  constexpr int ZL = (mm + 15) / 16;  // plane rows (and z-lines) per thread
+  __shared__ double xs[mm * kDtnLd];
+  __shared__ double dd[2][M];  // D[0][l+1] and D[p-1][l+1]: outward derivative weights
+  const int box = blockIdx.y, cb = blockIdx.x;
+  const int p = g.p, nb = g.nb, ldx = g.ldx;
+  const int cl = threadIdx.x & 15, sub = threadIdx.x >> 4;  // column lane, row group
+  DtnCtx k;
+  k.g = g;
+  k.gdir = gdir ? gdir + (size_t)box * nb : nullptr;
+  k.smap = slot_map + box * 36;
+  k.T_vals = T_vals;
+  k.c = cb * kDtnCols + cl;
+  k.box_nb = nb;
+  k.valid = k.c <= nb;
+  // column c < ldx for every lane (ncb * 16 <= ldx), so loads need no guard; rows past
+  // the plane reread its last row
+  const double* X = X_all + (size_t)box * g.n_pad * ldx + cb * kDtnCols + cl;
+  double* pb = part + ((size_t)box * ncb + cb) * nb;
+  const double* D0 = g.D;
+  const double* D1 = g.D + (size_t)(p - 1) * p;
+  for (int e = threadIdx.x; e < 2 * M; e += blockDim.x) dd[e / M][e % M] = (e < M ? D0 : D1)[e % M + 1];
+  double zm[ZL], zp[ZL], pre[ZL];
+#pragma unroll
+  for (int u = 0; u < ZL; u++) {
+    zm[u] = zp[u] = 0.0;
+    const int t = min(sub + 16 * u, mm - 1);
+    pre[u] = X[(size_t)t * ldx];
+  }
+  for (int kk = 0; kk < M; kk++) {
+    __syncthreads();  // the previous plane is consumed
+#pragma unroll
+    for (int u = 0; u < ZL; u++) {
+      const int t = sub + 16 * u;
+      if (t < mm) xs[t * kDtnLd + cl] = k.valid ? pre[u] : 0.0;
     }
-    if (c == nb) {  // load column: g = -A_bi v
-      lift_m += s1 * xm;
-      lift_p += -s1 * xp;
-      continue;
-    }
-    double tm = s1 * xm, tp = -s1 * xp;  // -A_bi X_b
-    if (c == row_m) { tm += -s1 * D0[0]; tp += s1 * D1[0]; }
-    if (c == row_p) { tm += -s1 * D0[p - 1]; tp += s1 * D1[p - 1]; }
-    const int b = c / mm, qc = c - b * mm;
-    const bool bdir = smap[b * 6 + b] < 0;
-    if (bdir) {
-      const double gd = gdir ? gdir[(size_t)box * nb + c] : 0.0;
-      lift_m -= tm * gd;
-      lift_p -= tp * gd;
-    } else {
-      if (do_minus) {
-        const int sl = smap[a_minus * 6 + b];
-        if (sl >= 0) T_vals[(size_t)sl * m4 + (size_t)q * mm + qc] = tm;
+    __syncthreads();
+    if (kk + 1 < M) {  // the next plane is in flight while this one is used
+#pragma unroll
+      for (int u = 0; u < ZL; u++) {
+        const int t = min(sub + 16 * u, mm - 1);
+        pre[u] = X[(size_t)((kk + 1) * mm + t) * ldx];
       }
-      if (do_plus) {
-        const int sl = smap[a_plus * 6 + b];
-        if (sl >= 0) T_vals[(size_t)sl * m4 + (size_t)q * mm + qc] = tp;
+    }
+    // z-lines (ii, jj) = plane row zl: this thread owns zl = sub + 16 u
+    const double d0 = dd[0][kk], d1 = dd[1][kk];
+#pragma unroll
+    for (int u = 0; u < ZL; u++) {
+      const int zl = sub + 16 * u;
+      if (zl < mm) {
+        const double x = xs[zl * kDtnLd + cl];
+        zm[u] += d0 * x;
+        zp[u] += d1 * x;
+      }
+    }
+    // x-lines (jj fixed, ii runs) and y-lines (ii fixed, jj runs) of this plane
+    for (int j = sub; j < M; j += 16) {
+      double xm = 0.0, xp = 0.0, ym = 0.0, yp = 0.0;
+#pragma unroll 2
+      for (int l = 0; l < M; l++) {
+        const double a0 = dd[0][l], a1 = dd[1][l];
+        const double vx = xs[(l + M * j) * kDtnLd + cl];  // node (ii = l, jj = j)
+        const double vy = xs[(j + M * l) * kDtnLd + cl];  // node (ii = j, jj = l)
+        xm += a0 * vx;
+        xp += a1 * vx;
+        ym += a0 * vy;
+        yp += a1 * vy;
+      }
+      const int q = j + M * kk;
+      const double lxm = group16_sum(dtn_entry(k, 0, q, xm, mm));
+      const double lxp = group16_sum(dtn_entry(k, 1, q, xp, mm));
+      const double lym = group16_sum(dtn_entry(k, 2, q, ym, mm));
+      const double lyp = group16_sum(dtn_entry(k, 3, q, yp, mm));
+      if (cl == 0) {
+        pb[0 * mm + q] = lxm;
+        pb[1 * mm + q] = lxp;
+        pb[2 * mm + q] = lym;
+        pb[3 * mm + q] = lyp;
       }
     }
   }
-  lift_m = wave_sum(lift_m);
-  lift_p = wave_sum(lift_p);
-  if (lane == 0) {
-    gload[(size_t)box * nb + row_m] = do_minus ? lift_m : 0.0;
-    gload[(size_t)box * nb + row_p] = do_plus ? lift_p : 0.0;
+#pragma unroll
+  for (int u = 0; u < ZL; u++) {
+    const int zl = sub + 16 * u;
+    if (zl < mm) {
+      const double lzm = group16_sum(dtn_entry(k, 4, zl, zm[u], mm));
+      const double lzp = group16_sum(dtn_entry(k, 5, zl, zp[u], mm));
+      if (cl == 0) {
+        pb[4 * mm + zl] = lzm;
+        pb[5 * mm + zl] = lzp;
+      }
+    }
   }
 }
 
+// gload[box][row] = sum over column blocks of part (fixed order); 0 on Dirichlet faces.
+__global__ void dtn_lift_kernel(int nb, int mm, int nbox, int ncb, const int* slot_map, const double* part,
+                                double* gload) {
+  const int box = blockIdx.y;
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nb) return;
+  const int a = row / mm;
+  double s = 0.0;
+  if (slot_map[box * 36 + a * 6 + a] >= 0) {
+    const double* pb = part + (size_t)box * ncb * nb + row;
+    for (int cb = 0; cb < ncb; cb++) s += pb[(size_t)cb * nb];
+  }
+  gload[(size_t)box * nb + row] = s;
+}
+
 hipError_t launch_dtn(const Geom& g, int nbox, const double* X, const double* gdir, const int* slot_map,
-                      double* T_vals, double* gload, hipStream_t st) {
-  const int lines = 3 * g.m * g.m;
-  hipLaunchKernelGGL(dtn_kernel, dim3((lines + 3) / 4, nbox), dim3(256), 0, st, g, nbox, X, gdir, slot_map, T_vals,
-                     gload);
+                      double* T_vals, double* gload, double* part, hipStream_t st) {
+  const int ncb = (g.nb + 1 + kDtnCols - 1) / kDtnCols;
+  const dim3 grid(ncb, nbox);
+  switch (g.m) {
+#define HPS_DTN_CASE(M)                                                                                      case M:                                                                                                      hipLaunchKernelGGL(dtn_kernel<M>, grid, dim3(256), 0, st, g, nbox, ncb, X, gdir, slot_map, T_vals, part);     break;
+    HPS_DTN_CASE(2) HPS_DTN_CASE(3) HPS_DTN_CASE(4) HPS_DTN_CASE(5) HPS_DTN_CASE(6) HPS_DTN_CASE(7)
+    HPS_DTN_CASE(8) HPS_DTN_CASE(9) HPS_DTN_CASE(10) HPS_DTN_CASE(11) HPS_DTN_CASE(12) HPS_DTN_CASE(13)
+    HPS_DTN_CASE(14) HPS_DTN_CASE(15) HPS_DTN_CASE(16) HPS_DTN_CASE(17) HPS_DTN_CASE(18)
+#undef HPS_DTN_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dtn_lift_kernel, dim3((g.nb + 255) / 256, nbox), dim3(256), 0, st, g.nb, g.m * g.m, nbox, ncb,
+                     slot_map, part, gload);
   return hipGetLastError();
+}
+
+// bytes of `part` for nbox boxes
+size_t dtn_part_bytes(const Geom& g, int nbox) {
+  const size_t ncb = (g.nb + 1 + kDtnCols - 1) / kDtnCols;
+  return 8 * ncb * g.nb * (size_t)nbox;
 }
 
 // T_vals[dst] += T_vals[src] for each (dst, src) pair; every dst appears once.

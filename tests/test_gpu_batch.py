@@ -116,3 +116,26 @@ def test_autotune_config4(gpu, tmp_path):
     for q in range(len(probs)):
         for a, b in zip(runs[0][q], runs[1][q]):
             assert torch.equal(a, b), f"group {q}: tuned run differs"
+
+
+def test_full_size_config3_sampled(gpu):
+    # The headline workload at full size in the launch configuration the benchmark times
+    # (16^3 boxes, p = 16, FP32 + refinement, chunks of 1024 boxes, f = 0 passed as null):
+    # every box factors and converges; sampled boxes (corner, edge, interior, last)
+    # against the oracle: off-diagonal DtN blocks and lifted loads, bar 1e-9.
+    from paper_2503_04033_amd.batch import BatchedLeafReduction
+    prob = W.config3()
+    br = BatchedLeafReduction([prob], "fp32_ir", chunks=[1024])
+    br.sample_inputs(0, prob)
+    gr = br.groups[0]
+    br.set_inputs(0, gr.b, None, gr.g_dir)
+    br.allocate()
+    say(f"full size: {prob.nbox} boxes, chunk {gr.chunk}")
+    br.run()
+    torch.cuda.synchronize()
+    assert int((gr.info != 0).sum()) == 0
+    it = gr.iters.cpu().numpy()
+    say(f"  refinement steps: {np.bincount(it[it >= 0]).tolist()}, unconverged {(it < 0).sum()}")
+    assert it.min() >= 0
+    n1 = prob.nboxes[0]
+    _check_group(br, 0, prob, [0, n1 - 1, 8 + n1 * (8 + n1 * 8), prob.nbox - 1])
