@@ -1,4 +1,5 @@
 // extern "C" entry points of libhps_leaf (declared in include/hps_leaf.h).
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -195,9 +196,32 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
   pl->t = pl->tables;
   g.D = pl->tables + g.p;
   g.D2 = pl->tables + g.p + (size_t)g.p * g.p;
-  std::vector<int> coords(g.n);
+  const int ngrp = g.ldx / 16;
+  std::vector<int> coords(g.n + 2 * (size_t)ngrp);
   for (int node = 0; node < g.n; node++)
     coords[node] = (node % g.m) | (((node / g.m) % g.m) << 8) | ((node / (g.m * g.m)) << 16);
+  // Internal order of the right-hand-side columns of FP32_IR plans: 16-column groups
+  // sorted by the first interior row their A_ib columns touch (the first node of the
+  // face node's normal line), so that a 64-column tile of the first forward sweep holds
+  // columns with alike runs of leading zero rows (see the first-row kernel).  The f
+  // column counts as touching row 0.  FP64 plans solve in place in X: natural order.
+  {
+    const int m = g.m, mm = m * m;
+    std::vector<int> first(ngrp, g.n_pad), order(ngrp);
+    for (int c = 0; c < g.nb; c++) {
+      const int axis = c / (2 * mm), tq = c % mm, t0 = tq % m, t1 = tq / m;
+      const int base = axis == 0 ? m * t0 + mm * t1 : (axis == 1 ? t0 + mm * t1 : t0 + m * t1);
+      first[c / 16] = std::min(first[c / 16], base);
+    }
+    first[g.nb / 16] = 0;
+    for (int i = 0; i < ngrp; i++) order[i] = i;
+    if (d->precision == HPS_FP32_IR)
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return first[a] < first[b]; });
+    for (int i = 0; i < ngrp; i++) {
+      coords[g.n + i] = order[i];
+      coords[g.n + ngrp + order[i]] = i;
+    }
+  }
   if (hipMalloc(&pl->coords, coords.size() * sizeof(int)) != hipSuccess) {
     (void)hipFree(pl->tables);
     delete pl;
@@ -210,6 +234,8 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
     return HPS_EDEVICE;
   }
   g.coords = pl->coords;
+  g.gmap = pl->coords + g.n;
+  g.ginv = pl->coords + g.n + ngrp;
   sched_lu(pl->lu_ops, 0, g.n_pad, g.n_pad);
   if (hps::residual_prepare(g) != hipSuccess) {
     (void)hipFree(pl->coords);

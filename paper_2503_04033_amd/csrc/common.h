@@ -76,7 +76,15 @@ struct Geom {
   const double* D;     // [p][p] Gauss-Lobatto differentiation matrix on [-1,1]
   const double* D2;    // [p][p] D*D
   const int* coords;   // [n] interior node -> ii | jj << 8 | kk << 16
+  // Right-hand-side columns inside the solves (B, Y, the FP32 residual) are kept in 16-column
+  // groups in an internal order; X and everything outside the solves use the natural one.
+  const int* gmap;     // [ldx/16] internal group -> natural group
+  const int* ginv;     // [ldx/16] natural group -> internal group
 };
+
+// internal position of natural right-hand-side column c, and back
+__device__ inline int rhs_icol(const Geom& g, int c) { return g.ginv[c >> 4] * 16 + (c & 15); }
+__device__ inline int rhs_ncol(const Geom& g, int ic) { return g.gmap[ic >> 4] * 16 + (ic & 15); }
 
 // Schedule record kinds for the recursive LU and solves (record = {kind, a1..a7}):
 //   kOpPanel {c0, w}                 factor columns [c0, c0+w) (w <= 64)

@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void rhs_kernel(Geom g, int nbox, const double
       col = t * mm + tq;
       v = -g.s2[axis] * g.D2[(along + 1) * p + (side ? p - 1 : 0)];
     }
-    B[(size_t)r * ldx + col] = (T)v;
+    B[(size_t)r * ldx + rhs_icol(g, col)] = (T)v;
     mx = fmax(mx, fabs(v));
   }
   mx = wave_max(mx);
@@ -254,7 +254,8 @@ hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* ma
 template hipError_t launch_rhs<float>(const Geom&, int, const double*, float*, double*, hipStream_t);
 template hipError_t launch_rhs<double>(const Geom&, int, const double*, double*, double*, hipStream_t);
 
-// First pivoted row at which each 64-column tile of B = [A_ib | f] can be nonzero.
+// First pivoted row at which each 64-column tile of B = [A_ib | f] (columns in the
+// solves' internal order, see Geom) can be nonzero.
 // Column c < n_b belongs to face node c; its nonzeros in A_ib sit on the m interior
 // nodes of the grid line through that node normal to its face (the D2 coupling along
 // the line, Sec. 2.1), so after the row permutation its first nonzero is at
@@ -274,7 +275,8 @@ __global__ __launch_bounds__(256) void rhs_first_row_kernel(Geom g, int nbox, co
   for (int k = threadIdx.x; k < N; k += blockDim.x) pos[perm[k]] = k;
   for (int t = threadIdx.x; t < ntn; t += blockDim.x) tmin[t] = N;
   __syncthreads();
-  for (int c = threadIdx.x; c < ntn * 64; c += blockDim.x) {
+  for (int ic = threadIdx.x; ic < ntn * 64; ic += blockDim.x) {  // internal column order
+    const int c = rhs_ncol(g, ic);
     int v = N;
     if (c < g.nb) {
       const int axis = c / (2 * mm), tq = c % mm;
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(256) void rhs_first_row_kernel(Geom g, int nbox, co
     } else if (c == g.nb && has_f) {
       v = 0;
     }
-    atomicMin(&tmin[c >> 6], v);
+    atomicMin(&tmin[ic >> 6], v);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < ntn; t += blockDim.x) kstart[(size_t)box * ntn + t] = tmin[t] / 64 * 64;
@@ -379,7 +381,7 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox,
       bv = f[(size_t)box * n + node];
     }
     const double r = bv + g.s2[0] * ax + g.s2[1] * ay + g.s2[2] * az + g.kappa2 * bb[node] * xv;
-    if (R32) R32[(size_t)node * ldx + col] = (float)r;
+    if (R32) R32[(size_t)node * ldx + rhs_icol(g, col)] = (float)r;
     mr = fmax(mr, fabs(r));
     mxv = fmax(mxv, fabs(xv));
   }
@@ -616,7 +618,7 @@ __global__ __launch_bounds__(kRmThreads) void residual_mfma_kernel(Geom g, int n
       for (int t = threadIdx.x; t < nk * mm * V; t += kRmThreads) {
         const int row = t / V, h = t % V;  // row = (slab - k0) * m^2 + r
         const f4 v = *reinterpret_cast<const f4*>(O + row * CB + 4 * h);
-        *reinterpret_cast<f4*>(R32 + (size_t)(k0 * mm + row) * ldx + c0 + 4 * h) = v;
+        *reinterpret_cast<f4*>(R32 + (size_t)(k0 * mm + row) * ldx + rhs_icol(g, c0) + 4 * h) = v;
       }
     }
   }

@@ -558,7 +558,7 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
 #pragma unroll
       for (int i = 0; i < 4; i++) {
         const int r = wave * 16 + Mfma<T>::row(lane, i);
-        xo[ct][i] = r < w ? Xb[(size_t)(s + r) * ld + nt + ct * 16 + c16] : 0.0;
+        xo[ct][i] = r < w ? Xb[(size_t)(s + r) * ld + g.gmap[(nt >> 4) + ct] * 16 + c16] : 0.0;
       }
   }
   __syncthreads();
@@ -589,9 +589,10 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
     for (int i = 0; i < 4; i++) {
       const int r = wave * 16 + Mfma<T>::row(lane, i);
       if (r < w) {
-        const size_t e = (size_t)(s + r) * ld + nt + ct * 16 + c16;
-        Y[e] = out[ct][i];
-        if (Xb) Xb[e] = xadd ? xo[ct][i] + (double)out[ct][i] : (double)out[ct][i];
+        Y[(size_t)(s + r) * ld + nt + ct * 16 + c16] = out[ct][i];
+        // X is in the natural column order
+        const size_t ex = (size_t)(s + r) * ld + g.gmap[(nt >> 4) + ct] * 16 + c16;
+        if (Xb) Xb[ex] = xadd ? xo[ct][i] + (double)out[ct][i] : (double)out[ct][i];
       }
     }
 }

@@ -80,7 +80,9 @@ def test_first_nonzero_rows_of_rhs(gpu, precision):
     # the leading rows of P B that are zero.  The tile starts the library computed
     # (white box: they sit in the workspace after the per-box scalars) must equal the
     # structure of the oracle's A_ib under the factor's row permutation (the f column
-    # counts as dense), rounded down to 64.
+    # counts as dense), rounded down to 64.  Tiles hold the columns in the solves'
+    # internal order: FP64 natural; FP32 + refinement 16-column groups stably sorted by
+    # the first row their (unpermuted) A_ib columns touch, the f column's group first.
     prob = W.multi_bump((1, 1, 2), 12, 8.0, 13, gaussian_source=True, name="skip_p12")
     out = _check_leaf(prob, [0, 1], precision, FP64_TOL if precision == "fp64" else IR_TOL)
     i = out["plan"].info
@@ -93,6 +95,14 @@ def test_first_nonzero_rows_of_rhs(gpu, precision):
         PB = B[out["perm"][k]] != 0
         first = np.where(PB.any(axis=0), PB.argmax(axis=0), i.n_pad)
         first[i.n_b] = 0
+        order = np.arange(i.ldx // 16)
+        if precision == "fp32_ir":
+            nz = blk.A_ib != 0
+            f0 = np.full(i.ldx, i.n_pad)
+            f0[:i.n_b] = nz.argmax(axis=0)
+            f0[i.n_b] = 0
+            order = np.argsort(f0.reshape(-1, 16).min(axis=1), kind="stable")
+        first = first.reshape(-1, 16)[order].reshape(-1)
         want = first.reshape(ntn, 64).min(axis=1) // 64 * 64
         say(f"  box {k}: tile starts {ks[k].tolist()}")
         assert np.array_equal(ks[k], want)
