@@ -495,20 +495,16 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
       }
     return;
   }
-  // The accumulator starts at R_j (rows past w: 0), so that no load waits after the K loop.
+  // acc = -F Y first, R_j added once at the end: every rounding of the K loop is relative
+  // to the running sum of products, not to R_j (this matters where the two cancel)
   typename G::acc_t acc[WRT][WCT];
 #pragma unroll
   for (int rt = 0; rt < WRT; rt++)
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int r = (wm * WRT + rt) * 16 + Mfma<T>::row(lane, i);
-      const T* rr = r < w ? (UPPER ? Y + (size_t)(s + r) * ld : B + (size_t)perm[s + r] * ld) + nt : nullptr;
-#pragma unroll
-      for (int ct = 0; ct < WCT; ct++) acc[rt][ct][i] = rr ? rr[(wn * WCT + ct) * 16 + c16] : T(0);
-    }
+    for (int ct = 0; ct < WCT; ct++) acc[rt][ct] = Mfma<T>::zero();
   auto arow = [&](int r) -> const T* { return r < w ? F + (size_t)perm[s + r] * N : nullptr; };
   auto brow = [&](int k) -> const T* { return Y + (size_t)k * ld + nt; };
-  // acc -= F Y.  With SEG (FP32, long K) the running sum `part` is folded into acc every
+  // With SEG (FP32, long K) the running sum `part` is folded into acc every
   // kTrsmSeg values of k, so that no accumulator adds more than kTrsmSeg products in
   // sequence; the fold runs inside the K loop and keeps its pipeline going.
   const int k0 = UPPER ? s + w : ks, k1 = UPPER ? N : s;
@@ -541,8 +537,12 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const int r = (wm * WRT + rt) * 16 + Mfma<T>::row(lane, i);
+      const T* rr = r < w ? (UPPER ? Y + (size_t)(s + r) * ld : B + (size_t)perm[s + r] * ld) + nt : nullptr;
 #pragma unroll
-      for (int ct = 0; ct < WCT; ct++) zs[r * kLeafLd + (wn * WCT + ct) * 16 + c16] = acc[rt][ct][i];
+      for (int ct = 0; ct < WCT; ct++) {
+        const int c = (wn * WCT + ct) * 16 + c16;
+        zs[r * kLeafLd + c] = rr ? rr[c] + acc[rt][ct][i] : T(0);
+      }
     }
   // Y_j = Inv_j Z: the wave's 16 rows of the inverse (columns past w zeroed) times all 64
   // columns of Z, the inverse read one 16-column chunk ahead; for X += Y (xmode 2) the
