@@ -211,9 +211,13 @@ hps_status hps_leaf_adjoint_grad(hps_plan plan, int32_t nbox, const double* lam_
  *     default 4) the solve kernels are register-allocated for, i.e. how many of
  *     their workgroups one CU keeps resident.  FP64 plans and p >= 19 always run
  *     at 4; the value is accepted and ignored there.
+ *   HPS_TUNE_RESIDUAL_COLS: the FP64 refinement residual of FP32_IR plans (the
+ *     Alg. 1 solves, refined), 6 <= p <= 18: right-hand-side columns per workgroup,
+ *     8 (1024 threads, default) or 4 (512 threads, two workgroups per CU).  Other p
+ *     use one kernel and ignore the value.
  * set: HPS_EINVAL for an unknown key or value (the plan is left unchanged);
  * get: writes the current value to *value. */
-typedef enum { HPS_TUNE_TRSM_SCHEDULE = 0, HPS_TUNE_TRSM_WAVES = 1 } hps_tuning_key;
+typedef enum { HPS_TUNE_TRSM_SCHEDULE = 0, HPS_TUNE_TRSM_WAVES = 1, HPS_TUNE_RESIDUAL_COLS = 2 } hps_tuning_key;
 hps_status hps_plan_set_tuning(hps_plan plan, int32_t key, int32_t value);
 hps_status hps_plan_get_tuning(hps_plan plan, int32_t key, int32_t* value);
 

@@ -18,8 +18,9 @@ EXPORTS = (
     "hps_leaf_interior_solve", "hps_leaf_flux", "hps_plan_set_tuning", "hps_plan_get_tuning",
 )
 
-HPS_TUNE_TRSM_SCHEDULE, HPS_TUNE_TRSM_WAVES = 0, 1
-TUNING_KEYS = {"trsm_schedule": HPS_TUNE_TRSM_SCHEDULE, "trsm_waves": HPS_TUNE_TRSM_WAVES}
+HPS_TUNE_TRSM_SCHEDULE, HPS_TUNE_TRSM_WAVES, HPS_TUNE_RESIDUAL_COLS = 0, 1, 2
+TUNING_KEYS = {"trsm_schedule": HPS_TUNE_TRSM_SCHEDULE, "trsm_waves": HPS_TUNE_TRSM_WAVES,
+               "residual_cols": HPS_TUNE_RESIDUAL_COLS}
 
 PROFILE_FAMILIES = ("lu_gemm", "lu_panel", "lu_leaf", "solve_fwd", "solve_bwd", "residual", "dtn", "operators")
 

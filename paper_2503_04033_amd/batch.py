@@ -157,6 +157,7 @@ class BatchedLeafReduction:
 
 TRSM_KNOBS = ({"trsm_schedule": 0, "trsm_waves": 4}, {"trsm_schedule": 0, "trsm_waves": 6},
               {"trsm_schedule": 0, "trsm_waves": 8}, {"trsm_schedule": 1, "trsm_waves": 4})
+RESIDUAL_KNOBS = ({"residual_cols": 8}, {"residual_cols": 4})
 
 
 def _time_build(pr, precision, hbm_budget, chunk, knobs, reps):
@@ -178,13 +179,14 @@ def _time_build(pr, precision, hbm_budget, chunk, knobs, reps):
 
 
 def autotune(problems, precision="fp32_ir", candidates=(128, 256, 512, 1024), hbm_budget=64e9, cache=None,
-             reps=1, knobs=TRSM_KNOBS):
-    """Pick, per problem, the chunk size and the solve knobs by timing the build stage.
+             reps=1, knob_stages=(TRSM_KNOBS, RESIDUAL_KNOBS)):
+    """Pick, per problem, the chunk size and the plan knobs by timing the build stage.
 
-    Two passes: every knob setting at the largest chunk that fits hbm_budget, then every
-    candidate chunk with the fastest setting.  Returns a list of
-    {"chunk": c, "tuning": {knob: value}}; results are cached as JSON under the key
-    (GPU name, p, nbox, precision).
+    One stage per group of knobs (solve schedule and occupancy, then the residual's
+    column blocking), each timed at the largest chunk that fits hbm_budget on top of the
+    choices of the earlier stages; then every candidate chunk with the chosen knobs.
+    Returns a list of {"chunk": c, "tuning": {knob: value}}; results are cached as JSON
+    under the key (GPU name, p, nbox, precision).
     """
     name = torch.cuda.get_device_name(0)
     table = {}
@@ -203,8 +205,12 @@ def autotune(problems, precision="fp32_ir", candidates=(128, 256, 512, 1024), hb
         if not fits:
             raise ValueError(f"no candidate chunk of p={pr.p} fits {hbm_budget:.3g} bytes")
         c0 = max(fits)
-        ktrials = [(kn, _time_build(pr, precision, hbm_budget, c0, kn, reps)) for kn in knobs]
-        best_kn = min(ktrials, key=lambda t: t[1])[0]
+        best_kn, ktrials = {}, []
+        for stage in knob_stages:
+            trials = [(dict(best_kn, **kn), _time_build(pr, precision, hbm_budget, c0, dict(best_kn, **kn), reps))
+                      for kn in stage]
+            best_kn = min(trials, key=lambda t: t[1])[0]
+            ktrials += trials
         ctrials = {}
         for c in sorted(set(fits)):
             ctrials[c] = _time_build(pr, precision, hbm_budget, c, best_kn, reps)

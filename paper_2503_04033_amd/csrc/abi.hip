@@ -21,6 +21,7 @@ struct hps_plan_s {
   const double* t;
   int trsm_sched = hps::kTrsmRows;             // HPS_TUNE_TRSM_SCHEDULE
   int trsm_waves = 4;                          // HPS_TUNE_TRSM_WAVES
+  int res_cols = 8;                            // HPS_TUNE_RESIDUAL_COLS
 };
 
 namespace {
@@ -324,7 +325,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     if (berr) {
       HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
       hps::ProfScope ps(&pl->prof, hps::Profiler::kResidual, 0.0, st);
-      HPS_TRY(hps::launch_residual(g, nbox, b, f, X, nullptr, L.maxr, L.maxx, nullptr, st));
+      HPS_TRY(hps::launch_residual(g, nbox, b, f, X, nullptr, L.maxr, L.maxx, nullptr, st, pl->res_cols));
       HPS_TRY(hps::launch_ir_check(nbox, 0, 1, INFINITY, anorm, L.maxb, L.maxr, L.maxx, L.active, nullptr, berr,
                                    st));
     }
@@ -344,7 +345,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
       const int last = it == kmax;
       {
         hps::ProfScope ps(&pl->prof, hps::Profiler::kResidual, 0.0, st);
-        HPS_TRY(hps::launch_residual(g, nbox, b, f, X, B, L.maxr, L.maxx, L.active, st));
+        HPS_TRY(hps::launch_residual(g, nbox, b, f, X, B, L.maxr, L.maxx, L.active, st, pl->res_cols));
       }
       HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
                                    st));
@@ -430,6 +431,10 @@ hps_status hps_plan_set_tuning(hps_plan pl, int32_t key, int32_t value) {
     pl->trsm_waves = value;
     return HPS_OK;
   }
+  if (key == HPS_TUNE_RESIDUAL_COLS && (value == 4 || value == 8)) {
+    pl->res_cols = value;
+    return HPS_OK;
+  }
   return HPS_EINVAL;
 }
 
@@ -441,6 +446,10 @@ hps_status hps_plan_get_tuning(hps_plan pl, int32_t key, int32_t* value) {
   }
   if (key == HPS_TUNE_TRSM_WAVES) {
     *value = pl->trsm_waves;
+    return HPS_OK;
+  }
+  if (key == HPS_TUNE_RESIDUAL_COLS) {
+    *value = pl->res_cols;
     return HPS_OK;
   }
   return HPS_EINVAL;

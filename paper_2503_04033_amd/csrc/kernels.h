@@ -103,7 +103,7 @@ hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* ma
 hipError_t launch_rhs_first_row(const Geom& g, int nbox, const int* perm, int has_f, int* kstart, hipStream_t st);
 hipError_t residual_prepare(const Geom& g);
 hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const double* X, float* R32,
-                           double* maxr, double* maxx, const int* active, hipStream_t st);
+                           double* maxr, double* maxx, const int* active, hipStream_t st, int cols = 8);
 hipError_t launch_ir_check(int nbox, int it, int last, double tol, const double* anorm, const double* maxb,
                            const double* maxr, const double* maxx, int* active, int* iters, double* berr,
                            hipStream_t st);

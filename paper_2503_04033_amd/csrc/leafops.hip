@@ -393,8 +393,8 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox,
   }
 }
 
-// Residual for boxes with m <= 16 interior nodes per direction.  One workgroup of 1024
-// threads per (box, CB = 16 / NW columns); NW waves share a column, each owning a run of
+// Residual for boxes with m <= 16 interior nodes per direction.  One workgroup of
+// 64 CB NW threads per (box, CB columns); NW waves share a column, each owning a run of
 // H = ceil(m / NW) output slabs.  For a fixed column the z-slab kk of X is an m x m
 // matrix S[ii][jj]; its x- and y-derivative terms are D2i S and S D2i^T, both written as
 // 16x16x4 FP64 MFMA chains into one 16x16 accumulator (rows ii, columns jj, zero
@@ -403,10 +403,6 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox,
 // (VALU).  X, b and f are read once: branch-free 8-byte loads run PD slabs ahead in
 // registers and pass through two LDS slab buffers.  R32 is written through LDS in
 // row segments of CB floats.
-#ifndef HPS_RES_NW
-#define HPS_RES_NW 2  // waves per column (2: 8-column blocks, 4: 4-column blocks)
-#endif
-constexpr int kRmThreads = 1024;
 constexpr int kRmLd = 17;                // row stride of a 16x16 slab tile in LDS
 constexpr int kRmTile = 16 * kRmLd + 4;  // doubles per tile plane
 
@@ -418,13 +414,13 @@ __device__ inline double wave_uniform(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int M, int NW>
-__global__ __launch_bounds__(kRmThreads) void residual_mfma_kernel(Geom g, int nbox, int ncb, const double* b,
+template <int M, int NW, int CB>
+__global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, int nbox, int ncb, const double* b,
                                                                    const double* f, const double* X_all,
                                                                    float* R32_all, double* maxr, double* maxx,
                                                                    const int* active) {
   constexpr int m = M, mm = M * M;
-  constexpr int CB = 16 / NW;                 // columns per workgroup
+  constexpr int kRmThreads = 64 * CB * NW;
   constexpr int H = (M + NW - 1) / NW;        // output slabs per wave
   constexpr int PLANES = CB + 2;              // CB columns of X, then b and f
   constexpr int BUF = PLANES * kRmTile;       // one slab buffer
@@ -642,30 +638,39 @@ hipError_t residual_prepare(const Geom& g) {
   return e;
 }
 
+template <int NW, int CB>
+static hipError_t launch_residual_mfma(const Geom& g, int nbox, int grid_boxes, const double* b, const double* f,
+                                       const double* X, float* R32, double* maxr, double* maxx, const int* active,
+                                       hipStream_t st) {
+  // column blocks past the f column hold zeros in X and in R32 (left as the caller wrote them)
+  const int ncb = (g.nb + 1 + CB - 1) / CB;
+  const dim3 grid(grid_boxes * ncb), block(64 * CB * NW);
+  switch (g.m) {
+#define HPS_RES_CASE(M)                                                                                        \
+  case M:                                                                                                      \
+    hipLaunchKernelGGL((residual_mfma_kernel<M, NW, CB>), grid, block, 0, st, g, nbox, ncb, b, f, X, R32, maxr, \
+                       maxx, active);                                                                          \
+    break;
+    HPS_RES_CASE(4) HPS_RES_CASE(5) HPS_RES_CASE(6) HPS_RES_CASE(7) HPS_RES_CASE(8) HPS_RES_CASE(9)
+    HPS_RES_CASE(10) HPS_RES_CASE(11) HPS_RES_CASE(12) HPS_RES_CASE(13) HPS_RES_CASE(14) HPS_RES_CASE(15)
+    HPS_RES_CASE(16)
+#undef HPS_RES_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const double* X, float* R32,
-                           double* maxr, double* maxx, const int* active, hipStream_t st) {
+                           double* maxr, double* maxx, const int* active, hipStream_t st, int cols) {
   hipError_t e = launch_fill_zero(maxr, sizeof(double) * nbox, st);
   if (e == hipSuccess) e = launch_fill_zero(maxx, sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
   const int grid_boxes = 8 * ((nbox + 7) / 8);
   if (g.m >= 4 && g.m <= 16) {
-    // column blocks past the f column hold zeros in X and in R32 (left as the caller wrote them)
-    constexpr int NW = HPS_RES_NW, CB = 16 / NW;
-    const int ncb = (g.nb + 1 + CB - 1) / CB;
-    const dim3 grid(grid_boxes * ncb), block(kRmThreads);
-    switch (g.m) {
-#define HPS_RES_CASE(M)                                                                                   \
-  case M:                                                                                                 \
-    hipLaunchKernelGGL((residual_mfma_kernel<M, NW>), grid, block, 0, st, g, nbox, ncb, b, f, X, R32, maxr, maxx, \
-                       active);                                                                           \
-    break;
-      HPS_RES_CASE(4) HPS_RES_CASE(5) HPS_RES_CASE(6) HPS_RES_CASE(7) HPS_RES_CASE(8) HPS_RES_CASE(9)
-      HPS_RES_CASE(10) HPS_RES_CASE(11) HPS_RES_CASE(12) HPS_RES_CASE(13) HPS_RES_CASE(14) HPS_RES_CASE(15)
-      HPS_RES_CASE(16)
-#undef HPS_RES_CASE
-      default:
-        return hipErrorInvalidValue;
-    }
+    // two waves per column; 8 columns (1024 threads) or 4 columns (512 threads) per workgroup
+    if (cols == 4) return launch_residual_mfma<2, 4>(g, nbox, grid_boxes, b, f, X, R32, maxr, maxx, active, st);
+    return launch_residual_mfma<2, 8>(g, nbox, grid_boxes, b, f, X, R32, maxr, maxx, active, st);
   } else if (((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double) <= 96 * 1024) {
     const size_t shm = ((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double);
     hipLaunchKernelGGL(residual_kernel<4>, dim3(grid_boxes * (g.ldx / 4)), dim3(kResThreads), shm, st, g, nbox, b, f,

@@ -52,19 +52,20 @@ def test_leaf_fp32_ir_small(gpu, p):
 
 @pytest.mark.parametrize("precision,case", [("fp64", "p9"), ("fp32_ir", "p9"), ("fp32_ir", "p20")])
 def test_trsm_schedules(gpu, precision, case):
-    # every schedule and occupancy of the interior solves: parity with the oracle, and
-    # bitwise the same results (same tiles, same order of every sum); p = 20 takes the
-    # segmented FP32 sums
+    # every schedule and occupancy of the interior solves and both column blockings of the
+    # refinement residual: parity with the oracle, and bitwise the same results (same
+    # tiles, same order of every sum); p = 20 takes the segmented FP32 sums
     if case == "p9":
         prob, boxes = W.multi_bump((2, 2, 2), 9, 6.0, 14, gaussian_source=True, name="sched_p9"), range(8)
     else:
         prob, boxes = W.config3_p20(), [5]
     tol = FP64_TOL if precision == "fp64" else IR_TOL
     sweep = _check_leaf(prob, boxes, precision, tol, tuning={"trsm_schedule": 1})
-    for waves in (4, 6, 8):
-        rows = gpu_leaf_boxes(prob, boxes, precision, tuning={"trsm_schedule": 0, "trsm_waves": waves})
+    for waves, cols in ((4, 8), (6, 4), (8, 8)):
+        rows = gpu_leaf_boxes(prob, boxes, precision,
+                              tuning={"trsm_schedule": 0, "trsm_waves": waves, "residual_cols": cols})
         for k in ("X", "T", "g", "iters"):
-            assert np.array_equal(sweep[k], rows[k]), (waves, k)
+            assert np.array_equal(sweep[k], rows[k]), (waves, cols, k)
     plan = rows["plan"]
     from paper_2503_04033_amd._lib import HpsError
     with pytest.raises(HpsError):
