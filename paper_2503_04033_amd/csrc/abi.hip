@@ -109,8 +109,9 @@ Sizes sizes_of(const hps_plan_s* pl) {
   s.x = 8 * (size_t)g.n_pad * g.ldx;
   const size_t elems = (size_t)g.n_pad * g.ldx;
   // FP32_IR: B32 (right-hand side, later the FP32 residual) and Y32; FP64: B64.
-  // Plus per-box scalars and the first nonzero row of each right-hand-side tile.
-  s.ws = 8 * elems + 64 + 4 * round_up(g.ldx / 64, 16);
+  // Plus per-box scalars, the first nonzero row of each right-hand-side tile and the
+  // inverse row permutation.
+  s.ws = 8 * elems + 64 + 4 * round_up(g.ldx / 64, 16) + 4 * (size_t)g.n_pad;
   return s;
 }
 
@@ -120,6 +121,7 @@ struct WsLayout {
   double *maxb, *maxr, *maxx;
   int* active;
   int* kstart;  // [nbox][ldx/64]
+  int* pos;     // [nbox][n_pad]: inverse of perm
 };
 
 WsLayout ws_layout(const hps_plan_s* pl, int nbox, void* ws) {
@@ -135,6 +137,7 @@ WsLayout ws_layout(const hps_plan_s* pl, int nbox, void* ws) {
   L.maxx = L.maxr + nbox;
   L.active = reinterpret_cast<int*>(L.maxx + nbox);
   L.kstart = reinterpret_cast<int*>(p + 64 * (size_t)nbox);
+  L.pos = L.kstart + round_up(g.ldx / 64, 16) * (size_t)nbox;
   return L;
 }
 
@@ -317,7 +320,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
   if (!ir) {
     double* B = static_cast<double*>(L.B);
     HPS_TRY(hps::launch_rhs<double>(g, nbox, f, B, L.maxb, st));
-    HPS_TRY(hps::launch_rhs_first_row(g, nbox, perm, f != nullptr, L.kstart, st));
+    HPS_TRY(hps::launch_rhs_first_row(g, nbox, perm, f != nullptr, L.kstart, nullptr, st));
     HPS_TRY(hps::getrs_run<double>(g, static_cast<const double*>(LU), perm,
                                    static_cast<const double*>(dinv), B, X, nbox, nullptr, st, &pl->prof, nullptr, 0,
                                    pl->trsm_sched, pl->trsm_waves, L.kstart));
@@ -325,7 +328,8 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     if (berr) {
       HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
       hps::ProfScope ps(&pl->prof, hps::Profiler::kResidual, 0.0, st);
-      HPS_TRY(hps::launch_residual(g, nbox, b, f, X, nullptr, L.maxr, L.maxx, nullptr, st, pl->res_cols));
+      HPS_TRY(hps::launch_residual<double>(g, nbox, b, f, X, nullptr, nullptr, L.maxr, L.maxx, nullptr, st,
+                                           pl->res_cols));
       HPS_TRY(hps::launch_ir_check(nbox, 0, 1, INFINITY, anorm, L.maxb, L.maxr, L.maxx, L.active, nullptr, berr,
                                    st));
     }
@@ -334,9 +338,11 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     const float* LUf = static_cast<const float*>(LU);
     const float* Dinv = static_cast<const float*>(dinv);
     HPS_TRY(hps::launch_rhs<float>(g, nbox, f, B, L.maxb, st));
-    HPS_TRY(hps::launch_rhs_first_row(g, nbox, perm, f != nullptr, L.kstart, st));
-    // the first solve also writes X = Y in FP64; each correction below adds into X
-    HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st, &pl->prof, X, 1,
+    HPS_TRY(hps::launch_rhs_first_row(g, nbox, perm, f != nullptr, L.kstart, L.pos, st));
+    // First solve into Y32 only: X0 = Y32 is exact in FP32 and is read from there.  The
+    // residual writes R32 in the factor's row order, so each correction runs in place in
+    // B; the first correction writes X = X0 + d once, later ones X += d.
+    HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st, &pl->prof, nullptr, 0,
                                   pl->trsm_sched, pl->trsm_waves, L.kstart));
     HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
     const int kmax = pl->desc.ir_max_iter;
@@ -345,13 +351,19 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
       const int last = it == kmax;
       {
         hps::ProfScope ps(&pl->prof, hps::Profiler::kResidual, 0.0, st);
-        HPS_TRY(hps::launch_residual(g, nbox, b, f, X, B, L.maxr, L.maxx, L.active, st, pl->res_cols));
+        if (it == 0)
+          HPS_TRY(hps::launch_residual<float>(g, nbox, b, f, L.Y32, B, L.pos, L.maxr, L.maxx, L.active, st,
+                                              pl->res_cols));
+        else
+          HPS_TRY(hps::launch_residual<double>(g, nbox, b, f, X, B, L.pos, L.maxr, L.maxx, L.active, st,
+                                               pl->res_cols));
       }
       HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
                                    st));
+      if (it == 0) HPS_TRY(hps::launch_x_from_y(g, nbox, L.Y32, X, L.active, st));  // boxes done after 0 steps
       if (last) break;
-      HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, L.active, st, &pl->prof, X, 2,
-                                    pl->trsm_sched, pl->trsm_waves));
+      HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, B, nbox, L.active, st, &pl->prof, X, it == 0 ? 3 : 2,
+                                    pl->trsm_sched, pl->trsm_waves, nullptr, 1, L.Y32));
     }
   }
   hps::ProfScope ps(&pl->prof, hps::Profiler::kDtn, 0.0, st);

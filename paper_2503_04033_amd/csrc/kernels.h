@@ -84,12 +84,15 @@ struct ProfScope {
 template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
                      hipStream_t st, Profiler* prof);
-// xmode 1: X = Y, xmode 2: X += Y (FP64 X: the refinement's solution and corrections),
-// written by the backward block-row launches as they finish each tile
+// xmode 1: X = Y, 2: X += Y, 3: X = Y0 + Y (FP64 X: the refinement's solution and
+// corrections), written by the backward block-row launches as they finish each tile.
+// bdirect: the rows of B are already in the factor's row order (else gathered via perm);
+// B may then be Y itself (the solve runs in place).
 template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
                      const int* active, hipStream_t st, Profiler* prof, double* X = nullptr, int xmode = 0,
-                     int sched = kTrsmRows, int waves = 4, const int* kstart = nullptr);
+                     int sched = kTrsmRows, int waves = 4, const int* kstart = nullptr, int bdirect = 0,
+                     const T* Y0 = nullptr);
 
 // leafops.hip
 hipError_t launch_nodes(const Geom& g, const double* t, const double* h, int nbox, const double* origin, double* xi,
@@ -100,10 +103,19 @@ template <typename T>
 hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* maxb, hipStream_t st);
 // kstart [nbox][ldx/64]: first pivoted row at which each 64-column tile of [A_ib | f]
 // can be nonzero, rounded down to 64 (for the forward sweep of the first solve)
-hipError_t launch_rhs_first_row(const Geom& g, int nbox, const int* perm, int has_f, int* kstart, hipStream_t st);
+// and, if pos is given, the inverse permutation pos [nbox][n_pad] (pos[perm[k]] = k)
+hipError_t launch_rhs_first_row(const Geom& g, int nbox, const int* perm, int has_f, int* kstart, int* pos,
+                                hipStream_t st);
 hipError_t residual_prepare(const Geom& g);
-hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const double* X, float* R32,
-                           double* maxr, double* maxx, const int* active, hipStream_t st, int cols = 8);
+// R32 = B - A_ii X (FP64 arithmetic), max|R| and max|X| per box.  X in FP64 (natural
+// column order) or FP32 (the solve buffer: internal column order).  R32 columns in the
+// internal order, rows at pos[node] when pos is given (the factor's row order), else node
+template <typename TX>
+hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const TX* X, float* R32,
+                           const int* pos, double* maxr, double* maxx, const int* active, hipStream_t st,
+                           int cols = 8);
+// X = (double) Y (natural column order) for the boxes whose active flag is 0
+hipError_t launch_x_from_y(const Geom& g, int nbox, const float* Y, double* X, const int* active, hipStream_t st);
 hipError_t launch_ir_check(int nbox, int it, int last, double tol, const double* anorm, const double* maxb,
                            const double* maxr, const double* maxx, int* active, int* iters, double* berr,
                            hipStream_t st);

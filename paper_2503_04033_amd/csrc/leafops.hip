@@ -266,7 +266,7 @@ template hipError_t launch_rhs<double>(const Geom&, int, const double*, double*,
 constexpr int kMaxPad = 5888;  // n_pad at p = 20 is 5856
 
 __global__ __launch_bounds__(256) void rhs_first_row_kernel(Geom g, int nbox, const int* perm_all, int has_f, int ntn,
-                                                            int* kstart) {
+                                                            int* kstart, int* pos_out) {
   __shared__ int pos[kMaxPad];
   __shared__ int tmin[64];
   const int box = blockIdx.x;
@@ -291,12 +291,30 @@ __global__ __launch_bounds__(256) void rhs_first_row_kernel(Geom g, int nbox, co
   }
   __syncthreads();
   for (int t = threadIdx.x; t < ntn; t += blockDim.x) kstart[(size_t)box * ntn + t] = tmin[t] / 64 * 64;
+  if (pos_out)
+    for (int k = threadIdx.x; k < N; k += blockDim.x) pos_out[(size_t)box * N + k] = pos[k];
 }
 
-hipError_t launch_rhs_first_row(const Geom& g, int nbox, const int* perm, int has_f, int* kstart, hipStream_t st) {
+hipError_t launch_rhs_first_row(const Geom& g, int nbox, const int* perm, int has_f, int* kstart, int* pos,
+                                hipStream_t st) {
   const int ntn = g.ldx / 64;
   if (g.n_pad > kMaxPad || ntn > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rhs_first_row_kernel, dim3(nbox), dim3(256), 0, st, g, nbox, perm, has_f, ntn, kstart);
+  hipLaunchKernelGGL(rhs_first_row_kernel, dim3(nbox), dim3(256), 0, st, g, nbox, perm, has_f, ntn, kstart, pos);
+  return hipGetLastError();
+}
+
+// The FP32 first solution Y (internal column order) as the FP64 X (natural order), for the
+// boxes that need no correction.  One workgroup per (row, box).
+__global__ __launch_bounds__(256) void x_from_y_kernel(Geom g, const float* Y_all, double* X_all,
+                                                       const int* active) {
+  const int box = blockIdx.y, row = blockIdx.x;
+  if (active[box] != 0) return;
+  const size_t base = ((size_t)box * g.n_pad + row) * g.ldx;
+  for (int c = threadIdx.x; c < g.ldx; c += blockDim.x) X_all[base + c] = (double)Y_all[base + rhs_icol(g, c)];
+}
+
+hipError_t launch_x_from_y(const Geom& g, int nbox, const float* Y, double* X, const int* active, hipStream_t st) {
+  hipLaunchKernelGGL(x_from_y_kernel, dim3(g.n_pad, nbox), dim3(256), 0, st, g, Y, X, active);
   return hipGetLastError();
 }
 
@@ -319,10 +337,10 @@ __device__ inline bool map_box_chunk(int nbox, int nchunk, int& box, int& chunk)
   return box < nbox;
 }
 
-template <int CW>
+template <int CW, typename TX>
 __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox, const double* b, const double* f,
-                                                               const double* X_all, float* R32_all, double* maxr,
-                                                               double* maxx, const int* active) {
+                                                               const TX* X_all, float* R32_all, const int* pos_all,
+                                                               double* maxr, double* maxx, const int* active) {
   extern __shared__ double xs[];  // [n][CW] then D2 interior block [m][m] and its two boundary columns
   int box, chunk;
   if (!map_box_chunk(nbox, g.ldx / CW, box, chunk)) return;
@@ -331,10 +349,11 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox,
   double* d2s = xs + (size_t)n * CW;   // D2[i+1][j+1]
   double* d2e = d2s + mm;              // D2[i+1][0] and D2[i+1][p-1]
   const int c0 = chunk * CW;
-  const double* X = X_all + (size_t)box * g.n_pad * ldx;
-  for (int e = threadIdx.x; e < n * CW; e += kResThreads) {
+  const TX* X = X_all + (size_t)box * g.n_pad * ldx;
+  const int* pos = pos_all ? pos_all + (size_t)box * g.n_pad : nullptr;
+  for (int e = threadIdx.x; e < n * CW; e += kResThreads) {  // an FP32 X: internal column order
     const int node = e / CW, c = e - node * CW;
-    xs[e] = X[(size_t)node * ldx + c0 + c];
+    xs[e] = (double)X[(size_t)node * ldx + (sizeof(TX) == 4 ? rhs_icol(g, c0 + c) : c0 + c)];
   }
   for (int e = threadIdx.x; e < mm; e += kResThreads) d2s[e] = g.D2[(e / m + 1) * p + e % m + 1];
   for (int e = threadIdx.x; e < 2 * m; e += kResThreads) d2e[e] = g.D2[(e % m + 1) * p + (e < m ? 0 : p - 1)];
@@ -381,7 +400,7 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox,
       bv = f[(size_t)box * n + node];
     }
     const double r = bv + g.s2[0] * ax + g.s2[1] * ay + g.s2[2] * az + g.kappa2 * bb[node] * xv;
-    if (R32) R32[(size_t)node * ldx + rhs_icol(g, col)] = (float)r;
+    if (R32) R32[(size_t)(pos ? pos[node] : node) * ldx + rhs_icol(g, col)] = (float)r;
     mr = fmax(mr, fabs(r));
     mxv = fmax(mxv, fabs(xv));
   }
@@ -414,11 +433,12 @@ __device__ inline double wave_uniform(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int M, int NW, int CB>
+template <int M, int NW, int CB, typename TX>
 __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, int nbox, int ncb, const double* b,
-                                                                   const double* f, const double* X_all,
-                                                                   float* R32_all, double* maxr, double* maxx,
-                                                                   const int* active) {
+                                                                       const double* f, const TX* X_all,
+                                                                       float* R32_all, const int* pos_all,
+                                                                       double* maxr, double* maxx,
+                                                                       const int* active) {
   constexpr int m = M, mm = M * M;
   constexpr int kRmThreads = 64 * CB * NW;
   constexpr int H = (M + NW - 1) / NW;        // output slabs per wave
@@ -432,6 +452,7 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
   __shared__ double tz[16 * 16];     // s2z * D2i[kk][q] at [q][kk]
   __shared__ double te[2 * 16];      // D2[i+1][0] and D2[i+1][p-1]
   __shared__ double td[2][16 * 16];  // s2x D2i and s2y D2i at [k][l], zero padded (MFMA operands)
+  __shared__ int spos[M * M * M];    // R32 row of each node (pos, or the node itself)
   int box, cb;
   if (!map_box_chunk(nbox, ncb, box, cb)) return;
   if (active && active[box] == 0) return;
@@ -440,10 +461,12 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
   const int wc = w % CB, part = w / CB;  // column within the block, run of slabs
   const int c0 = cb * CB, col = c0 + wc;
   const int lr = lane >> 4, lc = lane & 15;
-  const double* X = X_all + (size_t)box * g.n_pad * ldx;
+  const TX* X = X_all + (size_t)box * g.n_pad * ldx;
+  const int* pos = pos_all ? pos_all + (size_t)box * g.n_pad : nullptr;
   const double* bb = b + (size_t)box * g.n;
-  const double* fb = f ? f + (size_t)box * g.n : X;
+  const double* fb = f ? f + (size_t)box * g.n : bb;
   for (int e = threadIdx.x; e < 2 * BUF + 2; e += kRmThreads) sm[e] = 0.0;
+  for (int e = threadIdx.x; e < m * mm; e += kRmThreads) spos[e] = pos ? pos[e] : e;
   for (int e = threadIdx.x; e < mm; e += kRmThreads) tz[(e % m) * 16 + e / m] = g.s2[2] * g.D2[(e / m + 1) * p + e % m + 1];
   for (int e = threadIdx.x; e < 2 * m; e += kRmThreads) te[e] = g.D2[(e % m + 1) * p + (e < m ? 0 : p - 1)];
   for (int e = threadIdx.x; e < 256; e += kRmThreads) {
@@ -470,7 +493,9 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
 #pragma unroll
   for (int s = 0; s < NTK; s++) {
     const int t = threadIdx.x + s * kRmThreads, k = task_kind(s);
-    off[s] = k == 0 ? (t / CB) * ldx + c0 + t % CB : (k == 1 ? t - CB * mm : (k == 2 ? t - (CB + 1) * mm : 0));
+    // an FP32 X is the solve buffer: its columns are in the internal order
+    const int xc = sizeof(TX) == 4 ? rhs_icol(g, c0 + t % CB) : c0 + t % CB;
+    off[s] = k == 0 ? (t / CB) * ldx + xc : (k == 1 ? t - CB * mm : (k == 2 ? t - (CB + 1) * mm : 0));
   }
   // This wave's column of [A_ib | f].  A_ib column col is nonzero on the normal line of
   // face node (la, lb); bit i of emask marks this lane's node (lr + 4i, lc) on it, whose
@@ -504,8 +529,15 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
 #pragma unroll
     for (int s = 0; s < NTK; s++) {
       const int k = task_kind(s);
-      const double* base = k == 0 ? X + xq : (k == 1 ? bb + q * mm : (k == 2 ? fb + q * mm : X));
-      pf[slot][s] = base[k == 3 ? 0 : off[s]];
+      if constexpr (sizeof(TX) == 8) {
+        const double* base = k == 0 ? X + xq : (k == 1 ? bb + q * mm : (k == 2 ? fb + q * mm : X));
+        pf[slot][s] = base[k == 3 ? 0 : off[s]];
+      } else {  // FP32 X: both loads issued, the task's kind picks one (no branch around loads)
+        const float xv = X[k == 0 ? xq + off[s] : 0];
+        const double* base = k == 1 ? bb + q * mm : (k == 2 ? fb + q * mm : bb);
+        const double dv = base[(k == 1 || k == 2) ? off[s] : 0];
+        pf[slot][s] = k == 0 ? (double)xv : dv;
+      }
     }
   };
   auto stash = [&](int buf, int slot) {
@@ -614,7 +646,7 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
       for (int t = threadIdx.x; t < nk * mm * V; t += kRmThreads) {
         const int row = t / V, h = t % V;  // row = (slab - k0) * m^2 + r
         const f4 v = *reinterpret_cast<const f4*>(O + row * CB + 4 * h);
-        *reinterpret_cast<f4*>(R32 + (size_t)(k0 * mm + row) * ldx + rhs_icol(g, c0) + 4 * h) = v;
+        *reinterpret_cast<f4*>(R32 + (size_t)spos[k0 * mm + row] * ldx + rhs_icol(g, c0) + 4 * h) = v;
       }
     }
   }
@@ -630,26 +662,29 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
 hipError_t residual_prepare(const Geom& g) {
   const size_t shm4 = ((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double);
   const size_t shm2 = ((size_t)g.n * 2 + g.m * g.m + 2 * g.m) * sizeof(double);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&residual_kernel<4>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)(shm4 < 160 * 1024 ? shm4 : 160 * 1024));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&residual_kernel<2>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)(shm2 < 160 * 1024 ? shm2 : 160 * 1024));
+  const int s4 = (int)(shm4 < 160 * 1024 ? shm4 : 160 * 1024), s2 = (int)(shm2 < 160 * 1024 ? shm2 : 160 * 1024);
+  const void* k[4] = {reinterpret_cast<const void*>(&residual_kernel<4, double>),
+                      reinterpret_cast<const void*>(&residual_kernel<2, double>),
+                      reinterpret_cast<const void*>(&residual_kernel<4, float>),
+                      reinterpret_cast<const void*>(&residual_kernel<2, float>)};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 4 && e == hipSuccess; i++)
+    e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, (i % 2) ? s2 : s4);
   return e;
 }
 
-template <int NW, int CB>
+template <int NW, int CB, typename TX>
 static hipError_t launch_residual_mfma(const Geom& g, int nbox, int grid_boxes, const double* b, const double* f,
-                                       const double* X, float* R32, double* maxr, double* maxx, const int* active,
-                                       hipStream_t st) {
+                                       const TX* X, float* R32, const int* pos, double* maxr, double* maxx,
+                                       const int* active, hipStream_t st) {
   // column blocks past the f column hold zeros in X and in R32 (left as the caller wrote them)
   const int ncb = (g.nb + 1 + CB - 1) / CB;
   const dim3 grid(grid_boxes * ncb), block(64 * CB * NW);
   switch (g.m) {
 #define HPS_RES_CASE(M)                                                                                        \
   case M:                                                                                                      \
-    hipLaunchKernelGGL((residual_mfma_kernel<M, NW, CB>), grid, block, 0, st, g, nbox, ncb, b, f, X, R32, maxr, \
-                       maxx, active);                                                                          \
+    hipLaunchKernelGGL((residual_mfma_kernel<M, NW, CB, TX>), grid, block, 0, st, g, nbox, ncb, b, f, X, R32,  \
+                       pos, maxr, maxx, active);                                                               \
     break;
     HPS_RES_CASE(4) HPS_RES_CASE(5) HPS_RES_CASE(6) HPS_RES_CASE(7) HPS_RES_CASE(8) HPS_RES_CASE(9)
     HPS_RES_CASE(10) HPS_RES_CASE(11) HPS_RES_CASE(12) HPS_RES_CASE(13) HPS_RES_CASE(14) HPS_RES_CASE(15)
@@ -661,27 +696,32 @@ static hipError_t launch_residual_mfma(const Geom& g, int nbox, int grid_boxes, 
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const double* X, float* R32,
-                           double* maxr, double* maxx, const int* active, hipStream_t st, int cols) {
+template <typename TX>
+hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const TX* X, float* R32,
+                           const int* pos, double* maxr, double* maxx, const int* active, hipStream_t st, int cols) {
   hipError_t e = launch_fill_zero(maxr, sizeof(double) * nbox, st);
   if (e == hipSuccess) e = launch_fill_zero(maxx, sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
   const int grid_boxes = 8 * ((nbox + 7) / 8);
   if (g.m >= 4 && g.m <= 16) {
     // two waves per column; 8 columns (1024 threads) or 4 columns (512 threads) per workgroup
-    if (cols == 4) return launch_residual_mfma<2, 4>(g, nbox, grid_boxes, b, f, X, R32, maxr, maxx, active, st);
-    return launch_residual_mfma<2, 8>(g, nbox, grid_boxes, b, f, X, R32, maxr, maxx, active, st);
+    if (cols == 4) return launch_residual_mfma<2, 4>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st);
+    return launch_residual_mfma<2, 8>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st);
   } else if (((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double) <= 96 * 1024) {
     const size_t shm = ((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double);
-    hipLaunchKernelGGL(residual_kernel<4>, dim3(grid_boxes * (g.ldx / 4)), dim3(kResThreads), shm, st, g, nbox, b, f,
-                       X, R32, maxr, maxx, active);
+    hipLaunchKernelGGL((residual_kernel<4, TX>), dim3(grid_boxes * (g.ldx / 4)), dim3(kResThreads), shm, st, g, nbox,
+                       b, f, X, R32, pos, maxr, maxx, active);
   } else {
     const size_t shm = ((size_t)g.n * 2 + g.m * g.m + 2 * g.m) * sizeof(double);
-    hipLaunchKernelGGL(residual_kernel<2>, dim3(grid_boxes * (g.ldx / 2)), dim3(kResThreads), shm, st, g, nbox, b, f,
-                       X, R32, maxr, maxx, active);
+    hipLaunchKernelGGL((residual_kernel<2, TX>), dim3(grid_boxes * (g.ldx / 2)), dim3(kResThreads), shm, st, g, nbox,
+                       b, f, X, R32, pos, maxr, maxx, active);
   }
   return hipGetLastError();
 }
+template hipError_t launch_residual<double>(const Geom&, int, const double*, const double*, const double*, float*,
+                                            const int*, double*, double*, const int*, hipStream_t, int);
+template hipError_t launch_residual<float>(const Geom&, int, const double*, const double*, const float*, float*,
+                                           const int*, double*, double*, const int*, hipStream_t, int);
 
 // Backward error check of one refinement step; decides which boxes continue.
 __global__ void ir_check_kernel(int nbox, int it, int last, double tol, const double* anorm, const double* maxb,

@@ -474,7 +474,7 @@ template <typename T, bool UPPER, bool SEG>
 __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom& g, const T* F, const int* perm,
                                                                       const T* Inv, const T* B, T* Y, double* Xb,
                                                                       int xmode, int s, int w, int nt, int ks,
-                                                                      T* smem) {
+                                                                      int bdirect, const T* Y0, T* smem) {
   typedef typename GemmCfg<T>::G G;
   static_assert(G::MT == 64 && G::NT == 64, "one 64 x 64 tile per workgroup");
   static_assert(G::SMEM >= 64 * kLeafLd, "Z must fit the GEMM staging buffer");
@@ -537,7 +537,8 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const int r = (wm * WRT + rt) * 16 + Mfma<T>::row(lane, i);
-      const T* rr = r < w ? (UPPER ? Y + (size_t)(s + r) * ld : B + (size_t)perm[s + r] * ld) + nt : nullptr;
+      const T* rr =
+          r < w ? (UPPER ? Y + (size_t)(s + r) * ld : B + (size_t)(bdirect ? s + r : perm[s + r]) * ld) + nt : nullptr;
 #pragma unroll
       for (int ct = 0; ct < WCT; ct++) {
         const int c = (wn * WCT + ct) * 16 + c16;
@@ -550,7 +551,8 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
   const T* irow = Inv + (wave * 16 + c16) * 64 + 4 * g4;
   T ia[4];
   Vec4<T>::load(irow, ia);
-  const bool xadd = Xb && xmode == 2;
+  // X += Y (xmode 2) or X = Y0 + Y (xmode 3): the old X or Y0 is loaded now
+  const bool xadd = Xb && (xmode == 2 || xmode == 3);
   double xo[4][4];
   if (xadd) {
 #pragma unroll
@@ -558,7 +560,9 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
 #pragma unroll
       for (int i = 0; i < 4; i++) {
         const int r = wave * 16 + Mfma<T>::row(lane, i);
-        xo[ct][i] = r < w ? Xb[(size_t)(s + r) * ld + g.gmap[(nt >> 4) + ct] * 16 + c16] : 0.0;
+        xo[ct][i] = r >= w ? 0.0
+                    : xmode == 2 ? Xb[(size_t)(s + r) * ld + g.gmap[(nt >> 4) + ct] * 16 + c16]
+                                 : (double)Y0[(size_t)(s + r) * ld + nt + ct * 16 + c16];
       }
   }
   __syncthreads();
@@ -582,7 +586,7 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
       for (int t = 0; t < 4; t++) ia[t] = ib[t];
   }
   // the finished rows; the backward sweep may also write them to the FP64 X (xmode 1:
-  // X = Y, xmode 2: X += Y)
+  // X = Y, 2: X += Y, 3: X = Y0 + Y)
 #pragma unroll
   for (int ct = 0; ct < 4; ct++)
 #pragma unroll
@@ -603,7 +607,7 @@ template <typename T, bool UPPER, bool SEG, int OCC>
 __global__ __launch_bounds__(256, OCC) void trsm_row_kernel(Geom g, const T* F_all, const int* perm_all,
                                                           const T* dinv_all, const T* B_all, T* Y_all, int s, int w,
                                                           int nbox, int ntn, const int* active, double* X_all,
-                                                          int xmode, const int* kstart) {
+                                                          int xmode, const int* kstart, int bdirect, const T* Y0_all) {
   typedef typename GemmCfg<T>::G G;
   __shared__ T smem[G::SMEM];
   int box, tn;
@@ -616,7 +620,8 @@ __global__ __launch_bounds__(256, OCC) void trsm_row_kernel(Geom g, const T* F_a
   solve_block_row<T, UPPER, SEG>(g, F_all + (size_t)box * N * N, perm_all + (size_t)box * N, Inv,
                                  B_all + (size_t)box * xs, Y_all + (size_t)box * xs,
                                  X_all ? X_all + (size_t)box * xs : nullptr, xmode, s, w, tn * 64,
-                                 kstart ? kstart[(size_t)box * ntn + tn] : 0, smem);
+                                 kstart ? kstart[(size_t)box * ntn + tn] : 0, bdirect,
+                                 Y0_all ? Y0_all + (size_t)box * xs : nullptr, smem);
 }
 
 // One whole triangular sweep per workgroup: the right-hand-side columns of a box are
@@ -630,7 +635,7 @@ template <typename T, bool UPPER, bool SEG, int OCC>
 __global__ __launch_bounds__(256, OCC) void trsm_sweep_kernel(Geom g, const T* F_all, const int* perm_all,
                                                             const T* dinv_all, const T* B_all, T* Y_all, int nbox,
                                                             int ntn, const int* active, double* X_all, int xmode,
-                                                            const int* kstart) {
+                                                            const int* kstart, int bdirect, const T* Y0_all) {
   typedef typename GemmCfg<T>::G G;
   __shared__ T smem[G::SMEM];
   int box, tn;
@@ -644,6 +649,7 @@ __global__ __launch_bounds__(256, OCC) void trsm_sweep_kernel(Geom g, const T* F
   T* Y = Y_all + (size_t)box * xs;
   const T* B = B_all + (size_t)box * xs;
   double* Xb = X_all ? X_all + (size_t)box * xs : nullptr;
+  const T* Y0 = Y0_all ? Y0_all + (size_t)box * xs : nullptr;
   const int nblk = (N + kPanel - 1) / kPanel;
   const int ks = kstart ? kstart[(size_t)box * ntn + tn] : 0;
 #pragma unroll 1
@@ -651,7 +657,7 @@ __global__ __launch_bounds__(256, OCC) void trsm_sweep_kernel(Geom g, const T* F
     const int jb = UPPER ? nblk - 1 - q : q;
     const int s = jb * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
     solve_block_row<T, UPPER, SEG>(g, F, perm, dinv + (size_t)jb * 2 * 64 * 64, B, Y, Xb, xmode, s, w, tn * 64, ks,
-                                   smem);
+                                   bdirect, Y0, smem);
     __syncthreads();  // Y_j stored before the next block row loads it
   }
 }
@@ -745,18 +751,18 @@ hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm
 template <typename T, bool UPPER, bool SEG, int OCC>
 static hipError_t launch_sweep(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
                                const int* active, hipStream_t st, double* X, int xmode, int sched,
-                               const int* kstart) {
+                               const int* kstart, int bdirect, const T* Y0) {
   const int ntn = g.ldx / 64, N = g.n_pad;
   if (sched == kTrsmSweep) {
     hipLaunchKernelGGL((trsm_sweep_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F,
-                       perm, dinv, B, Y, nbox, ntn, active, X, xmode, kstart);
+                       perm, dinv, B, Y, nbox, ntn, active, X, xmode, kstart, bdirect, Y0);
     return hipGetLastError();
   }
   const int nblk = (N + kPanel - 1) / kPanel;
   for (int q = 0; q < nblk; q++) {
     const int s = (UPPER ? nblk - 1 - q : q) * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
     hipLaunchKernelGGL((trsm_row_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F,
-                       perm, dinv, B, Y, s, w, nbox, ntn, active, X, xmode, kstart);
+                       perm, dinv, B, Y, s, w, nbox, ntn, active, X, xmode, kstart, bdirect, Y0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -769,16 +775,16 @@ static hipError_t launch_sweep(const Geom& g, const T* F, const int* perm, const
 template <typename T, bool UPPER>
 static hipError_t dispatch_sweep(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y,
                                  int nbox, const int* active, hipStream_t st, double* X, int xmode, int sched,
-                                 int waves, const int* kstart) {
+                                 int waves, const int* kstart, int bdirect, const T* Y0) {
+#define HPS_SWEEP(SEG, OCC) \
+  launch_sweep<T, UPPER, SEG, OCC>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched, kstart, bdirect, Y0)
   if constexpr (sizeof(T) == 4) {
-    if (g.n_pad > kTrsmSegAbove)
-      return launch_sweep<T, UPPER, true, 4>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched, kstart);
-    if (waves == 8)
-      return launch_sweep<T, UPPER, false, 8>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched, kstart);
-    if (waves == 6)
-      return launch_sweep<T, UPPER, false, 6>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched, kstart);
+    if (g.n_pad > kTrsmSegAbove) return HPS_SWEEP(true, 4);
+    if (waves == 8) return HPS_SWEEP(false, 8);
+    if (waves == 6) return HPS_SWEEP(false, 6);
   }
-  return launch_sweep<T, UPPER, false, 4>(g, F, perm, dinv, B, Y, nbox, active, st, X, xmode, sched, kstart);
+  return HPS_SWEEP(false, 4);
+#undef HPS_SWEEP
 }
 
 // X = A^{-1} B for every active box: the forward sweep L Y = P B reads the rows of B
@@ -790,7 +796,7 @@ static hipError_t dispatch_sweep(const Geom& g, const T* F, const int* perm, con
 template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
                      const int* active, hipStream_t st, Profiler* prof, double* X, int xmode, int sched, int waves,
-                     const int* kstart) {
+                     const int* kstart, int bdirect, const T* Y0) {
   const double N = g.n_pad, nrhs = g.nb + 1;
   // per sweep: sum over block rows of 2 w K + w^2 = N^2 per right-hand side
   const double flops = N * N * nrhs * nbox;
@@ -798,13 +804,14 @@ hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, 
   hipError_t e;
   {
     ProfScope ps(prof, Profiler::kSolveFwd, flops, st, nlaunch);
-    e = dispatch_sweep<T, false>(g, F, perm, dinv, B, Y, nbox, active, st, nullptr, 0, sched, waves, kstart);
+    e = dispatch_sweep<T, false>(g, F, perm, dinv, B, Y, nbox, active, st, nullptr, 0, sched, waves, kstart, bdirect,
+                                 nullptr);
   }
   if (e != hipSuccess) return e;
   {
     ProfScope ps(prof, Profiler::kSolveBwd, flops, st, nlaunch);
     e = dispatch_sweep<T, true>(g, F, perm, dinv, Y, Y, nbox, active, st, xmode ? X : nullptr, xmode, sched, waves,
-                                nullptr);
+                                nullptr, 0, Y0);
   }
   return e;
 }
@@ -814,9 +821,10 @@ template hipError_t getrf_run<double>(const Geom&, const std::vector<int>&, doub
                                       hipStream_t, Profiler*);
 template hipError_t getrs_run<float>(const Geom&, const float*,
                                      const int*, const float*, const float*, float*, int, const int*, hipStream_t,
-                                     Profiler*, double*, int, int, int, const int*);
+                                     Profiler*, double*, int, int, int, const int*, int, const float*);
 template hipError_t getrs_run<double>(const Geom&, const double*,
                                       const int*, const double*, const double*, double*, int, const int*,
-                                      hipStream_t, Profiler*, double*, int, int, int, const int*);
+                                      hipStream_t, Profiler*, double*, int, int, int, const int*, int,
+                                      const double*);
 
 }  // namespace hps
