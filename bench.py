@@ -262,7 +262,7 @@ def main():
         fams[k]["flops"] *= passes / launched_passes
     KNAMES = {"solve_fwd": "trsm_row_kernel<float, false, false, 4>", "solve_bwd": "trsm_row_kernel<float, true, false, 4>",
               "lu_gemm": "gemm_op_kernel<float, true>", "lu_panel": "lu_panel_kernel<float, 6, 8, 64>",
-              "residual": "residual_mfma_kernel<14, 2, 8>"}
+              "residual": "residual_mfma_kernel<14, 2, 8, double>"}
     # the LU/TRSM phase: device time of the factorization and solve kernels (events around
     # each launch) against the algorithmic LU and solve flops of the step
     ph_ms = sum(fams[k]["ms"] for k in ("lu_gemm", "lu_panel", "lu_leaf", "solve_fwd", "solve_bwd")) / a.steps
