@@ -61,7 +61,7 @@ class TwoLevelSolver:
 
     def __init__(self, nboxes, lo, hi, p: int, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
                  ir_tol: float = 1e-11, chunk: Optional[int] = None, keep_X: bool = True, device="cuda",
-                 refine: Optional[int] = None, refine_steps: int = 2):
+                 refine: Optional[int] = None, refine_steps: int = 2, tuning: Optional[dict] = None):
         self.nboxes = tuple(int(v) for v in nboxes)
         self.nbox = int(np.prod(self.nboxes))
         self.lo = tuple(float(v) for v in lo)
@@ -70,6 +70,8 @@ class TwoLevelSolver:
         self.p, self.kappa = int(p), float(kappa)
         self.device = torch.device(device)
         self.plan = LeafPlan(p, self.h, kappa, precision, ir_max_iter, ir_tol)
+        for k, v in (tuning or {}).items():  # scheduling knobs (batch.autotune's choices)
+            self.plan.hps_plan_set_tuning(k, v)
         self.info = self.plan.info
         self.layout = itf.build_layout(self.nboxes, self.info.m)
         self.chunk = int(chunk) if chunk else self.nbox

@@ -323,3 +323,16 @@ def test_interior_solve_and_flux(gpu, precision):
         eu, ef = rel(ui_h[k], u_ref), rel(fl_h[k], fl_ref)
         say(f"  box {t}: u_i err {eu:.2e}  flux err {ef:.2e}")
         assert eu < FP64_TOL and ef < FP64_TOL
+
+
+def test_pipeline_tuned_matches_default(gpu):
+    # the solver with every non-default scheduling knob gives bitwise the default solution
+    from paper_2503_04033_amd.solver import TwoLevelSolver
+    prob = W.multi_bump((2, 2, 2), 8, 6.0, 15, gaussian_source=True, name="tuned_p8")
+    outs = []
+    for tuning in (None, {"trsm_schedule": 1, "trsm_waves": 8, "residual_cols": 4}):
+        s = TwoLevelSolver.for_problem(prob, precision="fp32_ir", tuning=tuning)
+        outs.append(s.solve_problem(prob))
+        torch.cuda.synchronize()
+    assert torch.equal(outs[0]["u_i"], outs[1]["u_i"])
+    assert np.array_equal(outs[0]["u_face"], outs[1]["u_face"])
