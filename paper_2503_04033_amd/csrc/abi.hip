@@ -315,6 +315,7 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
   if (nbox == 0) return HPS_OK;
   if (!LU || !perm || !dinv || !b || !anorm || !slot_map || !T_vals || !gload || !X || !ws) return HPS_EINVAL;
   const Geom& g = pl->g;
+  if (hps::dtn_part_bytes(g, 1) > 8 * (size_t)g.n_pad * g.ldx) return HPS_EUNSUPPORTED;  // never, for p <= 20
   WsLayout L = ws_layout(pl, nbox, ws);
   const bool ir = pl->desc.precision == HPS_FP32_IR;
   if (!ir) {
@@ -367,8 +368,8 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     }
   }
   hps::ProfScope ps(&pl->prof, hps::Profiler::kDtn, 0.0, st);
-  // the right-hand-side region of the workspace is free again: the column-block sums of
-  // the loads go there
+  // the right-hand-side region of the workspace (8 n_pad ldx bytes per box) is free again:
+  // the column-block sums of the loads go there
   return dev(hps::launch_dtn(g, nbox, X, g_dir, slot_map, T_vals, gload, static_cast<double*>(L.B), st));
 }
 
