@@ -336,3 +336,24 @@ def test_pipeline_tuned_matches_default(gpu):
         torch.cuda.synchronize()
     assert torch.equal(outs[0]["u_i"], outs[1]["u_i"])
     assert np.array_equal(outs[0]["u_face"], outs[1]["u_face"])
+
+
+def test_mixed_refinement_steps(gpu):
+    # Boxes of one launch that stop after 0 corrections keep the FP32 first solution as X;
+    # the others take the correction path.  ir_tol is set between the boxes' backward
+    # errors after the first solve so both kinds occur; each box must equal, bitwise, the
+    # run that takes the same number of steps.
+    prob = W.multi_bump((2, 2, 2), 9, 6.0, 16, gaussian_source=True, name="mixed_p9")
+    zero = gpu_leaf_boxes(prob, range(8), "fp32_ir", ir_max_iter=0, ir_tol=1e-30)
+    tol = float(np.median(zero["berr"]))
+    mixed = gpu_leaf_boxes(prob, range(8), "fp32_ir", ir_max_iter=3, ir_tol=tol)
+    full = gpu_leaf_boxes(prob, range(8), "fp32_ir", ir_max_iter=3, ir_tol=1e-11)
+    it = mixed["iters"]
+    say(f"  berr after the first solve {zero['berr'].tolist()}; steps at tol {tol:.2e}: {it.tolist()}")
+    assert (it == 0).any() and (it > 0).any()
+    for k in range(8):
+        ref = zero if it[k] == 0 else full
+        if it[k] > 0:
+            assert full["iters"][k] == it[k]
+        for key in ("X", "T", "g"):
+            assert np.array_equal(mixed[key][k], ref[key][k]), (k, key)
