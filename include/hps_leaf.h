@@ -232,7 +232,8 @@ const char* hps_status_string(hps_status s);
  * milliseconds and the algorithmic flops of those launches (2*M*N*K for tile
  * GEMMs, 2*w*w*ncols for leaves, n_pad^2 * (n_b + 1) per box for a triangular
  * sweep even where structurally zero blocks are skipped, 0 for bandwidth
- * kernels).  Families: 0 LU GEMM, 1 LU panel, 2 LU leaf, 3 forward solve (L),
+ * kernels).  Families: 0 LU GEMM, 1 LU panel, 2 LU triangular solves (leaves and
+ * short block rows: 2*w*K*ncols + w*w*ncols), 3 forward solve (L),
  * 4 backward solve (U), 5 residual, 6 DtN, 7 operators.  Enabling clears the
  * counters.  Event recording adds launch overhead; leave it off in
  * production. */

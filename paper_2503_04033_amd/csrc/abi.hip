@@ -69,12 +69,12 @@ void cheb_tables(int p, std::vector<double>& t, std::vector<double>& D, std::vec
 // Recursive column-split LU unrolled into records (see lu.hip):
 //   lu(c0, c1): panel if c1 - c0 <= 64, else lu(c0, mid); trsm(c0, mid | mid, c1);
 //               gemm(rows [mid, N), cols [mid, c1), k [c0, mid)); lu(mid, c1)
-//   trsm(r0, r1 | cA, cB): leaf if r1 - r0 <= 64, else trsm(r0, mid); gemm(rows [mid, r1),
-//               cols [cA, cB), k [r0, mid)); trsm(mid, r1)
+//   trsm(r0, r1 | cA, cB): block rows if r1 - r0 <= 256, else trsm(r0, mid); gemm(rows
+//               [mid, r1), cols [cA, cB), k [r0, mid)); trsm(mid, r1)
 // Split points are multiples of 64 so that leaves coincide with 64-wide panels.
 void sched_trsm(std::vector<int>& ops, int r0, int r1, int cA, int cB) {
-  if (r1 - r0 <= 64) {
-    ops.insert(ops.end(), {hps::kOpLeaf, r0, r1 - r0, cA, cB, 0, 0, 0});
+  if (r1 - r0 <= hps::kLuRowsMax) {  // short: 64-row blocks, each a K loop plus the leaf product
+    ops.insert(ops.end(), {hps::kOpRows, r0, r1, cA, cB, 0, 0, 0});
     return;
   }
   const int mid = r0 + (int)round_up((r1 - r0) / 2, 64);

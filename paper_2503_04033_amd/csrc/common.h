@@ -88,10 +88,11 @@ __device__ inline int rhs_ncol(const Geom& g, int ic) { return g.gmap[ic >> 4] *
 
 // Schedule record kinds for the recursive LU and solves (record = {kind, a1..a7}):
 //   kOpPanel {c0, w}                 factor columns [c0, c0+w) (w <= 64)
-//   kOpLeaf  {r0, w, cA, cB}          rows [r0, r0+w) := Inv * rows on columns [cA, cB),
-//                                     Inv the stored inverse of the L (or U) diagonal block
 //   kOpGemm  {m0, m1, n0, n1, k0, k1} rows [m0,m1) x cols [n0,n1) -= F[., k0:k1] X[k0:k1, .]
-constexpr int kOpPanel = 0, kOpLeaf = 1, kOpGemm = 2;
+//   kOpRows  {r0, r1, cA, cB}         rows [r0, r1) := L[r0:r1, r0:r1]^-1 rows on columns [cA, cB),
+//                                     left-looking 64-row blocks (r1 - r0 <= kLuRowsMax)
+constexpr int kOpPanel = 0, kOpGemm = 2, kOpRows = 3;
+constexpr int kLuRowsMax = 256;
 
 __device__ inline int panel_start(int r) { return r * kPanel; }
 __device__ inline int panel_width(const Geom& g, int r) {

@@ -112,15 +112,15 @@ template <> struct Store4<double> {
 // A_ii has 3m - 2 nonzeros per row (the three D2 lines through the node; the identity
 // on the padding rows), so each workgroup first writes zero rows with 16-byte stores and,
 // after one barrier, the nonzeros of its rows.
-constexpr int kOpRows = 8;
+constexpr int kOperatorRows = 8;
 
 template <typename T>
 __global__ __launch_bounds__(256) void operators_kernel(Geom g, int nbox, const double* b, T* A_all, double* anorm) {
   const int box = blockIdx.y;
   const int N = g.n_pad, n = g.n, m = g.m, mm = m * m, p = g.p;
   T* A = A_all + (size_t)box * N * N;
-  const int r0 = blockIdx.x * kOpRows;
-  const int nr = (N - r0) < kOpRows ? (N - r0) : kOpRows;
+  const int r0 = blockIdx.x * kOperatorRows;
+  const int nr = (N - r0) < kOperatorRows ? (N - r0) : kOperatorRows;
   const double zero[4] = {0.0, 0.0, 0.0, 0.0};
   const int q4 = N / 4;
   for (int e = threadIdx.x; e < nr * q4; e += blockDim.x) {
@@ -177,7 +177,7 @@ template <typename T>
 hipError_t launch_operators(const Geom& g, int nbox, const double* b, T* A, double* anorm, hipStream_t st) {
   hipError_t e = launch_fill_zero(anorm, sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((operators_kernel<T>), dim3((g.n_pad + kOpRows - 1) / kOpRows, nbox), dim3(256), 0, st, g, nbox,
+  hipLaunchKernelGGL((operators_kernel<T>), dim3((g.n_pad + kOperatorRows - 1) / kOperatorRows, nbox), dim3(256), 0, st, g, nbox,
                      b, A, anorm);
   return hipGetLastError();
 }
@@ -208,8 +208,8 @@ __global__ __launch_bounds__(256) void rhs_kernel(Geom g, int nbox, const double
   const int box = blockIdx.y;
   const int N = g.n_pad, ldx = g.ldx, n = g.n, m = g.m, mm = m * m, p = g.p;
   T* B = B_all + (size_t)box * N * ldx;
-  const int r0 = blockIdx.x * kOpRows;
-  const int nr = (N - r0) < kOpRows ? (N - r0) : kOpRows;
+  const int r0 = blockIdx.x * kOperatorRows;
+  const int nr = (N - r0) < kOperatorRows ? (N - r0) : kOperatorRows;
   const double zero[4] = {0.0, 0.0, 0.0, 0.0};
   const int q4 = ldx / 4;
   for (int e = threadIdx.x; e < nr * q4; e += blockDim.x) {
@@ -247,7 +247,7 @@ template <typename T>
 hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* maxb, hipStream_t st) {
   hipError_t e = launch_fill_zero(maxb, sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((rhs_kernel<T>), dim3((g.n_pad + kOpRows - 1) / kOpRows, nbox), dim3(256), 0, st, g, nbox, f, B,
+  hipLaunchKernelGGL((rhs_kernel<T>), dim3((g.n_pad + kOperatorRows - 1) / kOperatorRows, nbox), dim3(256), 0, st, g, nbox, f, B,
                      maxb);
   return hipGetLastError();
 }

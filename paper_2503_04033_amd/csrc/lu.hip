@@ -3,22 +3,25 @@
 //
 // The paper factors every box's interior block A_ii and solves with it (Alg. 1
 // "form the local solution operator", Alg. 2 "form u = A_ii^{-1} f"; A_ii is
-// block diagonal over boxes, Sec. 2.2).  Both run as a recursive column split:
+// block diagonal over boxes, Sec. 2.2).  The factorization is a recursive column
+// split, the solves are block rows:
 //
 //   lu(c0, c1):  if c1 - c0 <= 64: pivoted panel factorization
-//                else: lu(c0, mid); U12 = L11^{-1} A12 (recursive triangular
-//                solve); A22 -= L21 U12 (tile GEMM on MFMA); lu(mid, c1)
-//   solve:       Y = P B; Y = L^{-1} Y and X = U^{-1} Y, each a recursive
-//                triangular solve (leaves: 64 x 64 stored inverses, the rest
-//                tile GEMMs)
+//                else: lu(c0, mid); U12 = L11^{-1} A12 (triangular solve: up to
+//                256 rows left-looking 64-row blocks, above that split again with
+//                a tile GEMM between the halves); A22 -= L21 U12 (tile GEMM on
+//                MFMA); lu(mid, c1)
+//   solve:       L Y = P B and U X = Y as left-looking 64-row block rows: a tile
+//                GEMM over the finished rows, then a product with the stored
+//                64 x 64 inverse of the diagonal block
 //
-// so nearly all flops are large MFMA tile GEMMs.  The recursion depends only on
-// the matrix size, so the host unrolls it into an op list once per plan and
-// launches one kernel per op over all boxes of a chunk: a GEMM kernel (many
-// workgroups per box, each one output tile, XCD-aware placement so a box's
-// tiles share one L2), a leaf kernel, and a panel kernel (one workgroup per box,
-// sub-panels in registers, workgroup-wide pivot search).  Each kernel gets its
-// own register budget and occupancy.
+// so nearly all flops are MFMA tile GEMMs.  The recursion depends only on the
+// matrix size, so the host unrolls it into an op list once per plan and launches
+// one kernel per op over all boxes of a chunk: a GEMM kernel (many workgroups per
+// box, each one output tile, XCD-aware placement so a box's tiles share one L2),
+// a block-row solve kernel, and a panel kernel (one workgroup per box, sub-panels
+// in registers, workgroup-wide pivot search).  Each kernel gets its own register
+// budget and occupancy.
 //
 // Rows are never moved: perm[pos] names the physical row at position pos (a
 // row gather in row-major storage is a contiguous read).  Pivot rule: largest
@@ -418,49 +421,10 @@ __global__ __launch_bounds__(256, 4) void gemm_op_kernel(Geom g, const T* F_all,
     }
 }
 
-// X[row(r0+i)][c] := sum_j Inv[i][j] X[row(r0+j)][c] for one 64-column tile,
-// Inv the stored inverse of the diagonal block of L (lower) or U (upper).
+// Row stride (elements) of a 64 x 64 block in LDS that is multiplied by a stored
+// diagonal-block inverse (the last step of every 64-row block of a triangular solve).
 constexpr int kLeafLd = 64 + 4;
 
-template <typename T, int W, bool UPPER, bool PERM>
-__global__ __launch_bounds__(256) void leaf_op_kernel(Geom g, const int* perm_all, const T* dinv_all, T* X_all,
-                                                      int ld, size_t xstride, int r0, int cA, int cB, int nbox,
-                                                      int ntn, const int* active) {
-  constexpr int NRT = W / 16;      // row tiles: 4 (W=64) or 2 (W=32)
-  constexpr int NCG = 4 / NRT;     // column groups over the 4 waves
-  constexpr int CT = 4 / NCG;      // 16-column tiles per wave
-  __shared__ T xs[64 * kLeafLd];
-  int box, tn;
-  if (!map_box_tile(nbox, ntn, box, tn)) return;
-  if (active && active[box] == 0) return;
-  const int N = g.n_pad;
-  const int* perm = perm_all + (size_t)box * N;
-  const T* Inv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(r0 / kPanel) * 2 * 64 * 64 +
-                 (UPPER ? 64 * 64 : 0);
-  T* X = X_all + (size_t)box * xstride;
-  const int c0 = cA + tn * 64;
-  const int ncol = (cB - c0) < 64 ? (cB - c0) : 64;
-  for (int e = threadIdx.x; e < W * 64; e += 256) {
-    const int i = e >> 6, c = e & 63;
-    xs[i * kLeafLd + c] = c < ncol ? X[(size_t)(PERM ? perm[r0 + i] : r0 + i) * ld + c0 + c] : T(0);
-  }
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rt = wave % NRT, cg = wave / NRT;
-  typename Mfma<T>::acc out[1][CT];
-#pragma unroll
-  for (int ct = 0; ct < CT; ct++) out[0][ct] = Mfma<T>::zero();
-  auto arow = [&](int) -> const T* { return Inv + (rt * 16 + (lane & 15)) * 64; };
-  wg_gemm_lds_add<T, 1, CT>(out, arow, xs, kLeafLd, W, cg * CT * 16);
-#pragma unroll
-  for (int ct = 0; ct < CT; ct++)
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int r = rt * 16 + Mfma<T>::row(lane, i);
-      const int c = (cg * CT + ct) * 16 + (lane & 15);
-      if (c < ncol) X[(size_t)(PERM ? perm[r0 + r] : r0 + r) * ld + c0 + c] = out[0][ct][i];
-    }
-}
 
 // One block row of the solves, left-looking: Z = R_j - F[j rows][k range] Y[k range]
 // over the finished rows, then Y_j = Inv_j Z with the stored inverse of the diagonal
@@ -624,6 +588,89 @@ __global__ __launch_bounds__(256, OCC) void trsm_row_kernel(Geom g, const T* F_a
                                  Y0_all ? Y0_all + (size_t)box * xs : nullptr, smem);
 }
 
+// Short triangular solves of the LU recursion (rows [r0, r1), r1 - r0 <= kLuRowsMax, of
+// the U block right of a factored panel): one launch per 64-row block s, left-looking like
+// the block rows of the solves but on the factor itself, rows through perm:
+//   Z = A[perm[s + i]][cols] - L[s + i, r0:s) U[r0:s, cols],  U_s = Linv_s Z  (in place).
+// The K loop is the tile GEMM (the K range of perm staged in LDS), the leaf product reads
+// Z from LDS; the short GEMMs and separate leaf launches of a deeper recursion go away.
+template <typename T>
+__global__ __launch_bounds__(256, 4) void lu_rows_kernel(Geom g, T* A_all, const int* perm_all, const T* dinv_all,
+                                                         int r0, int s, int w, int cA, int cB, int nbox, int ntn) {
+  typedef typename GemmCfg<T>::G G;
+  static_assert(G::MT == 64 && G::NT == 64, "one 64 x 64 tile per workgroup");
+  static_assert(G::SMEM >= 64 * kLeafLd, "Z must fit the GEMM staging buffer");
+  constexpr int WRT = 2, WCT = 2;
+  __shared__ T smem[G::SMEM];
+  __shared__ int kperm[kLuRowsMax];
+  int box, tn;
+  if (!map_box_tile(nbox, ntn, box, tn)) return;
+  const int N = g.n_pad;
+  T* A = A_all + (size_t)box * N * N;
+  const int* perm = perm_all + (size_t)box * N;
+  const T* Inv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(s / kPanel) * 2 * 64 * 64;
+  const int nt = cA + tn * 64;
+  const int bcols = (cB - nt) < 64 ? (cB - nt) : 64;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = wave % 2, wn = wave / 2;
+  const int g4 = lane >> 4, c16 = lane & 15;
+  for (int i = threadIdx.x; i < s - r0; i += blockDim.x) kperm[i] = perm[r0 + i];
+  __syncthreads();
+  typename G::acc_t acc[WRT][WCT];
+#pragma unroll
+  for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+    for (int ct = 0; ct < WCT; ct++) acc[rt][ct] = Mfma<T>::zero();
+  auto arow = [&](int r) -> const T* { return r < w ? A + (size_t)perm[s + r] * N : nullptr; };
+  auto brow = [&](int k) -> const T* { return A + (size_t)kperm[k - r0] * N + nt; };
+  G::run(acc, arow, brow, bcols, r0, s, smem);
+  __syncthreads();  // every wave is done with the staging buffer
+  T* zs = smem;     // Z [64][kLeafLd]
+#pragma unroll
+  for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int r = (wm * WRT + rt) * 16 + Mfma<T>::row(lane, i);
+      const T* rr = r < w ? A + (size_t)perm[s + r] * N + nt : nullptr;
+#pragma unroll
+      for (int ct = 0; ct < WCT; ct++) {
+        const int c = (wn * WCT + ct) * 16 + c16;
+        zs[r * kLeafLd + c] = (rr && c < bcols) ? rr[c] + acc[rt][ct][i] : T(0);
+      }
+    }
+  const T* irow = Inv + (wave * 16 + c16) * 64 + 4 * g4;
+  T ia[4];
+  Vec4<T>::load(irow, ia);
+  __syncthreads();
+  typename Mfma<T>::acc out[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++) out[ct] = Mfma<T>::zero();
+#pragma unroll
+  for (int kc = 0; kc < 4; kc++) {
+    T ib[4];
+    if (kc + 1 < 4) Vec4<T>::load(irow + (kc + 1) * 16, ib);
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int k = kc * 16 + 4 * g4 + t;
+      const T a = k < w ? ia[t] : T(0);
+      const T* zr = zs + k * kLeafLd + c16;
+#pragma unroll
+      for (int ct = 0; ct < 4; ct++) out[ct] = Mfma<T>::op(a, zr[ct * 16], out[ct]);
+    }
+    if (kc + 1 < 4)
+#pragma unroll
+      for (int t = 0; t < 4; t++) ia[t] = ib[t];
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int r = wave * 16 + Mfma<T>::row(lane, i);
+      const int c = ct * 16 + c16;
+      if (r < w && c < bcols) A[(size_t)perm[s + r] * N + nt + c] = out[ct][i];
+    }
+}
+
 // One whole triangular sweep per workgroup: the right-hand-side columns of a box are
 // independent, so the workgroup of (box, 64-column tile) runs every block row of its
 // tile in order (top down for L, bottom up for U) with no other workgroup involved.
@@ -672,7 +719,6 @@ static int grid_for(int nbox, int ntile) { return 8 * ((nbox + 7) / 8) * ntile; 
 static double gemm_flops(const int* op, int nbox) {
   return 2.0 * (op[2] - op[1]) * (double)(op[4] - op[3]) * (op[6] - op[5]) * nbox;
 }
-static double leaf_flops(const int* op, int nbox) { return 2.0 * op[2] * (double)op[2] * (op[4] - op[3]) * nbox; }
 
 template <typename T, bool PERM>
 static hipError_t launch_gemm(const Geom& g, const T* F, const int* perm, T* X, int ld, size_t xstride, const int* op,
@@ -686,19 +732,6 @@ static hipError_t launch_gemm(const Geom& g, const T* F, const int* perm, T* X, 
   return hipGetLastError();
 }
 
-template <typename T, bool UPPER, bool PERM>
-static hipError_t launch_leaf(const Geom& g, const int* perm, const T* dinv, T* X, int ld, size_t xstride,
-                              const int* op, int nbox, const int* active, hipStream_t st) {
-  const int r0 = op[1], w = op[2], cA = op[3], cB = op[4];
-  const int ntn = (cB - cA + 63) / 64;
-  if (w == 64)
-    hipLaunchKernelGGL((leaf_op_kernel<T, 64, UPPER, PERM>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, perm,
-                       dinv, X, ld, xstride, r0, cA, cB, nbox, ntn, active);
-  else
-    hipLaunchKernelGGL((leaf_op_kernel<T, 32, UPPER, PERM>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, perm,
-                       dinv, X, ld, xstride, r0, cA, cB, nbox, ntn, active);
-  return hipGetLastError();
-}
 
 template <typename T, int ROWS, int SP>
 static hipError_t launch_panel(const Geom& g, T* A, int* perm, T* dinv, int* info, int nbox, int c0, int w,
@@ -723,9 +756,15 @@ static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* 
     if (op[0] == kOpPanel) {
       ProfScope ps(prof, Profiler::kLuPanel, 0.0, st);
       e = launch_panel<T, ROWS, SP>(g, A, perm, dinv, info, nbox, op[1], op[2], st);
-    } else if (op[0] == kOpLeaf) {
-      ProfScope ps(prof, Profiler::kLuLeaf, leaf_flops(op, nbox), st);
-      e = launch_leaf<T, false, true>(g, perm, dinv, A, N, (size_t)N * N, op, nbox, nullptr, st);
+    } else if (op[0] == kOpRows) {
+      const int r0 = op[1], r1 = op[2], cA = op[3], cB = op[4], ntn = (cB - cA + 63) / 64;
+      for (int s = r0; s < r1 && e == hipSuccess; s += kPanel) {
+        const int w = (r1 - s) < kPanel ? (r1 - s) : kPanel;
+        ProfScope ps(prof, Profiler::kLuLeaf, (2.0 * w * (s - r0) + (double)w * w) * (cB - cA) * nbox, st);
+        hipLaunchKernelGGL((lu_rows_kernel<T>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, A, perm, dinv, r0,
+                           s, w, cA, cB, nbox, ntn);
+        e = hipGetLastError();
+      }
     } else {
       ProfScope ps(prof, Profiler::kLuGemm, gemm_flops(op, nbox), st);
       e = launch_gemm<T, true>(g, A, perm, A, N, (size_t)N * N, op, nbox, nullptr, st);
