@@ -37,13 +37,13 @@ def _check_leaf(prob, box_ids, precision, tol, f_on=True, tuning=None):
     return gout
 
 
-@pytest.mark.parametrize("p", [6, 7, 8, 9])
+@pytest.mark.parametrize("p", [4, 5, 6, 7, 8, 9])
 def test_leaf_fp64_small(gpu, p):
     prob = W.multi_bump((2, 2, 2), p, 6.0, 11, gaussian_source=True, name=f"bump_p{p}")
     _check_leaf(prob, range(8), "fp64", FP64_TOL)
 
 
-@pytest.mark.parametrize("p", [6, 8, 9])
+@pytest.mark.parametrize("p", [4, 5, 6, 8, 9])
 def test_leaf_fp32_ir_small(gpu, p):
     prob = W.multi_bump((2, 2, 2), p, 6.0, 12, gaussian_source=True, name=f"bump_p{p}")
     out = _check_leaf(prob, range(8), "fp32_ir", IR_TOL)
