@@ -68,7 +68,7 @@ def flops_per_box(n_i: int, n_b: int, passes: int) -> dict:
 class Runner:
     """Buffers and the per-chunk ABI call sequence for one precision."""
 
-    def __init__(self, prob, precision, nbox, chunk, ir_max_iter=3, ir_tol=1e-11, streams=1):
+    def __init__(self, prob, precision, nbox, chunk, ir_max_iter=3, ir_tol=1e-12, streams=1):
         import torch
         from paper_2503_04033_amd import interface as itf
         from paper_2503_04033_amd.leaf import LeafPlan
@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=24)
     ap.add_argument("--ir-max-iter", type=int, default=3)
-    ap.add_argument("--ir-tol", type=float, default=1e-11)
+    ap.add_argument("--ir-tol", type=float, default=1e-12)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (HBM counter calibration)")
     a = ap.parse_args()

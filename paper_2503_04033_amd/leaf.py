@@ -55,7 +55,7 @@ class LeafPlan:
     """Owns one hps_plan (Chebyshev tables on the device) for a box size and wavenumber."""
 
     def __init__(self, p: int, h, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
-                 ir_tol: float = 1e-11):
+                 ir_tol: float = 1e-12):
         self.lib = _lib.load()
         d = _lib.LeafDesc()
         d.p = int(p)

@@ -60,7 +60,7 @@ class TwoLevelSolver:
     """Solve -Lap u - kappa^2 b u = f on a box grid with Dirichlet data g."""
 
     def __init__(self, nboxes, lo, hi, p: int, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
-                 ir_tol: float = 1e-11, chunk: Optional[int] = None, keep_X: bool = True, device="cuda",
+                 ir_tol: float = 1e-12, chunk: Optional[int] = None, keep_X: bool = True, device="cuda",
                  refine: Optional[int] = None, refine_steps: int = 2, tuning: Optional[dict] = None):
         self.nboxes = tuple(int(v) for v in nboxes)
         self.nbox = int(np.prod(self.nboxes))

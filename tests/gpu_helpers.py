@@ -16,7 +16,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_leaf_boxes(prob, box_ids, precision="fp64", ir_max_iter=3, ir_tol=1e-11, f_on=True, tuning=None):
+def gpu_leaf_boxes(prob, box_ids, precision="fp64", ir_max_iter=3, ir_tol=1e-12, f_on=True, tuning=None):
     """Run a1..a4 on the listed boxes with a slot map that keeps every DtN block.
 
     tuning: optional {knob: value} set on the plan (hps_plan_set_tuning) first.
