@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void operators_kernel(Geom g, int nbox, const 
     }
     A[(size_t)r * N + col] = (T)v;
   }
-  if (threadIdx.x < nr && r0 + threadIdx.x < n) {  // exact |row| sum of A_ii (FP64)
+  if ((int)threadIdx.x < nr && r0 + (int)threadIdx.x < n) {  // exact |row| sum of A_ii (FP64)
     const int r = r0 + threadIdx.x;
     const int cd = g.coords[r];
     const int ii = cd & 255, jj = (cd >> 8) & 255, kk = cd >> 16;
@@ -1040,13 +1040,13 @@ __global__ __launch_bounds__(256) void getrs_t_kernel(Geom g, int nbox, const do
   for (int bk = 0; bk < g.npanel; bk++) {
     const int s = bk * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
     const double* Uinv = dinv + (size_t)(2 * bk + 1) * 64 * 64;
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       double acc = 0.0;
       for (int k = 0; k < w; k++) acc += Uinv[k * 64 + threadIdx.x] * vec[s + k];
       tmp[threadIdx.x] = acc;
     }
     __syncthreads();
-    if (threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
+    if ((int)threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
     __syncthreads();
     for (int j = s + w + threadIdx.x; j < N; j += blockDim.x) {
       double acc = 0.0;
@@ -1059,13 +1059,13 @@ __global__ __launch_bounds__(256) void getrs_t_kernel(Geom g, int nbox, const do
   for (int bk = g.npanel - 1; bk >= 0; bk--) {
     const int s = bk * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
     const double* Linv = dinv + (size_t)(2 * bk) * 64 * 64;
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       double acc = 0.0;
       for (int k = 0; k < w; k++) acc += Linv[k * 64 + threadIdx.x] * vec[s + k];
       tmp[threadIdx.x] = acc;
     }
     __syncthreads();
-    if (threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
+    if ((int)threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
     __syncthreads();
     for (int j = threadIdx.x; j < s; j += blockDim.x) {
       double acc = 0.0;
@@ -1141,13 +1141,13 @@ __global__ __launch_bounds__(256) void getrs_vec_kernel(Geom g, int nbox, const 
   }
   __syncthreads();
   auto block_inverse = [&](const T* Inv, int s, int w) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       double acc = 0.0;
       for (int k = 0; k < w; k++) acc += (double)Inv[threadIdx.x * 64 + k] * vec[s + k];
       tmp[threadIdx.x] = acc;
     }
     __syncthreads();
-    if (threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
+    if ((int)threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
     __syncthreads();
   };
   // rows [j0, j1) -= LU[perm[row]][s .. s+w) . vec[s .. s+w)

@@ -37,7 +37,6 @@ namespace hps {
 
 constexpr int kLuThreads = 512;
 constexpr int kLuWaves = kLuThreads / 64;
-constexpr int kLdsLd = 64 + 8;  // padded row length of LDS tiles
 
 // LDS of the panel kernel.  M = L11^{-1} and Nn = U11^{-1} of the panel's
 // growing diagonal block (positions [j0, j0+npv)), kept up to date after every
