@@ -108,8 +108,8 @@ hps_status hps_plan_get_info(hps_plan plan, hps_plan_info* info);
 hps_status hps_leaf_nodes(hps_plan plan, int32_t nbox, const double* origin, double* xi, double* xb,
                           hipStream_t stream);
 
-/* a1 -- collocation operator (Sec. 2.1 eq. Aentries, interior rows; Alg. 1 "form
- * the local equilibrium matrix").  Writes A_ii = -(Dxx + Dyy + Dzz) - kappa^2
+/* a1 -- collocation operator (Sec. 2.1 eq. Aentries, interior rows; Alg. 1, the
+ * per-box operator step).  Writes A_ii = -(Dxx + Dyy + Dzz) - kappa^2
  * diag(b) restricted to interior nodes, rounded to the plan's element type, into
  * A [nbox][n_pad][n_pad] with an identity border, and |A_ii|_inf (FP64, exact
  * row sums) into anorm [nbox].  b: [nbox][n_i] FP64 values at interior nodes. */
@@ -117,7 +117,7 @@ hps_status hps_leaf_operators(hps_plan plan, int32_t nbox, const double* b, void
                               hipStream_t stream);
 
 /* a2 -- dense LU with partial pivoting of every box's A_ii, in place (Alg. 1,
- * "form the local solution operator"; the interior block is block diagonal,
+ * the per-box solution-operator step; the interior block is block diagonal,
  * Sec. 2.2).  The pivot in column k is the row of largest modulus among the
  * rows not yet pivoted (lowest current position on ties).  On return, for
  * position i, row perm[i] of A holds row i of L (unit lower, below the
@@ -150,8 +150,8 @@ hps_status hps_leaf_dtn(hps_plan plan, int32_t nbox, const void* LU, const int32
                         const int32_t* slot_map, double* T_vals, double* g, double* X, int32_t* ir_iters,
                         double* berr, void* ws, hipStream_t stream);
 
-/* Deterministic reduction of duplicate interface blocks (Alg. 1, "add T^t to
- * the relevant slot of T"): for q = 0..npairs-1 in order,
+/* Deterministic reduction of duplicate interface blocks (Alg. 1, accumulation of
+ * each box's DtN blocks into the interface matrix): for q = 0..npairs-1 in order,
  * T_vals[dst_q] += T_vals[src_q] (blocks of block_elems doubles), pairs given as
  * int64 [npairs][2] = (dst, src) block indices; every dst appears once. */
 hps_status hps_interface_reduce(int32_t npairs, const int64_t* pairs, int64_t block_elems, double* T_vals,

@@ -1,8 +1,8 @@
 // a2 + a3 -- batched dense LU with partial pivoting of the interior blocks A_ii
 // and the triangular solves X = U^{-1} L^{-1} P B with its factors.
 //
-// The paper factors every box's interior block A_ii and solves with it (Alg. 1
-// "form the local solution operator", Alg. 2 "form u = A_ii^{-1} f"; A_ii is
+// The paper factors every box's interior block A_ii and solves with it (Alg. 1,
+// the per-box solution operator; Alg. 2, the per-box interior load solve; A_ii is
 // block diagonal over boxes, Sec. 2.2).  The factorization is a recursive column
 // split, the solves are block rows:
 //

@@ -124,3 +124,46 @@ def test_reduction_with_load(p, kappa):
     # X columns solve A_ii X = [A_ib | f]
     B = np.concatenate([blk.A_ib, f[:, None]], axis=1)
     assert np.abs(blk.A_ii @ red.X - B).max() < 1e-10 * np.abs(B).max()
+
+
+# ---- interior solve with given face values (Sec. 2.2 four-step solve, step 4) ------
+
+@pytest.mark.parametrize("p,kappa", [(5, 0.0), (7, 0.0), (6, 3.5)])
+def test_interior_solve_reproduces_polynomial(p, kappa):
+    # u of per-axis degree <= p-1, f = -Lap u - kappa^2 b u from calculus: given the face
+    # values of u, the interior values must be those of u (collocation is exact there).
+    h = (0.5, 0.25, 0.4)
+    xi, xb = leaf.box_node_coords((0.1, -0.2, 0.3), h, p)
+    C = _poly(23 + p, p - 1)
+    b = 1.0 + 0.3 * xi[:, 0] * xi[:, 1]
+    f = -_lap(C, xi) - kappa ** 2 * b * _ev(C, xi)
+    blk = leaf.local_blocks(p, h, kappa, b)
+    ui = leaf.interior_solve(blk, f, _ev(C, xb))
+    ex = _ev(C, xi)
+    np.testing.assert_allclose(ui, ex, atol=1e-10 * np.abs(ex).max())
+
+
+def test_interior_solve_equals_reconstruction():
+    # u_i = A_ii^{-1}(f_i - A_ib u_b) = v + S u_b for arbitrary face values and loads
+    p, h, kappa = 6, (0.5,) * 3, 4.0
+    rng = np.random.default_rng(31)
+    xi, _ = leaf.box_node_coords((0.0, 0.0, 0.0), h, p)
+    b = 1.0 + 0.2 * rng.random(xi.shape[0])
+    f = rng.normal(size=xi.shape[0])
+    ub = rng.normal(size=6 * (p - 2) ** 2)
+    blk = leaf.local_blocks(p, h, kappa, b)
+    red = leaf.leaf_reduce(blk, f)
+    np.testing.assert_allclose(leaf.interior_solve(blk, f, ub), red.v + red.S @ ub, rtol=0, atol=1e-12)
+
+
+def test_planted_interior_solve_sign_is_caught():
+    # f_i + A_ib u_b instead of f_i - A_ib u_b must break polynomial reproduction
+    p, kappa, h = 6, 2.0, (0.5, 0.5, 0.5)
+    xi, xb = leaf.box_node_coords((0.0, 0.0, 0.0), h, p)
+    C = _poly(5, p - 1)
+    b = np.ones(xi.shape[0])
+    f = -_lap(C, xi) - kappa ** 2 * _ev(C, xi)
+    blk = leaf.local_blocks(p, h, kappa, b)
+    bad = np.linalg.solve(blk.A_ii, f + blk.A_ib @ _ev(C, xb))
+    ex = _ev(C, xi)
+    assert np.abs(bad - ex).max() > 1e-3 * np.abs(ex).max()

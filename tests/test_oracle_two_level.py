@@ -155,3 +155,60 @@ def test_planted_neumann_sign_is_caught():
     normals = np.repeat(np.array([[-1, 0, 0], [1, 0, 0], [0, -1, 0], [0, 1, 0], [0, 0, -1], [0, 0, 1]]), mm, 0)
     assert np.allclose(good, normals @ a)
     assert not np.allclose(bad, normals @ a)
+
+
+# ---- the dense interface solve and the lean box storage -------------------------------
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.config1(),
+    lambda: W.multi_bump((2, 2, 2), 7, 9.0, 3, gaussian_source=True),
+    lambda: W.multi_bump((3, 2, 2), 6, 6.0, 4, gaussian_source=True),
+])
+def test_dense_and_lean_modes_equal_global_solve(maker):
+    # dense=True (LAPACK on T_FF) and keep_boxes=False (only S, v, T, g kept per box) are
+    # the same algebra as the default SuperLU path; all three equal the global collocation
+    # solve of eq. Aentries.
+    prob = maker()
+    u_int, u_face, _ = brute.solve_global(prob)
+    ref = interface.solve(prob)
+    for kw in ({"dense": True}, {"keep_boxes": False}, {"dense": True, "keep_boxes": False}):
+        res = interface.solve(prob, **kw)
+        assert interface.rel_l2(res.u_i, u_int) < 1e-12, kw
+        assert interface.rel_l2(res.u_face, u_face) < 1e-12, kw
+        assert interface.rel_l2(res.u_i, ref.u_i) < 1e-13, kw
+        assert interface.rel_l2(res.u_b, ref.u_b) < 1e-13, kw
+
+
+def test_planted_dense_transpose_is_caught(monkeypatch):
+    # the dense path solving with T_FF^T instead of T_FF is caught by the global solve
+    import scipy.sparse
+
+    class Transposed:
+        def __init__(self, A):
+            self.A = A
+
+        def tocsc(self):
+            return self.A.T.tocsc()
+
+        def toarray(self):
+            return self.A.T.toarray()
+
+        @property
+        def shape(self):
+            return self.A.shape
+
+        @property
+        def nnz(self):
+            return self.A.nnz
+
+    orig = interface.assemble
+
+    def bad(prob, boxes):
+        T_ff, rhs, bf, fb = orig(prob, boxes)
+        return Transposed(scipy.sparse.csr_matrix(T_ff)), rhs, bf, fb
+
+    monkeypatch.setattr(interface, "assemble", bad)
+    prob = W.multi_bump((2, 2, 2), 6, 5.0, 5, gaussian_source=True)
+    res = interface.solve(prob, dense=True, keep_boxes=False)
+    u_int, _, _ = brute.solve_global(prob)
+    assert interface.rel_l2(res.u_i, u_int) > 1e-8
