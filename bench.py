@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "leaf boxes/s + % MFMA peak at p=16; FP32+IR vs FP64 path at <=1e-9 rel err"
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64_MFMA = 78.6e12
+PEAK_HBM = 8.0e12
 
 
 def log(*a):
@@ -60,9 +61,59 @@ def measured_traffic(kernel: str):
         return None
 
 
-def flops_per_box(n_i: int, n_b: int, passes: int) -> dict:
-    """Algorithmic flops of one box: LU 2/3 n^3, each solve pass 2 n^2 (n_b + 1)."""
-    return {"lu": 2.0 / 3.0 * n_i ** 3, "solve": passes * 2.0 * n_i ** 2 * (n_b + 1)}
+def host_cpu() -> dict:
+    """Model name and logical CPU count of the host (for the CPU baseline record)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def solve_stage(torch, prob, precision: str) -> dict:
+    """Build and solve stages end to end on a grid whose interface system the host solves
+    (paper Alg. 1 and Alg. 2): GPU build (a1-a4), copy of T and the loads, host factorization
+    of the interface matrix, interface solve, and the GPU interiors with the solve stage's
+    outer refinement (FP32+IR).  Wall-clock seconds per part; inputs resident in HBM."""
+    from paper_2503_04033_amd import interface as itf
+    from paper_2503_04033_amd.solver import TwoLevelSolver
+    s = TwoLevelSolver.for_problem(prob, precision=precision)
+    bv, fv, gv, _, _ = s.sample(prob.b, prob.f, prob.g)
+    s.build(bv, fv, gv)  # warm-up (kernel loading, allocator)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    br = s.build(bv, fv, gv)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    T_host = br.T_vals.cpu().numpy()
+    t2 = time.perf_counter()
+    isolver = itf.InterfaceSolver(s.layout, T_host)
+    t3 = time.perf_counter()
+    u_face, ub, ui, _ = s.solve(br, gv, isolver, b=bv, f=fv)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    # one pass of the GPU interiors alone (what the solve stage repeats per refinement round)
+    ub_d = torch.tensor(ub, device=s.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    if s.refine > 0 or br.X is None:
+        s._interiors(br, ub_d, bv, fv, want_flux=False)
+    else:
+        s.plan.hps_leaf_reconstruct(s.nbox, br.X, ub_d, torch.empty_like(ui))
+    e1.record()
+    torch.cuda.synchronize()
+    return {"precision": precision, "nbox": s.nbox, "interface_unknowns": int(s.layout.nunknown),
+            "interface_method": isolver.method, "keep": s.keep, "chunk": s.chunk, "refine_rounds": s.refine,
+            "build_s": round(t1 - t0, 4), "copy_T_s": round(t2 - t1, 4), "interface_factor_s": round(t3 - t2, 4),
+            "solve_stage_s": round(t4 - t3, 4), "interiors_gpu_ms": round(e0.elapsed_time(e1), 3),
+            "end_to_end_s": round(t4 - t0, 4), "u_i": ui, "u_face": u_face,
+            "interior_fp64_boxes": len(br.extra.get("interior_fp64", [])),
+            "build_fp64_fallback_boxes": len(br.extra.get("fp64_fallback", []))}
 
 
 class Runner:
@@ -92,7 +143,7 @@ class Runner:
         self.streams = [torch.cuda.Stream() for _ in range(streams)] if streams > 1 else None
         self.bufsets = [self.plan.alloc(self.chunk, dev) for _ in range(max(streams, 1))]
         self.slot_map = torch.tensor(self.layout.slot_map[:nbox], device=dev).contiguous()
-        self.pairs = torch.tensor(self.layout.reduce_pairs, device=dev)
+        self.triples = torch.tensor(self.layout.reduce_triples, device=dev)
         self.ev = {k: [] for k in ("operators", "factor", "dtn")}
 
     def step(self, b, g_dir, record=False):
@@ -138,10 +189,10 @@ class Runner:
             self.ev["dtn"].append((e[2], e[3], nb))
 
     def _reduce(self):
-        if self.pairs.shape[0] and self.nbox == self.prob.nbox:
+        if self.triples.shape[0] and self.nbox == self.prob.nbox:
             from paper_2503_04033_amd.leaf import hps_interface_reduce
             mm = self.info.m ** 2
-            hps_interface_reduce(self.pairs, mm * mm, self.T_vals)
+            hps_interface_reduce(self.triples, mm * mm, self.T_vals)
 
     def phase_ms(self):
         out = {}
@@ -166,7 +217,7 @@ def cpu_baseline(prob, nsample: int, seed: int = 0) -> dict:
         ol.leaf_reduce(blk, prob.f(xi))
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return {"value": nsample / dt, "unit": "boxes/s", "cores": int(threads), "kind": "oracle",
+    return {"value": nsample / dt, "unit": "boxes/s", "cores": int(threads), "kind": "oracle", "host": host_cpu(),
             "sample": f"{nsample} seeded boxes of the same 16^3 p=16 workload (operator + dense LU + "
                       f"{prob.p - 2}^3-row solve with {6 * (prob.p - 2) ** 2 + 1} right-hand sides + DtN), "
                       f"{dt:.1f} s"}
@@ -184,6 +235,8 @@ def main():
                          "than one overlaps kernels, so per-kernel event times then include the overlap")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve-stage", action="store_true",
+                    help="skip the end-to-end build + solve timing at 4x4x4 boxes, p = 16")
     ap.add_argument("--cpu-sample", type=int, default=24)
     ap.add_argument("--ir-max-iter", type=int, default=3)
     ap.add_argument("--ir-tol", type=float, default=1e-12)
@@ -251,26 +304,49 @@ def main():
     info_bad = int((fp32.infov.cpu().numpy() != 0).sum())
     log(f"fp32_ir: {ms:.1f} ms/step, {boxes_s:.1f} boxes/s (wall {wall:.1f} s); phases {phases}")
     steps = np.where(iters >= 0, iters, -1 - iters)  # corrections applied per box
-    passes = 1 + float(np.mean(steps))
-    fl = flops_per_box(i.n_i, i.n_b, passes)
-    tot_flops = nbox * (fl["lu"] + fl["solve"])
     fams = fp32.plan.profile_read()
-    # The library records the flops of every box a launch covers, but in the correction passes
-    # boxes that have already converged exit at once: count only the passes that ran.
-    launched_passes = 1 + a.ir_max_iter
-    for k in ("solve_fwd", "solve_bwd"):
-        fams[k]["flops"] *= passes / launched_passes
+    # algorithmic flops per step: LU 2/3 n_i^3 per box; each solve pass 2 n_i^2 (n_b + 1) per
+    # box that runs it (the library counts n_i^2 (n_b + 1) per sweep and active box)
+    lu_alg = nbox * 2.0 / 3.0 * i.n_i ** 3
+    solve_alg = (fams["solve_fwd"]["flops"] + fams["solve_bwd"]["flops"]) / a.steps
+    solve_exec = (fams["solve_fwd"]["exec_flops"] + fams["solve_bwd"]["exec_flops"]) / a.steps
+    tot_flops = lu_alg + solve_alg
     KNAMES = {"solve_fwd": "trsm_row_kernel<float, false, false, 4>", "solve_bwd": "trsm_row_kernel<float, true, false, 4>",
               "lu_gemm": "gemm_op_kernel<float, true>", "lu_panel": "lu_panel_kernel<float, 6, 8, 64>",
               "residual": "residual_mfma_kernel<14, 2, 8, double>"}
     # the LU/TRSM phase: device time of the factorization and solve kernels (events around
-    # each launch) against the algorithmic LU and solve flops of the step
+    # each launch) against the LU and solve flops of the step, algorithmic and as executed
+    # (the first forward sweep skips the structurally zero leading rows of A_ib's columns)
     ph_ms = sum(fams[k]["ms"] for k in ("lu_gemm", "lu_panel", "lu_leaf", "solve_fwd", "solve_bwd")) / a.steps
-    lu_trsm = {"ms_per_step": round(ph_ms, 3), "tflops": round(tot_flops / (ph_ms / 1e3) / 1e12, 2),
-               "frac_fp32_mfma_peak": round(tot_flops / (ph_ms / 1e3) / PEAK_FP32_MFMA, 4)}
+    lu_trsm = {"ms_per_step": round(ph_ms, 3),
+               "tflops": round(tot_flops / (ph_ms / 1e3) / 1e12, 2),
+               "frac_fp32_mfma_peak": round(tot_flops / (ph_ms / 1e3) / PEAK_FP32_MFMA, 4),
+               "tflops_executed": round((lu_alg + solve_exec) / (ph_ms / 1e3) / 1e12, 2),
+               "frac_fp32_mfma_peak_executed": round((lu_alg + solve_exec) / (ph_ms / 1e3) / PEAK_FP32_MFMA, 4),
+               "solve_flops_per_step": {"algorithmic": solve_alg, "executed": solve_exec},
+               "first_forward_skipped_frac": None}
+    fw = fams["solve_fwd"]
+    if fw["flops"]:
+        # executed / algorithmic of all forward sweeps; the first sweep is the one that skips
+        first_alg = nbox * i.n_i ** 2 * (i.n_b + 1) * a.steps
+        pad = (i.n_pad / i.n_i) ** 2
+        lu_trsm["first_forward_skipped_frac"] = round(1.0 - (fw["exec_flops"] - (fw["flops"] - first_alg) * pad) /
+                                                      (first_alg * pad), 4)
     dom = max(fams, key=lambda k: fams[k]["ms"])
     fd = fams[dom]
     achieved = fd["flops"] / (fd["ms"] / 1e3) if fd["ms"] > 0 else 0.0
+    # bandwidth kernels: algorithmic HBM bytes per step over their event time
+    nrhs = i.n_b + 1
+    res_bytes = nbox * i.n_i * nrhs * 8.0 + float(steps.sum()) * i.n_i * nrhs * 12.0
+    bw = {"operators": nbox * (i.n_pad ** 2 * 4.0 + i.n_i * 8.0),
+          "dtn": nbox * (i.n_i * nrhs * 8.0 + i.n_b ** 2 * 8.0 + i.n_b * 8.0),
+          "residual": res_bytes}
+    bandwidth = {}
+    for k, byt in bw.items():
+        t = fams[k]["ms"] / a.steps / 1e3
+        if t > 0:
+            bandwidth[k] = {"ms_per_step": round(t * 1e3, 3), "algorithmic_GB_per_step": round(byt / 1e9, 3),
+                            "TB_s": round(byt / t / 1e12, 3), "frac_hbm_peak": round(byt / t / PEAK_HBM, 4)}
     result = {
         "metric": METRIC, "value": round(boxes_s, 2), "unit": "boxes/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
@@ -286,13 +362,16 @@ def main():
                "berr_max": float(berr.max()), "lu_info_nonzero": info_bad},
         "phase_ms_per_step": {k: round(v["ms_total"] / a.steps, 3) for k, v in phases.items()},
         "kernel_families_per_step": {k: {"launches": v["launches"] // a.steps, "ms": round(v["ms"] / a.steps, 3),
-                                         "tflops": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2) if v["ms"] and v["flops"] else None}
+                                         "tflops": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2) if v["ms"] and v["flops"] else None,
+                                         "tflops_executed": round(v["exec_flops"] / (v["ms"] / 1e3) / 1e12, 2) if v["ms"] and v["exec_flops"] else None}
                                      for k, v in fams.items()},
+        "bandwidth_kernels": bandwidth,
         "roofline": {"kernel": KNAMES.get(dom, dom), "bound": "mfma" if fd["flops"] else "hbm",
                      "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(KNAMES.get(dom, dom)),
                      "per_launch": {"launches": fd["launches"], "avg_ms": round(fd["ms"] / max(fd["launches"], 1), 4),
-                                    "avg_algorithmic_flops": fd["flops"] / max(fd["launches"], 1)}},
+                                    "avg_algorithmic_flops": fd["flops"] / max(fd["launches"], 1),
+                                    "avg_executed_flops": fd["exec_flops"] / max(fd["launches"], 1)}},
     }
     log(f"whole path {tot_flops / (ms / 1e3) / 1e12:.2f} TFLOP/s; dominant {dom}: {achieved / 1e12:.2f} TFLOP/s")
     # ---- FP64 path beside it ----
@@ -321,6 +400,24 @@ def main():
         log(f"fp64: {ms64:.1f} ms/step; dT {dT:.2e} dg {dg:.2e}")
         del fp64
         torch.cuda.empty_cache()
+    if not a.no_solve_stage and not a.nbox:
+        # end to end (build, interface factorization and solve, interiors) where the host
+        # interface solve fits: the same family at 4x4x4 boxes, p = 16, kappa = 40
+        small = W.multi_bump((4, 4, 4), 16, 40.0, 3, name="cfg3_4x4x4_p16")
+        legs = {}
+        for prec in ("fp32_ir", "fp64"):
+            legs[prec] = solve_stage(torch, small, prec)
+            torch.cuda.empty_cache()
+            log(f"solve stage {prec}: { {k: v for k, v in legs[prec].items() if k not in ('u_i', 'u_face')} }")
+        du = float(torch.linalg.norm(legs["fp32_ir"]["u_i"] - legs["fp64"]["u_i"]) /
+                   torch.linalg.norm(legs["fp64"]["u_i"]))
+        df = float(np.linalg.norm(legs["fp32_ir"]["u_face"] - legs["fp64"]["u_face"]) /
+                   np.linalg.norm(legs["fp64"]["u_face"]))
+        for v in legs.values():
+            v.pop("u_i")
+            v.pop("u_face")
+        result["solve_stage_4x4x4_p16"] = {"legs": legs, "rel_diff_u_i_fp32ir_vs_fp64": du,
+                                           "rel_diff_u_face_fp32ir_vs_fp64": df}
     if not a.no_cpu:
         result["cpu_baseline"] = cpu_baseline(prob, a.cpu_sample)
         log(f"cpu baseline {result['cpu_baseline']}")

@@ -151,10 +151,14 @@ hps_status hps_leaf_dtn(hps_plan plan, int32_t nbox, const void* LU, const int32
                         double* berr, void* ws, hipStream_t stream);
 
 /* Deterministic reduction of duplicate interface blocks (Alg. 1, accumulation of
- * each box's DtN blocks into the interface matrix): for q = 0..npairs-1 in order,
- * T_vals[dst_q] += T_vals[src_q] (blocks of block_elems doubles), pairs given as
- * int64 [npairs][2] = (dst, src) block indices; every dst appears once. */
-hps_status hps_interface_reduce(int32_t npairs, const int64_t* pairs, int64_t block_elems, double* T_vals,
+ * each box's DtN blocks into the interface matrix).  The diagonal block of an
+ * internal face receives one contribution from each of its two boxes; each box
+ * writes its contribution to a slot of its own and this call forms, for
+ * q = 0..ntrip-1, T_vals[dst_q] = T_vals[lo_q] + T_vals[hi_q] (blocks of
+ * block_elems doubles; triples int64 [ntrip][3] = (dst, lo, hi) block indices,
+ * every dst once, no dst equal to any lo or hi).  The sources are left intact, so
+ * calling it again after some boxes were recomputed gives the right sums. */
+hps_status hps_interface_reduce(int32_t ntrip, const int64_t* triples, int64_t block_elems, double* T_vals,
                                 hipStream_t stream);
 
 /* a5 -- reconstruction (Sec. 2.2 step 4; Alg. 2 last loop): u_i = X_f - X_b u_b
@@ -170,12 +174,19 @@ hps_status hps_leaf_reconstruct(hps_plan plan, int32_t nbox, const double* X, co
  * `steps` times r = f_i - A_ib u_b - A_ii u (FP64, tensor structure of the
  * operator), u += (LU)^{-1} r.  The vector solves run in FP64 arithmetic on the
  * stored (FP32 or FP64) factors; with FP32 factors each step gains about six
- * digits on these boxes, so 2 steps reach FP64 rounding.  b, f_i (NULL = 0),
- * u_i: [nbox][n_i]; u_b: [nbox][n_b]; steps in 0..8.  ws: hps_plan_info.ws_bytes
- * per box (uses nbox * n_i doubles).  Any precision. */
+ * digits on well-conditioned boxes, so 2 steps reach FP64 rounding.
+ * b, f_i (NULL = 0), u_i: [nbox][n_i]; u_b: [nbox][n_b]; steps in 0..8.
+ * berr [nbox] (may be NULL): the final normwise backward error
+ *   max|f_i - A_ib u_b - A_ii u| / (|A_ii|_inf max|u| + max|f_i - A_ib u_b|)
+ * (NaN counts as +inf); anorm [nbox] (|A_ii|_inf from hps_leaf_operators) is
+ * required when berr is given.  A caller compares berr with its tolerance: on
+ * an ill-conditioned box FP32 factors can leave it large, and that box then
+ * needs FP64 factors.  ws: hps_plan_info.ws_bytes per box (uses
+ * 8 nbox (n_i + 3) bytes).  Any precision. */
 hps_status hps_leaf_interior_solve(hps_plan plan, int32_t nbox, const void* LU, const int32_t* perm,
-                                  const void* dinv, const double* b, const double* f, const double* u_b,
-                                  double* u_i, int32_t steps, void* ws, hipStream_t stream);
+                                  const void* dinv, const double* b, const double* anorm, const double* f,
+                                  const double* u_b, double* u_i, int32_t steps, double* berr, void* ws,
+                                  hipStream_t stream);
 
 /* Outward normal derivative at every face node of every box, flux = A_bi u_i +
  * A_bb u_b (the face rows of eq. Aentries: (2/h_a) D[p-1][.] along the normal line
@@ -229,19 +240,25 @@ const char* hps_status_string(hps_status s);
  * the block rows of one triangular sweep) is bracketed by HIP events on its
  * stream; hps_plan_profile_read synchronizes on the recorded events and
  * returns, per kernel family, the number of kernel launches, total
- * milliseconds and the algorithmic flops of those launches (2*M*N*K for tile
- * GEMMs, 2*w*w*ncols for leaves, n_pad^2 * (n_b + 1) per box for a triangular
- * sweep even where structurally zero blocks are skipped, 0 for bandwidth
- * kernels).  Families: 0 LU GEMM, 1 LU panel, 2 LU triangular solves (leaves and
- * short block rows: 2*w*K*ncols + w*w*ncols), 3 forward solve (L),
- * 4 backward solve (U), 5 residual, 6 DtN, 7 operators.  Enabling clears the
- * counters.  Event recording adds launch overhead; leave it off in
- * production. */
+ * milliseconds, the algorithmic flops of those launches and the flops the
+ * kernels executed.  Algorithmic: 2*M*N*K for tile GEMMs, 2*w*K*ncols + w*w*ncols
+ * for the LU's short triangular solves, n_i^2 * (n_b + 1) per box and sweep for
+ * the solves of hps_leaf_dtn (boxes whose refinement has already converged run
+ * no correction and count nothing), 0 for bandwidth kernels.  Executed equals
+ * algorithmic except for the solves, where it sums 2 w K + w^2 per 64-row block
+ * row over the real right-hand-side columns of each 64-column tile on the padded
+ * size n_pad, leaving out the block rows of the first forward sweep that are
+ * structurally zero and skipped.  Families: 0 LU GEMM, 1 LU panel, 2 LU
+ * triangular solves, 3 forward solve (L), 4 backward solve (U), 5 residual,
+ * 6 DtN, 7 operators.  Enabling clears the counters.  Event recording adds
+ * launch overhead and, for the solve flops, a host copy of small per-box arrays
+ * with a stream synchronization per solve; leave it off in production. */
 #define HPS_PROFILE_FAMILIES 8
 typedef struct {
   int64_t launches[HPS_PROFILE_FAMILIES];
   double ms[HPS_PROFILE_FAMILIES];
   double flops[HPS_PROFILE_FAMILIES];
+  double exec_flops[HPS_PROFILE_FAMILIES];
 } hps_profile;
 hps_status hps_plan_profile_enable(hps_plan plan, int32_t enable);
 hps_status hps_plan_profile_read(hps_plan plan, hps_profile* out);

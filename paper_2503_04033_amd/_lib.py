@@ -38,7 +38,8 @@ class PlanInfo(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8), ("flops", C.c_double * 8)]
+    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8), ("flops", C.c_double * 8),
+                ("exec_flops", C.c_double * 8)]
 
 
 class HpsError(RuntimeError):
@@ -70,7 +71,7 @@ def load() -> C.CDLL:
         "hps_leaf_reconstruct": [P, I32, P, P, P, P],
         "hps_leaf_adjoint_solve": [P, I32, P, P, P, P, P, P, P, P, P, P],
         "hps_leaf_adjoint_grad": [P, I32, P, P, P, P],
-        "hps_leaf_interior_solve": [P, I32, P, P, P, P, P, P, P, I32, P, P],
+        "hps_leaf_interior_solve": [P, I32, P, P, P, P, P, P, P, P, I32, P, P, P],
         "hps_leaf_flux": [P, I32, P, P, P, P],
         "hps_plan_profile_enable": [P, I32],
         "hps_plan_profile_read": [P, C.POINTER(Profile)],

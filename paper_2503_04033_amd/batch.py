@@ -24,7 +24,7 @@ import torch
 
 from . import interface as itf
 from .leaf import LeafPlan, hps_interface_reduce
-from .solver import _box_origins
+from .solver import _box_origins, fp64_redo
 
 
 @dataclass
@@ -47,7 +47,7 @@ class Group:
     iters: torch.Tensor = None
     berr: torch.Tensor = None
     slot_map: torch.Tensor = None
-    pairs: torch.Tensor = None
+    triples: torch.Tensor = None
     extra: dict = field(default_factory=dict)
 
     @property
@@ -118,7 +118,7 @@ class BatchedLeafReduction:
             gr.iters = torch.zeros(gr.nbox, dtype=torch.int32, device=self.device)
             gr.berr = torch.zeros(gr.nbox, dtype=torch.float64, device=self.device)
             gr.slot_map = torch.tensor(gr.layout.slot_map, device=self.device)
-            gr.pairs = torch.tensor(gr.layout.reduce_pairs, device=self.device)
+            gr.triples = torch.tensor(gr.layout.reduce_triples, device=self.device)
 
     def enqueue(self) -> None:
         """All launches of the build stage for every group, on the current stream."""
@@ -132,8 +132,8 @@ class BatchedLeafReduction:
                 plan.hps_leaf_dtn(nb, B["A"], B["perm"], B["dinv"], gr.b[sl], B["anorm"],
                                   gr.f[sl] if gr.f is not None else None, gr.g_dir[sl], gr.slot_map[sl],
                                   gr.T_vals, gr.g_loads[sl], B["X"], gr.iters[sl], gr.berr[sl], B["ws"])
-            if gr.pairs.shape[0]:
-                hps_interface_reduce(gr.pairs, mm * mm, gr.T_vals)
+            if gr.triples.shape[0]:
+                hps_interface_reduce(gr.triples, mm * mm, gr.T_vals)
 
     def capture(self) -> None:
         """Record the whole build stage in a HIP graph (after one eager warm-up run)."""
@@ -153,6 +153,29 @@ class BatchedLeafReduction:
             self.graph.replay()
         else:
             self.enqueue()
+
+    def fallback(self) -> dict:
+        """After run(): boxes whose FP64 refinement ended above ir_tol (ir_iters < 0) are
+        factored and solved again with an FP64 plan, eagerly (outside any captured graph),
+        and the shared diagonal blocks are reduced again (the reduction only reads the two
+        boxes' own slots, so repeating it is exact).  Their ir_iters stay negative.
+        Returns {group index: list of box ids redone}."""
+        done = {}
+        for q, gr in enumerate(self.groups):
+            if self.precision != "fp32_ir":
+                continue
+            ids = torch.nonzero(gr.iters < 0).flatten().cpu().tolist()
+            gr.extra["fp64_fallback"] = ids
+            if not ids:
+                continue
+            if "plan64" not in gr.extra:
+                gr.extra["plan64"] = LeafPlan(gr.p, gr.h, gr.kappa, "fp64")
+            fp64_redo(gr.extra["plan64"], ids, gr.b, gr.f, gr.g_dir, gr.slot_map, gr.T_vals, gr.g_loads, gr.berr,
+                      gr.chunk, self.device)
+            if gr.triples.shape[0]:
+                hps_interface_reduce(gr.triples, gr.plan.info.m ** 4, gr.T_vals)
+            done[q] = ids
+        return done
 
 
 TRSM_KNOBS = ({"trsm_schedule": 0, "trsm_waves": 4}, {"trsm_schedule": 0, "trsm_waves": 6},

@@ -17,6 +17,7 @@ struct hps_plan_s {
   double* tables;  // device: t[p], D[p*p], D2[p*p]
   int* coords;     // device: interior node coordinates (packed)
   std::vector<int> lu_ops;  // LU schedule (records of 8 ints)
+  std::vector<int> gmap_h;  // host copy of g.gmap (internal -> natural 16-column group)
   hps::Profiler prof;                          // optional kernel timing
   const double* t;
   int trsm_sched = hps::kTrsmRows;             // HPS_TUNE_TRSM_SCHEDULE
@@ -37,6 +38,7 @@ hps_status dev(hipError_t e) { return e == hipSuccess ? HPS_OK : HPS_EDEVICE; }
   } while (0)
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
 
 // Gauss-Lobatto points t_j = -cos(pi j/(p-1)) and the barycentric
 // differentiation matrix on them (weights (-1)^j, halved at the end points),
@@ -143,6 +145,53 @@ WsLayout ws_layout(const hps_plan_s* pl, int nbox, void* ws) {
 
 bool bad_plan(hps_plan p) { return p == nullptr; }
 
+// Profiling only (synchronizes the stream): the flops of one solve over nbox boxes.
+// Algorithmic: n_i^2 (n_b + 1) per sweep and active box.  Executed: per 64-column tile
+// and 64-row block row, (2 w K + w^2) times the tile's columns that are real right-hand
+// sides, K the rows the block row's product runs over; the forward sweep of a tile with
+// first nonzero row ks stores block rows that end above ks as zeros and starts K at ks.
+hps::SolveFlops solve_flops(const hps_plan_s* pl, int nbox, const int* kstart_dev, const int* active_dev,
+                            hipStream_t st) {
+  const Geom& g = pl->g;
+  const int ntn = g.ldx / 64, N = g.n_pad;
+  std::vector<int> act(nbox, 1), ks;
+  if (active_dev) (void)hipMemcpyAsync(act.data(), active_dev, sizeof(int) * nbox, hipMemcpyDeviceToHost, st);
+  if (kstart_dev) {
+    ks.resize((size_t)nbox * ntn);
+    (void)hipMemcpyAsync(ks.data(), kstart_dev, sizeof(int) * ks.size(), hipMemcpyDeviceToHost, st);
+  }
+  (void)hipStreamSynchronize(st);
+  std::vector<double> cols(ntn, 0.0);
+  for (int tn = 0; tn < ntn; tn++)
+    for (int q = 0; q < 4; q++) {
+      const int grp = pl->gmap_h[4 * tn + q];
+      cols[tn] += std::max(0, std::min(16, g.nrhs - 16 * grp));
+    }
+  double full = 0.0;  // executed flops of a full sweep: sum over block rows of 2 w K + w^2 = N^2
+  for (int tn = 0; tn < ntn; tn++) full += (double)N * N * cols[tn];
+  hps::SolveFlops f{0.0, 0.0, 0.0};
+  for (int b = 0; b < nbox; b++) {
+    if (!act[b]) continue;
+    f.alg += (double)g.n * g.n * g.nrhs;
+    f.bwd_exec += full;
+    if (ks.empty()) {
+      f.fwd_exec += full;
+      continue;
+    }
+    for (int tn = 0; tn < ntn; tn++) {
+      const int k0 = ks[(size_t)b * ntn + tn];
+      double t = 0.0;
+      for (int s = 0; s < N; s += 64) {
+        const int w = std::min(64, N - s);
+        if (s + w <= k0) continue;
+        t += 2.0 * w * std::max(0, s - k0) + (double)w * w;
+      }
+      f.fwd_exec += t * cols[tn];
+    }
+  }
+  return f;
+}
+
 }  // namespace
 
 extern "C" {
@@ -225,6 +274,7 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
       coords[g.n + i] = order[i];
       coords[g.n + ngrp + order[i]] = i;
     }
+    pl->gmap_h = order;
   }
   if (hipMalloc(&pl->coords, coords.size() * sizeof(int)) != hipSuccess) {
     (void)hipFree(pl->tables);
@@ -322,9 +372,11 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     double* B = static_cast<double*>(L.B);
     HPS_TRY(hps::launch_rhs<double>(g, nbox, f, B, L.maxb, st));
     HPS_TRY(hps::launch_rhs_first_row(g, nbox, perm, f != nullptr, L.kstart, nullptr, st));
+    hps::SolveFlops sf{};
+    if (pl->prof.on) sf = solve_flops(pl, nbox, L.kstart, nullptr, st);
     HPS_TRY(hps::getrs_run<double>(g, static_cast<const double*>(LU), perm,
                                    static_cast<const double*>(dinv), B, X, nbox, nullptr, st, &pl->prof, nullptr, 0,
-                                   pl->trsm_sched, pl->trsm_waves, L.kstart));
+                                   pl->trsm_sched, pl->trsm_waves, L.kstart, 0, nullptr, &sf));
     if (ir_iters) HPS_TRY(hps::launch_fill_int(ir_iters, 0, nbox, st));
     if (berr) {
       HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
@@ -343,8 +395,10 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     // First solve into Y32 only: X0 = Y32 is exact in FP32 and is read from there.  The
     // residual writes R32 in the factor's row order, so each correction runs in place in
     // B; the first correction writes X = X0 + d once, later ones X += d.
+    hps::SolveFlops sf{};
+    if (pl->prof.on) sf = solve_flops(pl, nbox, L.kstart, nullptr, st);
     HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, L.Y32, nbox, nullptr, st, &pl->prof, nullptr, 0,
-                                  pl->trsm_sched, pl->trsm_waves, L.kstart));
+                                  pl->trsm_sched, pl->trsm_waves, L.kstart, 0, nullptr, &sf));
     HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
     const int kmax = pl->desc.ir_max_iter;
     const double tol = pl->desc.ir_tol;
@@ -363,8 +417,10 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
                                    st));
       if (it == 0) HPS_TRY(hps::launch_x_from_y(g, nbox, L.Y32, X, L.active, st));  // boxes done after 0 steps
       if (last) break;
+      hps::SolveFlops sfc{};
+      if (pl->prof.on) sfc = solve_flops(pl, nbox, nullptr, L.active, st);
       HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, B, nbox, L.active, st, &pl->prof, X, it == 0 ? 3 : 2,
-                                    pl->trsm_sched, pl->trsm_waves, nullptr, 1, L.Y32));
+                                    pl->trsm_sched, pl->trsm_waves, nullptr, 1, L.Y32, &sfc));
     }
   }
   hps::ProfScope ps(&pl->prof, hps::Profiler::kDtn, 0.0, st);
@@ -373,10 +429,10 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
   return dev(hps::launch_dtn(g, nbox, X, g_dir, slot_map, T_vals, gload, static_cast<double*>(L.B), st));
 }
 
-hps_status hps_interface_reduce(int32_t npairs, const int64_t* pairs, int64_t block_elems, double* T_vals,
+hps_status hps_interface_reduce(int32_t ntrip, const int64_t* triples, int64_t block_elems, double* T_vals,
                                 hipStream_t st) {
-  if (npairs < 0 || npairs > 65535 || block_elems <= 0 || (npairs > 0 && (!pairs || !T_vals))) return HPS_EINVAL;
-  return dev(hps::launch_reduce(npairs, reinterpret_cast<const long long*>(pairs), block_elems, T_vals, st));
+  if (ntrip < 0 || ntrip > 65535 || block_elems <= 0 || (ntrip > 0 && (!triples || !T_vals))) return HPS_EINVAL;
+  return dev(hps::launch_reduce(ntrip, reinterpret_cast<const long long*>(triples), block_elems, T_vals, st));
 }
 
 hps_status hps_leaf_reconstruct(hps_plan pl, int32_t nbox, const double* X, const double* u_b, double* u_i,
@@ -386,18 +442,27 @@ hps_status hps_leaf_reconstruct(hps_plan pl, int32_t nbox, const double* X, cons
   return dev(hps::launch_reconstruct(pl->g, nbox, X, u_b, u_i, st));
 }
 
-hps_status hps_leaf_interior_solve(hps_plan pl, int32_t nbox, const void* LU, const int32_t* perm,
-                                  const void* dinv, const double* b, const double* f, const double* u_b,
-                                  double* u_i, int32_t steps, void* ws, hipStream_t st) {
-  if (bad_plan(pl) || nbox < 0 || nbox > 65535 || steps < 0 || steps > 8) return HPS_EINVAL;
-  if (nbox == 0) return HPS_OK;
-  if (!LU || !perm || !dinv || !b || !u_b || !u_i || !ws) return HPS_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Bytes of scratch an interior solve of nbox boxes uses: r [nbox][n_i], then the
+// per-box maxima max|f - A_ib u_b|, max|r|, max|u|.
+size_t interior_scratch_bytes(const Geom& g, int nbox) { return 8 * (size_t)nbox * (g.n + 3); }
+
+hps_status interior_solve(hps_plan pl, int nbox, const void* LU, const int32_t* perm, const void* dinv,
+                          const double* b, const double* anorm, const double* f, const double* u_b, double* u_i,
+                          int steps, double* berr, double* scratch, hipStream_t st) {
   const Geom& g = pl->g;
-  double* r = static_cast<double*>(ws);
+  double* r = scratch;
+  double* r0max = r + (size_t)nbox * g.n;
+  double* rmax = r0max + nbox;
+  double* umax = rmax + nbox;
   const bool f32 = pl->desc.precision == HPS_FP32_IR;
   for (int s = 0; s <= steps; s++) {
     // r = f - A_ib u_b - A_ii u (u = 0 first), then u += (LU)^{-1} r
-    HPS_TRY(hps::launch_box_residual(g, nbox, b, f, u_b, s == 0 ? nullptr : u_i, r, st));
+    HPS_TRY(hps::launch_box_residual(g, nbox, b, f, u_b, s == 0 ? nullptr : u_i, r,
+                                     (s == 0 && berr) ? r0max : nullptr, nullptr, st));
     if (f32)
       HPS_TRY(hps::launch_getrs_vec<float>(g, nbox, static_cast<const float*>(LU), perm,
                                            static_cast<const float*>(dinv), r, u_i, s > 0, st));
@@ -405,7 +470,34 @@ hps_status hps_leaf_interior_solve(hps_plan pl, int32_t nbox, const void* LU, co
       HPS_TRY(hps::launch_getrs_vec<double>(g, nbox, static_cast<const double*>(LU), perm,
                                             static_cast<const double*>(dinv), r, u_i, s > 0, st));
   }
+  if (berr) {
+    HPS_TRY(hps::launch_box_residual(g, nbox, b, f, u_b, u_i, r, rmax, umax, st));
+    HPS_TRY(hps::launch_interior_berr(nbox, anorm, r0max, rmax, umax, berr, st));
+  }
   return HPS_OK;
+}
+
+hps_status interior_args(hps_plan pl, int nbox, const void* LU, const int32_t* perm, const void* dinv,
+                         const double* b, const double* anorm, const double* u_b, double* u_i, int steps,
+                         const double* berr) {
+  if (bad_plan(pl) || nbox < 0 || nbox > 65535 || steps < 0 || steps > 8) return HPS_EINVAL;
+  if (nbox > 0 && (!LU || !perm || !dinv || !b || !u_b || !u_i || (berr && !anorm))) return HPS_EINVAL;
+  return HPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hps_status hps_leaf_interior_solve(hps_plan pl, int32_t nbox, const void* LU, const int32_t* perm,
+                                  const void* dinv, const double* b, const double* anorm, const double* f,
+                                  const double* u_b, double* u_i, int32_t steps, double* berr, void* ws,
+                                  hipStream_t st) {
+  const hps_status a = interior_args(pl, nbox, LU, perm, dinv, b, anorm, u_b, u_i, steps, berr);
+  if (a != HPS_OK) return a;
+  if (nbox == 0) return HPS_OK;
+  if (!ws) return HPS_EINVAL;
+  return interior_solve(pl, nbox, LU, perm, dinv, b, anorm, f, u_b, u_i, steps, berr, static_cast<double*>(ws), st);
 }
 
 hps_status hps_leaf_flux(hps_plan pl, int32_t nbox, const double* u_i, const double* u_b, double* flux,
@@ -482,6 +574,7 @@ hps_status hps_plan_profile_read(hps_plan pl, hps_profile* out) {
     out->launches[f] = pl->prof.launches[f];
     out->ms[f] = pl->prof.ms[f];
     out->flops[f] = pl->prof.flops[f];
+    out->exec_flops[f] = pl->prof.exec[f];
   }
   return HPS_OK;
 }

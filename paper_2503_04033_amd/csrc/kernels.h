@@ -15,7 +15,7 @@ struct Profiler {
   struct Rec {
     int fam;
     int n;  // kernel launches between the two events
-    double flops;
+    double flops, exec;
     hipEvent_t a, b;
   };
   bool on = false;
@@ -24,6 +24,7 @@ struct Profiler {
   long long launches[kFamilies] = {};
   double ms[kFamilies] = {};
   double flops[kFamilies] = {};
+  double exec[kFamilies] = {};
 
   hipEvent_t get() {
     if (!pool.empty()) {
@@ -37,7 +38,7 @@ struct Profiler {
   }
   void reset() {
     flush();
-    for (int f = 0; f < kFamilies; f++) launches[f] = 0, ms[f] = 0.0, flops[f] = 0.0;
+    for (int f = 0; f < kFamilies; f++) launches[f] = 0, ms[f] = 0.0, flops[f] = 0.0, exec[f] = 0.0;
   }
   void flush() {
     for (auto& r : pending) {
@@ -46,6 +47,7 @@ struct Profiler {
         launches[r.fam] += r.n;
         ms[r.fam] += t;
         flops[r.fam] += r.flops;
+        exec[r.fam] += r.exec;
       }
       pool.push_back(r.a);
       pool.push_back(r.b);
@@ -59,16 +61,19 @@ struct Profiler {
 };
 
 // Brackets `launches` kernel launches of one family with events when profiling is on.
+// flops: algorithmic flops of the launches; exec: flops the kernels carry out (less where
+// structurally zero blocks are skipped; negative = same as flops).
 struct ProfScope {
   Profiler* p;
   hipStream_t st;
   Profiler::Rec r;
-  ProfScope(Profiler* prof, int fam, double flops, hipStream_t s, int launches = 1)
+  ProfScope(Profiler* prof, int fam, double flops, hipStream_t s, int launches = 1, double exec = -1.0)
       : p(prof && prof->on ? prof : nullptr), st(s) {
     if (!p) return;
     r.fam = fam;
     r.n = launches;
     r.flops = flops;
+    r.exec = exec < 0.0 ? flops : exec;
     r.a = p->get();
     r.b = p->get();
     (void)hipEventRecord(r.a, st);
@@ -84,6 +89,11 @@ struct ProfScope {
 template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
                      hipStream_t st, Profiler* prof);
+// Flops of one solve for the profiler (set by the caller when profiling is on): algorithmic
+// n_i^2 (n_b + 1) per active box and sweep, and what the kernels execute per sweep.
+struct SolveFlops {
+  double alg, fwd_exec, bwd_exec;
+};
 // xmode 1: X = Y, 2: X += Y, 3: X = Y0 + Y (FP64 X: the refinement's solution and
 // corrections), written by the backward block-row launches as they finish each tile.
 // bdirect: the rows of B are already in the factor's row order (else gathered via perm);
@@ -92,7 +102,7 @@ template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
                      const int* active, hipStream_t st, Profiler* prof, double* X = nullptr, int xmode = 0,
                      int sched = kTrsmRows, int waves = 4, const int* kstart = nullptr, int bdirect = 0,
-                     const T* Y0 = nullptr);
+                     const T* Y0 = nullptr, const SolveFlops* sf = nullptr);
 
 // leafops.hip
 hipError_t launch_nodes(const Geom& g, const double* t, const double* h, int nbox, const double* origin, double* xi,
@@ -125,7 +135,7 @@ hipError_t launch_fill_int(int* p, int value, size_t count, hipStream_t st);
 hipError_t launch_dtn(const Geom& g, int nbox, const double* X, const double* gdir, const int* slot_map,
                       double* T_vals, double* gload, double* part, hipStream_t st);
 size_t dtn_part_bytes(const Geom& g, int nbox);
-hipError_t launch_reduce(int npairs, const long long* pairs, long long block_elems, double* T_vals, hipStream_t st);
+hipError_t launch_reduce(int ntrip, const long long* trip, long long block_elems, double* T_vals, hipStream_t st);
 hipError_t launch_reconstruct(const Geom& g, int nbox, const double* X, const double* ub, double* ui,
                               hipStream_t st);
 hipError_t launch_adjoint_rhs(const Geom& g, int nbox, const double* w, const double* lam_b, double* rhs,
@@ -134,8 +144,11 @@ hipError_t launch_getrs_t(const Geom& g, int nbox, const double* LU, const int* 
                           const double* rhs, double* z, hipStream_t st);
 hipError_t launch_adjoint_yb(const Geom& g, int nbox, const double* z, double* yb, hipStream_t st);
 hipError_t launch_compact(const Geom& g, int nbox, const double* in, double* out, hipStream_t st);
+// r = f - A_ib u_b - A_ii u per box (u null: u = 0); rmax/umax optional per-box max|r|, max|u|
 hipError_t launch_box_residual(const Geom& g, int nbox, const double* b, const double* f, const double* ub,
-                               const double* u, double* r, hipStream_t st);
+                               const double* u, double* r, double* rmax, double* umax, hipStream_t st);
+hipError_t launch_interior_berr(int nbox, const double* anorm, const double* r0max, const double* rmax,
+                                const double* umax, double* berr, hipStream_t st);
 template <typename T>
 hipError_t launch_getrs_vec(const Geom& g, int nbox, const T* LU, const int* perm, const T* dinv, const double* r,
                             double* x, int accumulate, hipStream_t st);

@@ -945,23 +945,26 @@ size_t dtn_part_bytes(const Geom& g, int nbox) {
   return 8 * ncb * g.nb * (size_t)nbox;
 }
 
-// T_vals[dst] += T_vals[src] for each (dst, src) pair; every dst appears once.
-__global__ void reduce_kernel(int npairs, const long long* pairs, long long block_elems, double* T) {
+// T_vals[dst] = T_vals[lo] + T_vals[hi] for each (dst, lo, hi) triple: the shared
+// diagonal block of an internal face is the sum of its two boxes' contributions, each
+// kept in a slot of its own, so that running the reduction again gives the same bits.
+__global__ void reduce_kernel(int ntrip, const long long* trip, long long block_elems, double* T) {
   const int pr = blockIdx.y;
-  if (pr >= npairs) return;
-  const long long dst = pairs[2 * pr], src = pairs[2 * pr + 1];
+  if (pr >= ntrip) return;
+  const long long dst = trip[3 * pr], lo = trip[3 * pr + 1], hi = trip[3 * pr + 2];
   double* d = T + dst * block_elems;
-  const double* s = T + src * block_elems;
+  const double* a = T + lo * block_elems;
+  const double* b = T + hi * block_elems;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < block_elems;
        i += (long long)gridDim.x * blockDim.x)
-    d[i] = d[i] + s[i];
+    d[i] = a[i] + b[i];
 }
 
-hipError_t launch_reduce(int npairs, const long long* pairs, long long block_elems, double* T_vals, hipStream_t st) {
-  if (npairs == 0) return hipSuccess;
+hipError_t launch_reduce(int ntrip, const long long* trip, long long block_elems, double* T_vals, hipStream_t st) {
+  if (ntrip == 0) return hipSuccess;
   int gx = (int)((block_elems + 255) / 256);
   if (gx > 64) gx = 64;
-  hipLaunchKernelGGL(reduce_kernel, dim3(gx, npairs), dim3(256), 0, st, npairs, pairs, block_elems, T_vals);
+  hipLaunchKernelGGL(reduce_kernel, dim3(gx, ntrip), dim3(256), 0, st, ntrip, trip, block_elems, T_vals);
   return hipGetLastError();
 }
 
@@ -1090,15 +1093,32 @@ hipError_t launch_getrs_t(const Geom& g, int nbox, const double* LU, const int* 
 // r = f - A_ib u_b - A_ii u for one vector per box: with the face values u_b at the
 // two ends of every line, -(A_ii u + A_ib u_b) is s2x, s2y, s2z times D2 applied
 // along the full x-, y- and z-lines, plus kappa^2 b u.  One workgroup per box.
+__device__ inline double block_max_256(double v, double* red) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return m;
+}
+
+// rmax/umax (optional, [nbox]): max|r| and max|u| of the box; a NaN counts as +inf.
 __global__ __launch_bounds__(256) void box_residual_kernel(Geom g, int nbox, const double* b, const double* f,
-                                                           const double* ub_all, const double* u_all, double* r_all) {
+                                                           const double* ub_all, const double* u_all, double* r_all,
+                                                           double* rmax, double* umax) {
   extern __shared__ double us[];  // u [n], then D2 [p][p]
+  __shared__ double red[4];
   const int box = blockIdx.x;
   const int m = g.m, mm = m * m, n = g.n, p = g.p;
   double* d2 = us + n;
   const double* u = u_all ? u_all + (size_t)box * n : nullptr;
   const double* ub = ub_all + (size_t)box * g.nb;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) us[i] = u ? u[i] : 0.0;
+  double am = 0.0, au = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    us[i] = u ? u[i] : 0.0;
+    const double a = fabs(us[i]);
+    au = (a == a) ? fmax(au, a) : INFINITY;
+  }
   for (int i = threadIdx.x; i < p * p; i += blockDim.x) d2[i] = g.D2[i];
   __syncthreads();
   for (int node = threadIdx.x; node < n; node += blockDim.x) {
@@ -1113,9 +1133,36 @@ __global__ __launch_bounds__(256) void box_residual_kernel(Geom g, int nbox, con
       lz += d2[(kk + 1) * p + l + 1] * us[node + mm * (l - kk)];
     }
     const double fv = f ? f[(size_t)box * n + node] : 0.0;
-    r_all[(size_t)box * n + node] = fv + g.s2[0] * lx + g.s2[1] * ly + g.s2[2] * lz +
-                                    g.kappa2 * b[(size_t)box * n + node] * us[node];
+    const double r = fv + g.s2[0] * lx + g.s2[1] * ly + g.s2[2] * lz + g.kappa2 * b[(size_t)box * n + node] * us[node];
+    r_all[(size_t)box * n + node] = r;
+    const double a = fabs(r);
+    am = (a == a) ? fmax(am, a) : INFINITY;
   }
+  if (rmax) {
+    const double v = block_max_256(am, red);
+    if (threadIdx.x == 0) rmax[box] = v;
+  }
+  if (umax) {
+    const double v = block_max_256(au, red);
+    if (threadIdx.x == 0) umax[box] = v;
+  }
+}
+
+// berr = max|r| / (|A_ii|_inf max|u| + max|f - A_ib u_b|) per box (NaN -> +inf)
+__global__ void interior_berr_kernel(int nbox, const double* anorm, const double* r0max, const double* rmax,
+                                     const double* umax, double* berr) {
+  const int box = blockIdx.x * blockDim.x + threadIdx.x;
+  if (box >= nbox) return;
+  const double den = anorm[box] * umax[box] + r0max[box];
+  double e = den > 0.0 ? rmax[box] / den : (rmax[box] > 0.0 ? INFINITY : 0.0);
+  berr[box] = (e == e) ? e : INFINITY;
+}
+
+hipError_t launch_interior_berr(int nbox, const double* anorm, const double* r0max, const double* rmax,
+                                const double* umax, double* berr, hipStream_t st) {
+  hipLaunchKernelGGL(interior_berr_kernel, dim3((nbox + 255) / 256), dim3(256), 0, st, nbox, anorm, r0max, rmax,
+                     umax, berr);
+  return hipGetLastError();
 }
 
 // x = (P^T L U)^{-1} r for one vector per box with the stored factors: positions hold
@@ -1176,9 +1223,9 @@ __global__ __launch_bounds__(256) void getrs_vec_kernel(Geom g, int nbox, const 
 }
 
 hipError_t launch_box_residual(const Geom& g, int nbox, const double* b, const double* f, const double* ub,
-                               const double* u, double* r, hipStream_t st) {
+                               const double* u, double* r, double* rmax, double* umax, hipStream_t st) {
   const size_t shm = sizeof(double) * ((size_t)g.n + (size_t)g.p * g.p);
-  hipLaunchKernelGGL(box_residual_kernel, dim3(nbox), dim3(256), shm, st, g, nbox, b, f, ub, u, r);
+  hipLaunchKernelGGL(box_residual_kernel, dim3(nbox), dim3(256), shm, st, g, nbox, b, f, ub, u, r, rmax, umax);
   return hipGetLastError();
 }
 

@@ -830,24 +830,22 @@ static hipError_t dispatch_sweep(const Geom& g, const T* F, const int* perm, con
 // sched: kTrsmRows (one launch per block row) or kTrsmSweep (one launch per sweep);
 // waves: FP32 occupancy target (see dispatch_sweep).  kstart (may be null): per (box,
 // 64-column tile), a multiple of 64 above which every row of P B is zero (the forward
-// sweep skips those rows; the flops recorded stay the dense count).
+// sweep skips those rows).  sf: the flops the profiler records (see SolveFlops).
 template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
                      const int* active, hipStream_t st, Profiler* prof, double* X, int xmode, int sched, int waves,
-                     const int* kstart, int bdirect, const T* Y0) {
-  const double N = g.n_pad, nrhs = g.nb + 1;
-  // per sweep: sum over block rows of 2 w K + w^2 = N^2 per right-hand side
-  const double flops = N * N * nrhs * nbox;
+                     const int* kstart, int bdirect, const T* Y0, const SolveFlops* sf) {
   const int nlaunch = sched == kTrsmSweep ? 1 : (g.n_pad + kPanel - 1) / kPanel;
+  const double alg = sf ? sf->alg : 0.0;
   hipError_t e;
   {
-    ProfScope ps(prof, Profiler::kSolveFwd, flops, st, nlaunch);
+    ProfScope ps(prof, Profiler::kSolveFwd, alg, st, nlaunch, sf ? sf->fwd_exec : 0.0);
     e = dispatch_sweep<T, false>(g, F, perm, dinv, B, Y, nbox, active, st, nullptr, 0, sched, waves, kstart, bdirect,
                                  nullptr);
   }
   if (e != hipSuccess) return e;
   {
-    ProfScope ps(prof, Profiler::kSolveBwd, flops, st, nlaunch);
+    ProfScope ps(prof, Profiler::kSolveBwd, alg, st, nlaunch, sf ? sf->bwd_exec : 0.0);
     e = dispatch_sweep<T, true>(g, F, perm, dinv, Y, Y, nbox, active, st, xmode ? X : nullptr, xmode, sched, waves,
                                 nullptr, 0, Y0);
   }
@@ -859,10 +857,11 @@ template hipError_t getrf_run<double>(const Geom&, const std::vector<int>&, doub
                                       hipStream_t, Profiler*);
 template hipError_t getrs_run<float>(const Geom&, const float*,
                                      const int*, const float*, const float*, float*, int, const int*, hipStream_t,
-                                     Profiler*, double*, int, int, int, const int*, int, const float*);
+                                     Profiler*, double*, int, int, int, const int*, int, const float*,
+                                     const SolveFlops*);
 template hipError_t getrs_run<double>(const Geom&, const double*,
                                       const int*, const double*, const double*, double*, int, const int*,
                                       hipStream_t, Profiler*, double*, int, int, int, const int*, int,
-                                      const double*);
+                                      const double*, const SolveFlops*);
 
 }  // namespace hps

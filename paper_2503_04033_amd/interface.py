@@ -9,9 +9,10 @@ box numbering (lower axis fastest), identical on both sides of the face.
 T is kept in block-sparse row (BSR) form with m^2 x m^2 blocks.  Block row F has
 one block per distinct internal face of the two boxes that share F (at most
 11, paper Fig. sparsity5 / Sec. 3.3).  The diagonal block gets a contribution
-from each of the two boxes: the lower box writes the BSR slot, the upper box
-writes an extra slot that hps_interface_reduce adds in afterwards (fixed order,
-no atomics).  This module only builds index arrays and calls the sparse LU;
+from each of the two boxes: each writes an extra slot of its own (the lower box
+nslot + nface + F, the upper box nslot + F) and hps_interface_reduce sets the BSR
+slot to lower + upper (fixed order, no atomics; it can run again after any box
+was recomputed).  This module only builds index arrays and calls the sparse LU;
 the factorization of T is p-independent and is not part of the GPU hot path.
 """
 from __future__ import annotations
@@ -32,8 +33,8 @@ class InterfaceLayout:
     box_faces: np.ndarray       # [nbox, 6] internal face id or -1
     slot_map: np.ndarray        # [nbox, 36] int32 BSR slot per (row face, col face) of the box
     nslot: int                  # BSR blocks (unique)
-    nslot_total: int            # plus the extra diagonal slots
-    reduce_pairs: np.ndarray    # [nface, 2] int64 (dst, src)
+    nslot_total: int            # plus the two extra diagonal slots per face
+    reduce_triples: np.ndarray  # [nface, 3] int64 (dst, lower box slot, upper box slot)
     indptr: np.ndarray
     indices: np.ndarray
 
@@ -85,14 +86,16 @@ def build_layout(nboxes, m: int) -> InterfaceLayout:
             Fa, Fb = box_faces[:, a], box_faces[:, b]
             ok = (Fa >= 0) & (Fb >= 0)
             s = np.searchsorted(key, Fa[ok] * max(nface, 1) + Fb[ok])
-            if a == b and a % 2 == 0:
-                # this box is the upper neighbour of face Fa: extra slot
-                s = nslot + Fa[ok]
+            if a == b:
+                # the shared diagonal block: the upper neighbour of face Fa (a on the - side)
+                # and the lower one (+ side) each write an extra slot of their own
+                s = nslot + Fa[ok] if a % 2 == 0 else nslot + nface + Fa[ok]
             slot_map[ok, 6 * a + b] = s
     diag_slots = np.searchsorted(key, np.arange(nface) * max(nface, 1) + np.arange(nface))
-    pairs = np.stack([diag_slots, nslot + np.arange(nface)], axis=1).astype(np.int64)
+    triples = np.stack([diag_slots, nslot + nface + np.arange(nface), nslot + np.arange(nface)],
+                       axis=1).astype(np.int64)
     return InterfaceLayout(nboxes=(n1, n2, n3), m=m, nface=nface, box_faces=box_faces, slot_map=slot_map,
-                           nslot=nslot, nslot_total=nslot + nface, reduce_pairs=pairs, indptr=indptr,
+                           nslot=nslot, nslot_total=nslot + 2 * nface, reduce_triples=triples, indptr=indptr,
                            indices=c_u.astype(np.int64))
 
 

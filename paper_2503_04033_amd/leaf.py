@@ -100,7 +100,8 @@ class LeafPlan:
     def profile_read(self) -> dict:
         pr = _lib.Profile()
         check(self.lib.hps_plan_profile_read(self.handle, C.byref(pr)), "hps_plan_profile_read")
-        return {name: {"launches": int(pr.launches[k]), "ms": float(pr.ms[k]), "flops": float(pr.flops[k])}
+        return {name: {"launches": int(pr.launches[k]), "ms": float(pr.ms[k]), "flops": float(pr.flops[k]),
+                       "exec_flops": float(pr.exec_flops[k])}
                 for k, name in enumerate(_lib.PROFILE_FAMILIES)}
 
     # ---- allocation helpers -------------------------------------------------
@@ -164,15 +165,21 @@ class LeafPlan:
                                             _ptr(u_i, torch.float64, nbox * i.n_i, "u_i"), _stream()),
               "hps_leaf_reconstruct")
 
-    def hps_leaf_interior_solve(self, nbox: int, LU, perm, dinv, b, f, u_b, u_i, steps: int, ws):
+    def _interior_args(self, nbox, LU, perm, dinv, b, anorm, f, u_b, u_i, berr):
+        i = self.info
+        return (self.handle, nbox, _ptr(LU, self.elem, nbox * i.n_pad * i.n_pad, "LU"),
+                _ptr(perm, torch.int32, nbox * i.n_pad, "perm"),
+                _ptr(dinv, self.elem, nbox * i.dinv_bytes // i.elem_bytes, "dinv"),
+                _ptr(b, torch.float64, nbox * i.n_i, "b"), _ptr(anorm, torch.float64, nbox, "anorm"),
+                _ptr(f, torch.float64, nbox * i.n_i, "f"), _ptr(u_b, torch.float64, nbox * i.n_b, "u_b"),
+                _ptr(u_i, torch.float64, nbox * i.n_i, "u_i"))
+
+    def hps_leaf_interior_solve(self, nbox: int, LU, perm, dinv, b, anorm, f, u_b, u_i, steps: int, berr, ws):
         i = self.info
         check(self.lib.hps_leaf_interior_solve(
-            self.handle, nbox, _ptr(LU, self.elem, nbox * i.n_pad * i.n_pad, "LU"),
-            _ptr(perm, torch.int32, nbox * i.n_pad, "perm"),
-            _ptr(dinv, self.elem, nbox * i.dinv_bytes // i.elem_bytes, "dinv"),
-            _ptr(b, torch.float64, nbox * i.n_i, "b"), _ptr(f, torch.float64, nbox * i.n_i, "f"),
-            _ptr(u_b, torch.float64, nbox * i.n_b, "u_b"), _ptr(u_i, torch.float64, nbox * i.n_i, "u_i"),
-            int(steps), _ptr(ws, torch.uint8, nbox * i.ws_bytes, "ws"), _stream()), "hps_leaf_interior_solve")
+            *self._interior_args(nbox, LU, perm, dinv, b, anorm, f, u_b, u_i, berr), int(steps),
+            _ptr(berr, torch.float64, nbox, "berr"), _ptr(ws, torch.uint8, nbox * i.ws_bytes, "ws"), _stream()),
+            "hps_leaf_interior_solve")
 
     def hps_leaf_flux(self, nbox: int, u_i, u_b, flux):
         i = self.info
@@ -199,8 +206,9 @@ class LeafPlan:
               "hps_leaf_adjoint_grad")
 
 
-def hps_interface_reduce(pairs: torch.Tensor, block_elems: int, T_vals: torch.Tensor):
+def hps_interface_reduce(triples: torch.Tensor, block_elems: int, T_vals: torch.Tensor):
+    """T_vals[dst] = T_vals[lo] + T_vals[hi] for the (dst, lo, hi) rows of triples [n, 3] int64."""
     lib = _lib.load()
-    n = pairs.shape[0] if pairs is not None else 0
-    check(lib.hps_interface_reduce(n, _ptr(pairs, torch.int64, 2 * n, "pairs"), int(block_elems),
+    n = triples.shape[0] if triples is not None else 0
+    check(lib.hps_interface_reduce(n, _ptr(triples, torch.int64, 3 * n, "triples"), int(block_elems),
                                    _ptr(T_vals, torch.float64, 1, "T_vals"), _stream()), "hps_interface_reduce")

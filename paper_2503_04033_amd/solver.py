@@ -5,10 +5,18 @@ Per chunk of boxes the GPU runs: hps_leaf_operators (a1) -> hps_leaf_factor (a2)
 interface matrix).  The host then reduces the duplicate diagonal blocks on the
 GPU (hps_interface_reduce), copies T and the loads, and factors the sparse
 interface matrix (p-independent, off the hot path).  The solve stage sums
-loads, solves for the interface values and reconstructs the interiors on the
-GPU (hps_leaf_reconstruct, a5).  X (the interior solution operator and load
-response) is kept in HBM per box when `keep_X` is set; otherwise the chunk is
-recomputed in the solve stage, as the paper does for large problems.
+loads, solves for the interface values and fills in the interiors on the GPU.
+
+What stays in HBM between the two stages is decided by an HBM budget (default:
+90 % of the free device memory when the solver is made).  Without the outer
+refinement (refine = 0) the interiors are one GEMV per box with X
+(hps_leaf_reconstruct), so X is the per-box data worth keeping; with it the
+interiors come from the box factors (hps_leaf_interior_solve), so the factors
+are.  `keep` = None keeps them when they fit next to the interface matrix and
+one chunk of working buffers, True insists (error if they do not fit), False
+never keeps them: every chunk's operators and factors are then computed again
+in the solve stage, as the paper does for problems whose local operators do not
+fit in memory (Sec. 3.2).
 
 Outer refinement of the solve stage (`refine` rounds; default 1 for FP32_IR,
 0 for FP64): the interface system amplifies the rounding left in the DtN maps
@@ -19,10 +27,13 @@ residual of T_FF u_F = rhs (hps_leaf_flux), and corrects u_F with the existing
 interface factorization; each round shrinks the error by that amplification times
 the maps' relative error.  The final interiors come from the factors as well.
 
-FP32_IR plans: a box whose refinement ends above ir_tol (ir_iters < 0) is
-factored and solved again with an FP64 plan before the interface matrix is
-reduced; its ir_iters stays negative and its id is listed in
-BuildResult.extra["fp64_fallback"].
+Boxes whose FP32 factors are not good enough.  In the build, a box whose
+refinement ends above ir_tol (ir_iters < 0) is factored and solved again with an
+FP64 plan before the interface matrix is reduced; its ir_iters stays negative and
+its id is listed in BuildResult.extra["fp64_fallback"].  In the solve stage those
+boxes, and any box whose interior solve ends with a backward error above
+`interior_tol`, get their interiors from FP64 factors; a box still above
+`interior_tol` then raises RuntimeError.
 """
 from __future__ import annotations
 
@@ -44,6 +55,44 @@ def _box_origins(nboxes, lo, h) -> np.ndarray:
     return np.stack([lo[0] + bx * h[0], lo[1] + by * h[1], lo[2] + bz * h[2]], axis=1).astype(np.float64)
 
 
+def chunk_bytes_per_box(info) -> int:
+    """Working buffers of one box in a chunk: A/LU, perm, dinv, X, workspace, scalars."""
+    return info.a_bytes + info.perm_bytes + info.dinv_bytes + info.x_bytes + info.ws_bytes + 64
+
+
+def factor_bytes_per_box(info) -> int:
+    return info.a_bytes + info.perm_bytes + info.dinv_bytes + 8
+
+
+def fp64_redo(plan64: LeafPlan, ids: list, b, f, g_dir, slot_map, T_vals, g_loads, berr, chunk: int, device,
+              keep_x: Optional[Callable] = None) -> None:
+    """Boxes `ids` (an FP32_IR run left them above ir_tol) factored and solved again with
+    the FP64 plan plan64: their DtN blocks are written into their slots of T_vals (the
+    shared diagonal blocks need hps_interface_reduce afterwards), their loads and backward
+    errors into g_loads and berr; keep_x(idx, X_rows) receives their X if given."""
+    i = plan64.info
+    xs = i.n_pad * i.ldx
+    C = min(chunk, len(ids))
+    bufs = plan64.alloc(C, device)
+    for k0 in range(0, len(ids), C):
+        part = ids[k0:k0 + C]
+        nb = len(part)
+        idx = torch.tensor(part, dtype=torch.long, device=device)
+        bb = b[idx].contiguous()
+        ff = f[idx].contiguous() if f is not None else None
+        gl = torch.empty(nb, i.n_b, dtype=torch.float64, device=device)
+        plan64.hps_leaf_operators(nb, bb, bufs["A"], bufs["anorm"])
+        plan64.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], bufs["info"])
+        plan64.hps_leaf_dtn(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
+                            g_dir[idx].contiguous(), slot_map[idx].contiguous(), T_vals, gl, bufs["X"],
+                            bufs["ir_iters"], bufs["berr"], bufs["ws"])
+        g_loads[idx] = gl
+        if berr is not None:
+            berr[idx] = bufs["berr"][:nb]
+        if keep_x is not None:
+            keep_x(idx, bufs["X"][:nb * xs].view(nb, xs))
+
+
 @dataclass
 class BuildResult:
     T_vals: torch.Tensor            # BSR blocks (+ extra diagonal slots), device
@@ -51,6 +100,7 @@ class BuildResult:
     info: torch.Tensor              # [nbox] LU info
     ir_iters: torch.Tensor
     berr: torch.Tensor
+    anorm: torch.Tensor             # [nbox] |A_ii|_inf
     X: Optional[torch.Tensor] = None  # [nbox * n_pad * ldx] when kept
     factors: Optional[dict] = None    # LU, perm, dinv of every box when kept
     extra: dict = field(default_factory=dict)
@@ -59,9 +109,12 @@ class BuildResult:
 class TwoLevelSolver:
     """Solve -Lap u - kappa^2 b u = f on a box grid with Dirichlet data g."""
 
+    MAX_CHUNK = 1024
+
     def __init__(self, nboxes, lo, hi, p: int, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
-                 ir_tol: float = 1e-12, chunk: Optional[int] = None, keep_X: bool = True, device="cuda",
-                 refine: Optional[int] = None, refine_steps: int = 2, tuning: Optional[dict] = None):
+                 ir_tol: float = 1e-12, chunk: Optional[int] = None, keep: Optional[bool] = None, device="cuda",
+                 refine: Optional[int] = None, refine_steps: int = 2, tuning: Optional[dict] = None,
+                 hbm_budget: Optional[float] = None, interior_tol: float = 1e-12):
         self.nboxes = tuple(int(v) for v in nboxes)
         self.nbox = int(np.prod(self.nboxes))
         self.lo = tuple(float(v) for v in lo)
@@ -74,13 +127,12 @@ class TwoLevelSolver:
             self.plan.hps_plan_set_tuning(k, v)
         self.info = self.plan.info
         self.layout = itf.build_layout(self.nboxes, self.info.m)
-        self.chunk = int(chunk) if chunk else self.nbox
-        self.keep_X = keep_X
         self.refine = (1 if precision == "fp32_ir" else 0) if refine is None else int(refine)
         self.refine_steps = int(refine_steps)
-        self.keep_factors = keep_X and self.refine > 0
+        self.interior_tol = float(interior_tol)
         self.precision = precision
         self._plan64 = None
+        self._plan_memory(chunk, keep, hbm_budget)
         self.origins = torch.tensor(_box_origins(self.nboxes, self.lo, self.h), device=self.device)
         self.slot_map = torch.tensor(self.layout.slot_map, device=self.device)
         self.bmask = itf.boundary_mask(self.layout)
@@ -88,6 +140,41 @@ class TwoLevelSolver:
     @classmethod
     def for_problem(cls, prob, **kw) -> "TwoLevelSolver":
         return cls(prob.nboxes, prob.lo, prob.hi, prob.p, prob.kappa, **kw)
+
+    # ---- memory plan ------------------------------------------------------------
+    def _plan_memory(self, chunk, keep, hbm_budget):
+        """Chunk size and what the solve stage finds resident, within hbm_budget bytes."""
+        i = self.info
+        if hbm_budget is None:
+            free = torch.cuda.mem_get_info(self.device)[0] if self.device.type == "cuda" else 0
+            hbm_budget = 0.9 * free
+        self.hbm_budget = float(hbm_budget)
+        mm = i.m * i.m
+        # interface matrix, loads and per-box scalars, and the host-facing copies made on the device
+        resident = 8 * (self.layout.nslot_total * mm * mm + 1) + 8 * self.nbox * (3 * i.n_b + 4)
+        per_box_keep = factor_bytes_per_box(i) if self.refine > 0 else i.x_bytes
+        keep_total = per_box_keep * self.nbox
+        per_chunk_box = chunk_bytes_per_box(i)
+        fits_keep = resident + keep_total + per_chunk_box <= self.hbm_budget
+        if keep is None:
+            keep = fits_keep
+        elif keep and not fits_keep:
+            raise ValueError(f"keeping the per-box data needs {(resident + keep_total) / 1e9:.1f} GB plus a "
+                             f"chunk; the HBM budget is {self.hbm_budget / 1e9:.1f} GB")
+        self.keep = bool(keep)
+        avail = self.hbm_budget - resident - (keep_total if self.keep else 0)
+        fit = int(avail // per_chunk_box)
+        if fit < 1:
+            raise ValueError(f"one box of working buffers ({per_chunk_box / 1e6:.1f} MB) does not fit the HBM "
+                             f"budget of {self.hbm_budget / 1e9:.2f} GB next to the interface matrix")
+        if chunk:
+            if int(chunk) > fit:
+                raise ValueError(f"chunk {chunk} exceeds the {fit} boxes that fit the HBM budget")
+            self.chunk = int(chunk)
+        else:
+            self.chunk = min(self.nbox, fit, self.MAX_CHUNK)
+        self.keep_X = self.keep and self.refine == 0
+        self.keep_factors = self.keep and self.refine > 0
 
     # ---- problem data at the collocation nodes --------------------------------
     def nodes(self):
@@ -117,6 +204,7 @@ class TwoLevelSolver:
         info = torch.empty(nbox, dtype=torch.int32, device=self.device)
         iters = torch.empty(nbox, dtype=torch.int32, device=self.device)
         berr = torch.empty(nbox, dtype=torch.float64, device=self.device)
+        anorm = torch.empty(nbox, dtype=torch.float64, device=self.device)
         X_all = torch.empty(nbox * i.n_pad * i.ldx, dtype=torch.float64, device=self.device) if self.keep_X else None
         C = min(self.chunk, nbox)
         bufs = plan.alloc(C, self.device)
@@ -138,19 +226,20 @@ class TwoLevelSolver:
                 A = factors["LU"][c0 * a_el:(c0 + nb) * a_el]
                 perm = factors["perm"][c0 * i.n_pad:(c0 + nb) * i.n_pad]
                 dinv = factors["dinv"][c0 * d_el:(c0 + nb) * d_el]
-            plan.hps_leaf_operators(nb, bb, A, bufs["anorm"])
+            plan.hps_leaf_operators(nb, bb, A, anorm[sl])
             plan.hps_leaf_factor(nb, A, perm, dinv, info[sl])
-            plan.hps_leaf_dtn(nb, A, perm, dinv, bb, bufs["anorm"], ff,
+            plan.hps_leaf_dtn(nb, A, perm, dinv, bb, anorm[sl], ff,
                               g_dir[sl].contiguous(), self.slot_map[sl].contiguous(), T_vals, g_loads[sl], X,
                               iters[sl], berr[sl], bufs["ws"])
+        del bufs
         redo = self._unconverged(iters)
         if redo:
             self._redo_fp64(redo, b, f, g_dir, T_vals, g_loads, berr, X_all)
-        pairs = torch.tensor(self.layout.reduce_pairs, device=self.device)
-        if pairs.shape[0]:
-            hps_interface_reduce(pairs, mm * mm, T_vals)
-        return BuildResult(T_vals=T_vals, g_loads=g_loads, info=info, ir_iters=iters, berr=berr, X=X_all,
-                           factors=factors, extra={"fp64_fallback": redo})
+        triples = torch.tensor(self.layout.reduce_triples, device=self.device)
+        if triples.shape[0]:
+            hps_interface_reduce(triples, mm * mm, T_vals)
+        return BuildResult(T_vals=T_vals, g_loads=g_loads, info=info, ir_iters=iters, berr=berr, anorm=anorm,
+                           X=X_all, factors=factors, extra={"fp64_fallback": redo})
 
     # ---- boxes whose FP64 refinement did not converge ----------------------------
     def _unconverged(self, iters: torch.Tensor, offset: int = 0) -> list:
@@ -158,35 +247,25 @@ class TwoLevelSolver:
             return []
         return [offset + int(t) for t in torch.nonzero(iters < 0).flatten().cpu().tolist()]
 
+    def _fp64_plan(self) -> LeafPlan:
+        if self._plan64 is None:
+            self._plan64 = LeafPlan(self.p, self.h, self.kappa, "fp64")
+        return self._plan64
+
     def _redo_fp64(self, ids: list, b, f, g_dir, T_vals, g_loads, berr, X_all=None, X_chunk=None, c0: int = 0):
         """Factor and solve boxes `ids` again in FP64, overwriting their T blocks, loads,
         backward errors and X (in X_all, or in X_chunk whose first box is c0)."""
-        if self._plan64 is None:
-            self._plan64 = LeafPlan(self.p, self.h, self.kappa, "fp64")
-        plan, i = self._plan64, self.info
+        i = self.info
         xs = i.n_pad * i.ldx
-        C = min(self.chunk, len(ids))
-        bufs = plan.alloc(C, self.device)
-        for k0 in range(0, len(ids), C):
-            part = ids[k0:k0 + C]
-            nb = len(part)
-            idx = torch.tensor(part, dtype=torch.long, device=self.device)
-            bb = b[idx].contiguous()
-            ff = f[idx].contiguous() if f is not None else None
-            gl = torch.empty(nb, i.n_b, dtype=torch.float64, device=self.device)
-            plan.hps_leaf_operators(nb, bb, bufs["A"], bufs["anorm"])
-            plan.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], bufs["info"])
-            plan.hps_leaf_dtn(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
-                              g_dir[idx].contiguous(), self.slot_map[idx].contiguous(), T_vals, gl, bufs["X"],
-                              bufs["ir_iters"], bufs["berr"], bufs["ws"])
-            g_loads[idx] = gl
-            if berr is not None:
-                berr[idx] = bufs["berr"][:nb]
-            Xn = bufs["X"][:nb * xs].view(nb, xs)
+
+        def keep_x(idx, Xn):
             if X_all is not None:
                 X_all.view(self.nbox, xs)[idx] = Xn
             elif X_chunk is not None:
                 X_chunk.view(-1, xs)[idx - c0] = Xn
+
+        fp64_redo(self._fp64_plan(), ids, b, f, g_dir, self.slot_map, T_vals, g_loads, berr, self.chunk,
+                  self.device, keep_x)
 
     # ---- solve stage (Alg. 2) ---------------------------------------------------
     def solve(self, br: BuildResult, g_dir: torch.Tensor, isolver: Optional[itf.InterfaceSolver] = None,
@@ -194,9 +273,8 @@ class TwoLevelSolver:
         """Return (u_face, u_b [nbox, n_b], u_i [nbox, n_i], interface solver).
 
         With X kept from the build the interiors are one GEMV per box.  Otherwise
-        (keep_X=False) every chunk's operators, factors and X are recomputed here,
-        as the paper does for problems whose local operators do not fit in
-        memory (Sec. 3.2); b and f must then be passed again.
+        the interiors come from the box factors (kept, or computed again per chunk),
+        which needs b and f again.
         """
         if isolver is None:
             isolver = itf.InterfaceSolver(self.layout, br.T_vals.cpu().numpy())
@@ -218,44 +296,26 @@ class TwoLevelSolver:
                 ub_d = torch.tensor(ub, device=self.device)
             ui, _ = self._interiors(br, ub_d, b, f, want_flux=False)
             return u_face, ub, ui, isolver
-        ui = torch.empty(self.nbox, self.info.n_i, dtype=torch.float64, device=self.device)
         if br.X is not None:
+            ui = torch.empty(self.nbox, self.info.n_i, dtype=torch.float64, device=self.device)
             self.plan.hps_leaf_reconstruct(self.nbox, br.X, ub_d, ui)
             return u_face, ub, ui, isolver
         if b is None:
             raise ValueError("recompute mode needs b (and f) again")
-        i, plan, nbox = self.info, self.plan, self.nbox
-        mm = i.m * i.m
-        C = min(self.chunk, nbox)
-        bufs = plan.alloc(C, self.device)
-        scratch_T = torch.zeros(self.layout.nslot_total * mm * mm + 1, dtype=torch.float64, device=self.device)
-        scratch_g = torch.empty(C, i.n_b, dtype=torch.float64, device=self.device)
-        for c0 in range(0, nbox, C):
-            nb = min(C, nbox - c0)
-            sl = slice(c0, c0 + nb)
-            bb = b[sl].contiguous()
-            ff = f[sl].contiguous() if f is not None else None
-            plan.hps_leaf_operators(nb, bb, bufs["A"], bufs["anorm"])
-            plan.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], bufs["info"])
-            plan.hps_leaf_dtn(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
-                              g_dir[sl].contiguous(), self.slot_map[sl].contiguous(), scratch_T, scratch_g[:nb],
-                              bufs["X"], bufs["ir_iters"], bufs["berr"], bufs["ws"])
-            redo = self._unconverged(bufs["ir_iters"][:nb], c0)
-            if redo:
-                self._redo_fp64(redo, b, f, g_dir, scratch_T, torch.empty(self.nbox, i.n_b, dtype=torch.float64,
-                                device=self.device), None, X_chunk=bufs["X"], c0=c0)
-            plan.hps_leaf_reconstruct(nb, bufs["X"], ub_d[sl].contiguous(), ui[sl])
+        ui, _ = self._interiors(br, ub_d, b, f, want_flux=False)
         return u_face, ub, ui, isolver
 
     def _interiors(self, br: BuildResult, ub_d: torch.Tensor, b, f, want_flux: bool):
         """u_i = A_ii^{-1} (f_i - A_ib u_b) of every box from its factors, refined in FP64
         (hps_leaf_interior_solve), and optionally the outward face fluxes (hps_leaf_flux).
-        Factors come from the build when kept, else each chunk is factored again."""
+        Factors come from the build when kept, else each chunk is factored again.  Boxes of
+        the build's FP64 fallback, and boxes whose interior backward error ends above
+        interior_tol, are solved again with FP64 factors."""
         i, plan, nbox = self.info, self.plan, self.nbox
         ui = torch.empty(nbox, i.n_i, dtype=torch.float64, device=self.device)
-        flux = torch.empty(nbox, i.n_b, dtype=torch.float64, device=self.device) if want_flux else None
+        berr = torch.empty(nbox, dtype=torch.float64, device=self.device)
         C = min(self.chunk, nbox)
-        bufs = plan.alloc(C, self.device)
+        bufs = plan.alloc(C, self.device) if br.factors is None else None
         a_el, d_el = i.a_bytes // i.elem_bytes, i.dinv_bytes // i.elem_bytes
         for c0 in range(0, nbox, C):
             nb = min(C, nbox - c0)
@@ -266,15 +326,55 @@ class TwoLevelSolver:
                 A = br.factors["LU"][c0 * a_el:(c0 + nb) * a_el]
                 perm = br.factors["perm"][c0 * i.n_pad:(c0 + nb) * i.n_pad]
                 dinv = br.factors["dinv"][c0 * d_el:(c0 + nb) * d_el]
+                ws = self._interior_ws(nb)
             else:
-                A, perm, dinv = bufs["A"], bufs["perm"], bufs["dinv"]
+                A, perm, dinv, ws = bufs["A"], bufs["perm"], bufs["dinv"], bufs["ws"]
                 plan.hps_leaf_operators(nb, bb, A, bufs["anorm"])
                 plan.hps_leaf_factor(nb, A, perm, dinv, bufs["info"])
-            ubs = ub_d[sl].contiguous()
-            plan.hps_leaf_interior_solve(nb, A, perm, dinv, bb, ff, ubs, ui[sl], self.refine_steps, bufs["ws"])
-            if want_flux:
-                plan.hps_leaf_flux(nb, ui[sl], ubs, flux[sl])
+            plan.hps_leaf_interior_solve(nb, A, perm, dinv, bb, br.anorm[sl], ff, ub_d[sl].contiguous(), ui[sl],
+                                         self.refine_steps, berr[sl], ws)
+        del bufs
+        redo = set(br.extra.get("fp64_fallback", []))
+        if self.precision == "fp32_ir":
+            redo |= set(torch.nonzero(~(berr <= self.interior_tol)).flatten().cpu().tolist())
+        redo = sorted(redo)
+        if redo:
+            self._interiors_fp64(redo, ub_d, b, f, ui, berr)
+        worst = float(berr.max()) if nbox else 0.0
+        if not worst <= self.interior_tol:
+            bad = torch.nonzero(~(berr <= self.interior_tol)).flatten().cpu().tolist()
+            raise RuntimeError(f"interior solves of boxes {bad[:16]} end with backward error up to {worst:.2e} "
+                               f"(> {self.interior_tol:.1e}) even with FP64 factors")
+        br.extra["interior_berr_max"] = worst
+        br.extra["interior_fp64"] = redo
+        flux = None
+        if want_flux:
+            flux = torch.empty(nbox, i.n_b, dtype=torch.float64, device=self.device)
+            plan.hps_leaf_flux(nbox, ui, ub_d, flux)
         return ui, flux
+
+    def _interior_ws(self, nb: int) -> torch.Tensor:
+        """Workspace of an interior solve of nb boxes (one vector and three scalars per box)."""
+        return torch.empty(8 * nb * (self.info.n_i + 3), dtype=torch.uint8, device=self.device)
+
+    def _interiors_fp64(self, ids: list, ub_d, b, f, ui, berr):
+        """Interiors of boxes `ids` from FP64 factors (written into ui and berr)."""
+        plan, i = self._fp64_plan(), self.info
+        C = min(self.chunk, len(ids))
+        bufs = plan.alloc(C, self.device)
+        for k0 in range(0, len(ids), C):
+            idx = torch.tensor(ids[k0:k0 + C], dtype=torch.long, device=self.device)
+            nb = idx.numel()
+            bb = b[idx].contiguous()
+            ff = f[idx].contiguous() if f is not None else None
+            u = torch.empty(nb, i.n_i, dtype=torch.float64, device=self.device)
+            e = torch.empty(nb, dtype=torch.float64, device=self.device)
+            plan.hps_leaf_operators(nb, bb, bufs["A"], bufs["anorm"])
+            plan.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], bufs["info"])
+            plan.hps_leaf_interior_solve(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
+                                         ub_d[idx].contiguous(), u, self.refine_steps, e, bufs["ws"])
+            ui[idx] = u
+            berr[idx] = e
 
     def solve_problem(self, prob):
         bv, fv, gv, xi, xb = self.sample(prob.b, prob.f, prob.g)

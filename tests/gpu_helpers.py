@@ -49,8 +49,9 @@ def gpu_leaf_boxes(prob, box_ids, precision="fp64", ir_max_iter=3, ir_tol=1e-12,
                       bufs["X"], bufs["ir_iters"], bufs["berr"], bufs["ws"])
     torch.cuda.synchronize()
     X = bufs["X"].view(nb, i.n_pad, i.ldx)[:, :i.n_i, :i.nrhs].cpu().numpy()
-    T = T_vals.view(nb, 6, 6, mm, mm).permute(0, 1, 3, 2, 4).reshape(nb, i.n_b, i.n_b).cpu().numpy()
-    return {"X": X, "T": T, "g": g.cpu().numpy(), "info": bufs["info"].cpu().numpy(),
+    T6 = T_vals.view(nb, 6, 6, mm, mm).cpu().numpy()
+    T = T6.transpose(0, 1, 3, 2, 4).reshape(nb, i.n_b, i.n_b)
+    return {"X": X, "T": T, "T6": T6, "g": g.cpu().numpy(), "info": bufs["info"].cpu().numpy(),
             "iters": bufs["ir_iters"].cpu().numpy(), "berr": bufs["berr"].cpu().numpy(),
             "A0": A0.view(nb, i.n_pad, i.n_pad).cpu().numpy(),
             "LU": bufs["A"].view(nb, i.n_pad, i.n_pad).cpu().numpy(),

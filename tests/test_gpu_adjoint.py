@@ -31,10 +31,10 @@ def _setup(nboxes, p, kappa, nobs, seed=5):
     return inv, prob, data, s, bv, fv, gv, xi, torch.tensor(tl, device="cuda")
 
 
-def _gpu_grad(s, bv, fv, gv, tl, data):
+def _gpu_grad(s, bv, fv, gv, tl, data, opts=None):
     from paper_2503_04033_amd.adjoint import HPSSolve
     b = bv.clone().requires_grad_(True)
-    u = HPSSolve.apply(b, s, fv, gv)
+    u = HPSSolve.apply(b, s, fv, gv, opts)
     r = u[tl[:, 0], tl[:, 1]] - torch.tensor(data, device="cuda")
     J = 0.5 * (r * r).sum()
     J.backward()
@@ -55,7 +55,7 @@ def test_adjoint_gradient_matches_oracle(gpu, nboxes, p, kappa, nobs):
 
 
 def test_adjoint_central_differences(gpu):
-    from paper_2503_04033_amd.adjoint import ResidentForward
+    from paper_2503_04033_amd.adjoint import AdjointSolve
     inv, prob, data, s, bv, fv, gv, xi, tl = _setup((2, 2, 2), 8, 9.0, 60, seed=15)
     J, g = _gpu_grad(s, bv, fv, gv, tl, data)
     d = torch.tensor(data, device="cuda")
@@ -67,7 +67,7 @@ def test_adjoint_central_differences(gpu):
         h = 1e-6
         Js = []
         for sgn in (1.0, -1.0):
-            fwd = ResidentForward(s)
+            fwd = AdjointSolve(s)
             u, _ = fwd.forward(bv + sgn * h * vd, fv, gv)
             r = u[tl[:, 0], tl[:, 1]] - d
             Js.append(0.5 * float((r * r).sum()))
@@ -75,3 +75,25 @@ def test_adjoint_central_differences(gpu):
         an = float((g * v).sum())
         say(f"  direction {trial}: adjoint {an:.8e} central difference {fd:.8e}")
         assert an == pytest.approx(fd, rel=1e-5, abs=1e-9 * abs(J))
+
+
+def test_adjoint_chunked_recompute_matches_resident(gpu):
+    # factors recomputed per chunk in both backward passes (a budget that holds neither the
+    # factors of every box nor more than 3 boxes of working buffers) give bitwise the
+    # gradient of the resident path, and both match the oracle
+    from paper_2503_04033_amd.adjoint import AdjointSolve
+    from paper_2503_04033_amd.solver import chunk_bytes_per_box
+    inv, prob, data, s, bv, fv, gv, xi, tl = _setup((4, 2, 2), 8, 9.0, 80, seed=25)
+    J0, g0 = _gpu_grad(s, bv, fv, gv, tl, data, {"resident": True})
+    i = s.info
+    mm = i.m * i.m
+    small = 8 * (s.layout.nslot_total * mm * mm + 1) + 8 * s.nbox * (3 * i.n_i + 3 * i.n_b + 4) + \
+        3 * chunk_bytes_per_box(i) + 1
+    probe = AdjointSolve(s, hbm_budget=small)
+    assert not probe.resident and probe.chunk == 3
+    del probe
+    J1, g1 = _gpu_grad(s, bv, fv, gv, tl, data, {"hbm_budget": small})
+    say(f"  J resident {J0:.12e} chunked {J1:.12e}")
+    assert J0 == J1 and np.array_equal(g0, g1)
+    Jo, go, _ = oa.two_level_gradient(prob, inv.obs_nodes, data)
+    assert rel(g1, go) < 1e-9

@@ -175,7 +175,7 @@ def test_pipeline_recompute_chunked(gpu, precision, tol):
     from paper_2503_04033_amd.solver import TwoLevelSolver
     prob = W.multi_bump((3, 2, 2), 7, 8.0, 23, gaussian_source=True, name="recompute_p7")
     say(f"pipeline recompute {prob.name} {precision}")
-    s = TwoLevelSolver.for_problem(prob, precision=precision, chunk=5, keep_X=False)
+    s = TwoLevelSolver.for_problem(prob, precision=precision, chunk=5, keep=False)
     out = s.solve_problem(prob)
     torch.cuda.synchronize()
     ref = oi.solve(prob)
@@ -205,25 +205,96 @@ def test_pipeline_single_box(gpu):
     _pipeline(prob, "fp64", FP64_TOL)
 
 
-@pytest.mark.parametrize("keep_X", [True, False])
-def test_fp64_fallback_for_unconverged_boxes(gpu, keep_X):
+@pytest.mark.parametrize("keep", [True, False])
+def test_fp64_fallback_for_unconverged_boxes(gpu, keep):
     # no correction step and an unreachable tolerance: every box ends above ir_tol, is
     # flagged (ir_iters = -1) and is factored and solved again in FP64
     from paper_2503_04033_amd.solver import TwoLevelSolver
     prob = W.multi_bump((2, 2, 2), 8, 6.0, 31, gaussian_source=True, name="fallback_p8")
-    say(f"fallback {prob.name} keep_X={keep_X}")
-    s = TwoLevelSolver.for_problem(prob, precision="fp32_ir", ir_max_iter=0, ir_tol=1e-30, chunk=3,
-                                   keep_X=keep_X)
+    say(f"fallback {prob.name} keep={keep}")
+    s = TwoLevelSolver.for_problem(prob, precision="fp32_ir", ir_max_iter=0, ir_tol=1e-30, chunk=3, keep=keep)
     out = s.solve_problem(prob)
     torch.cuda.synchronize()
     br = out["build"]
     assert br.extra["fp64_fallback"] == list(range(prob.nbox))
+    assert br.extra["interior_fp64"] == list(range(prob.nbox))
     assert np.all(br.ir_iters.cpu().numpy() == -1)
     ref = oi.solve(prob)
     eu = rel(out["u_i"].cpu().numpy(), ref.u_i)
     ef = rel(out["u_face"], ref.u_face)
     say(f"  u_i err {eu:.2e}  u_face err {ef:.2e}")
     assert eu < FP64_TOL and ef < FP64_TOL
+
+
+def _near_resonant(p=8, delta=1e-7):
+    """2x2x2 boxes, b = 1 in box 0 and 1.2 elsewhere (b only enters at interior nodes, so a
+    jump on box faces is fine), kappa^2 = (an eigenvalue of box 0's -Lap_ii) * (1 + delta):
+    box 0's A_ii has a condition number ~1/delta, beyond FP32 refinement, while the other
+    boxes are well conditioned.  The eigenvalue comes from the oracle's D2."""
+    from oracle import cheb
+    h = 0.5
+    D = cheb.diffmat(p)
+    d2 = (D @ D)[1:-1, 1:-1] * (2.0 / h) ** 2
+    mu = np.sort(-np.linalg.eigvals(d2).real)
+    lam = 3.0 * mu[0]  # the lowest mode, (i, j, k) = (0, 0, 0)
+    kappa = float(np.sqrt(lam * (1.0 + delta)))
+    base = W.multi_bump((2, 2, 2), p, kappa, 41, gaussian_source=True, name="near_resonant")
+
+    def b(x):
+        x = np.asarray(x)
+        inside = (x[..., 0] < 0.5) & (x[..., 1] < 0.5) & (x[..., 2] < 0.5)
+        return np.where(inside, 1.0, 1.2)
+
+    import dataclasses
+    return dataclasses.replace(base, b=b)
+
+
+def test_fp64_fallback_near_singular_box(gpu):
+    # A box whose FP32 refinement really diverges: the build flags it and redoes its DtN in
+    # FP64 (bitwise the FP64 plan's blocks), the solve stage takes its interior from FP64
+    # factors (the FP32 ones leave a backward error far above tolerance), the other boxes
+    # stay on the FP32 path.  Against the oracle the tolerance is cond(A_ii) u64 ~ 1e-10
+    # scaled by the interface amplification; without the FP64 interiors the error is O(1).
+    from paper_2503_04033_amd.solver import TwoLevelSolver
+    prob = _near_resonant()
+    say(f"near-singular box: kappa={prob.kappa:.10f}")
+    s = TwoLevelSolver.for_problem(prob, precision="fp32_ir", chunk=8)
+    out = s.solve_problem(prob)
+    torch.cuda.synchronize()
+    br = out["build"]
+    it = br.ir_iters.cpu().numpy()
+    say(f"  ir_iters {it.tolist()}  fallback {br.extra['fp64_fallback']}  interior fp64 "
+        f"{br.extra['interior_fp64']}  interior berr max {br.extra['interior_berr_max']:.2e}")
+    assert br.extra["fp64_fallback"] == [0] and it[0] < 0 and np.all(it[1:] >= 0)
+    assert 0 in br.extra["interior_fp64"] and br.extra["interior_berr_max"] <= 1e-12
+    # box 0's blocks and load equal the FP64 plan's, bitwise
+    g64 = gpu_leaf_boxes(prob, [0], "fp64")
+    g32 = gpu_leaf_boxes(prob, [0], "fp32_ir")
+    assert g32["iters"][0] < 0
+    blocks = _box_blocks(s, br, 0)
+    assert len(blocks) == 9
+    for (a, b), blk in blocks.items():
+        assert np.array_equal(blk, g64["T6"][0, a, b]), (a, b)
+    ref = oi.solve(prob)
+    eu = rel(out["u_i"].cpu().numpy(), ref.u_i)
+    ef = rel(out["u_face"], ref.u_face)
+    say(f"  u_i err {eu:.2e}  u_face err {ef:.2e}")
+    assert eu < 1e-6 and ef < 1e-6
+
+
+def _box_blocks(s, br, t):
+    """{(a, b): block} of the DtN blocks box t wrote into its own slots of the interface
+    matrix (both faces internal; the shared diagonal blocks in the box's own extra slot)."""
+    i = s.info
+    mm = i.m * i.m
+    T = br.T_vals[:-1].view(-1, mm, mm).cpu().numpy()
+    out = {}
+    for a in range(6):
+        for b in range(6):
+            sl = int(s.layout.slot_map[t, 6 * a + b])
+            if sl >= 0:
+                out[(a, b)] = T[sl]
+    return out
 
 
 _ORACLE = {}
@@ -321,9 +392,13 @@ def test_interior_solve_and_flux(gpu, precision):
     plan.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], bufs["info"])
     ui = torch.empty(nb, i.n_i, dtype=torch.float64, device=dev)
     flux = torch.empty(nb, i.n_b, dtype=torch.float64, device=dev)
-    plan.hps_leaf_interior_solve(nb, bufs["A"], bufs["perm"], bufs["dinv"], bv, fv, ubd, ui, 2, bufs["ws"])
+    berr = torch.empty(nb, dtype=torch.float64, device=dev)
+    plan.hps_leaf_interior_solve(nb, bufs["A"], bufs["perm"], bufs["dinv"], bv, bufs["anorm"], fv, ubd, ui, 2, berr,
+                                 bufs["ws"])
     plan.hps_leaf_flux(nb, ui, ubd, flux)
     torch.cuda.synchronize()
+    say(f"  interior backward errors {berr.cpu().numpy().tolist()}")
+    assert float(berr.max()) < 1e-14
     ui_h, fl_h = ui.cpu().numpy(), flux.cpu().numpy()
     for k, t in enumerate(ids):
         blk = ol.local_blocks(prob.p, prob.h, prob.kappa, prob.b(xi[k]))

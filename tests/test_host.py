@@ -79,10 +79,19 @@ def test_bsr_layout(nboxes):
     assert per_row.max() <= 11 and per_row.min() >= 1
     if nboxes == (5, 5, 5):
         assert per_row.max() == 11
-    # slots: each unique block written by exactly one box, extra diagonal slots once
+    # slots: each unique off-diagonal block and each extra diagonal slot written by exactly
+    # one box; the BSR diagonal slots only by the reduction (dst = lower + upper)
     used = lay.slot_map[lay.slot_map >= 0]
     counts = np.bincount(used, minlength=lay.nslot_total)
-    assert np.all(counts == 1)
+    dst, lo, hi = lay.reduce_triples.T
+    assert np.all(counts[dst] == 0) and np.all(counts[lo] == 1) and np.all(counts[hi] == 1)
+    assert counts.sum() == counts.size - lay.nface
+    assert lay.nslot_total == lay.nslot + 2 * lay.nface
+    # the lower box of face F writes lo, the upper box hi
+    for F in range(lay.nface):
+        t_lo = np.nonzero(lay.box_faces[:, 1::2] == F)[0][0]
+        a = 2 * int(np.nonzero(lay.box_faces[t_lo, 1::2] == F)[0][0]) + 1
+        assert lay.slot_map[t_lo, 6 * a + a] == lo[F]
     # slot map is -1 exactly where a row or column face is on the boundary
     ok = (lay.box_faces[:, :, None] >= 0) & (lay.box_faces[:, None, :] >= 0)
     np.testing.assert_array_equal(lay.slot_map.reshape(nbox, 6, 6) >= 0, ok)
@@ -108,8 +117,8 @@ def test_bsr_assembly_equals_coo_sum():
                 s = lay.slot_map[t, 6 * a + b]
                 if s >= 0:
                     vals[s] = Tbox[t, a, b]
-    for dst, src in lay.reduce_pairs:
-        vals[dst] += vals[src]
+    for dst, lo, hi in lay.reduce_triples:
+        vals[dst] = vals[lo] + vals[hi]
     A = itf.bsr_matrix(lay, vals.ravel()).toarray()
     ref = np.zeros((lay.nface * mm, lay.nface * mm))
     for t in range(nbox):
