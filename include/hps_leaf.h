@@ -181,8 +181,9 @@ hps_status hps_leaf_reconstruct(hps_plan plan, int32_t nbox, const double* X, co
  * (NaN counts as +inf); anorm [nbox] (|A_ii|_inf from hps_leaf_operators) is
  * required when berr is given.  A caller compares berr with its tolerance: on
  * an ill-conditioned box FP32 factors can leave it large, and that box then
- * needs FP64 factors.  ws: hps_plan_info.ws_bytes per box (uses
- * 8 nbox (n_i + 3) bytes).  Any precision. */
+ * needs FP64 factors.  ws: at least 8 nbox (n_i + 3) bytes (one FP64 vector and
+ * three scalars per box; hps_plan_info.ws_bytes per box is always enough).  Any
+ * precision. */
 hps_status hps_leaf_interior_solve(hps_plan plan, int32_t nbox, const void* LU, const int32_t* perm,
                                   const void* dinv, const double* b, const double* anorm, const double* f,
                                   const double* u_b, double* u_i, int32_t steps, double* berr, void* ws,

@@ -178,8 +178,8 @@ class LeafPlan:
         i = self.info
         check(self.lib.hps_leaf_interior_solve(
             *self._interior_args(nbox, LU, perm, dinv, b, anorm, f, u_b, u_i, berr), int(steps),
-            _ptr(berr, torch.float64, nbox, "berr"), _ptr(ws, torch.uint8, nbox * i.ws_bytes, "ws"), _stream()),
-            "hps_leaf_interior_solve")
+            _ptr(berr, torch.float64, nbox, "berr"), _ptr(ws, torch.uint8, 8 * nbox * (i.n_i + 3), "ws"),
+            _stream()), "hps_leaf_interior_solve")
 
     def hps_leaf_flux(self, nbox: int, u_i, u_b, flux):
         i = self.info
