@@ -189,6 +189,23 @@ hps_status hps_leaf_interior_solve(hps_plan plan, int32_t nbox, const void* LU, 
                                   const double* u_b, double* u_i, int32_t steps, double* berr, void* ws,
                                   hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): hps_leaf_interior_solve
+ * without the ws argument.  Its scratch (8 nbox (n_i + 3) bytes) lives in a
+ * device array of HPS_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends; the call allocates nothing.  Returns
+ * HPS_EINVAL when 8 nbox (n_i + 3) exceeds HPS_NOALLOC_SCRATCH_BYTES (at most
+ * 1526 boxes at p = 16, 718 at p = 20), HPS_EDEVICE if the array's device
+ * address could not be looked up at hps_plan_create.  Every call on one GPU
+ * shares the array, so calls that overlap on one GPU (two streams, two host
+ * threads) race and give wrong results; order them on one stream.  Results are
+ * bitwise those of hps_leaf_interior_solve. */
+#define HPS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+hps_status hps_leaf_interior_solve_noalloc(hps_plan plan, int32_t nbox, const void* LU, const int32_t* perm,
+                                          const void* dinv, const double* b, const double* anorm,
+                                          const double* f, const double* u_b, double* u_i, int32_t steps,
+                                          double* berr, hipStream_t stream);
+
 /* Outward normal derivative at every face node of every box, flux = A_bi u_i +
  * A_bb u_b (the face rows of eq. Aentries: (2/h_a) D[p-1][.] along the normal line
  * on + faces, -(2/h_a) D[0][.] on - faces).  Summed over the two boxes of an

@@ -16,7 +16,11 @@ EXPORTS = (
     "hps_leaf_factor", "hps_leaf_dtn", "hps_interface_reduce", "hps_leaf_reconstruct", "hps_leaf_adjoint_solve",
     "hps_leaf_adjoint_grad", "hps_status_string", "hps_plan_profile_enable", "hps_plan_profile_read",
     "hps_leaf_interior_solve", "hps_leaf_flux", "hps_plan_set_tuning", "hps_plan_get_tuning",
+    "hps_leaf_interior_solve_noalloc",
 )
+
+# HPS_NOALLOC_SCRATCH_BYTES: the fixed scratch of hps_leaf_interior_solve_noalloc
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 HPS_TUNE_TRSM_SCHEDULE, HPS_TUNE_TRSM_WAVES, HPS_TUNE_RESIDUAL_COLS = 0, 1, 2
 TUNING_KEYS = {"trsm_schedule": HPS_TUNE_TRSM_SCHEDULE, "trsm_waves": HPS_TUNE_TRSM_WAVES,
@@ -72,6 +76,7 @@ def load() -> C.CDLL:
         "hps_leaf_adjoint_solve": [P, I32, P, P, P, P, P, P, P, P, P, P],
         "hps_leaf_adjoint_grad": [P, I32, P, P, P, P],
         "hps_leaf_interior_solve": [P, I32, P, P, P, P, P, P, P, P, I32, P, P, P],
+        "hps_leaf_interior_solve_noalloc": [P, I32, P, P, P, P, P, P, P, P, I32, P, P],
         "hps_leaf_flux": [P, I32, P, P, P, P],
         "hps_plan_profile_enable": [P, I32],
         "hps_plan_profile_read": [P, C.POINTER(Profile)],

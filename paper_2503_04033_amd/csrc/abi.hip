@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -23,6 +24,7 @@ struct hps_plan_s {
   int trsm_sched = hps::kTrsmRows;             // HPS_TUNE_TRSM_SCHEDULE
   int trsm_waves = 4;                          // HPS_TUNE_TRSM_WAVES
   int res_cols = 8;                            // HPS_TUNE_RESIDUAL_COLS
+  void* scratch = nullptr;                     // this device's address of `scratch` (below)
 };
 
 namespace {
@@ -144,6 +146,32 @@ WsLayout ws_layout(const hps_plan_s* pl, int nbox, void* ws) {
 }
 
 bool bad_plan(hps_plan p) { return p == nullptr; }
+
+// Scratch of hps_leaf_interior_solve_noalloc: a device array of fixed size that every
+// GPU the library runs on holds until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol): the
+// device address is looked up once per device, with that device current, and kept.
+constexpr size_t kNoAllocScratchBytes = HPS_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+std::mutex g_scratch_mu;
+std::vector<std::pair<int, void*>> g_scratch_addr;  // (device, address of scratch there)
+
+// Address of `scratch` on `device`, which must be the current device.
+hipError_t scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  for (const auto& e : g_scratch_addr)
+    if (e.first == device) {
+      *out = e.second;
+      return hipSuccess;
+    }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr.emplace_back(device, ptr);
+  *out = ptr;
+  return hipSuccess;
+}
 
 // Profiling only (synchronizes the stream): the flops of one solve over nbox boxes.
 // Algorithmic: n_i^2 (n_b + 1) per sweep and active box.  Executed: per 64-column tile
@@ -297,6 +325,9 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
     delete pl;
     return HPS_EDEVICE;
   }
+  // the no-allocation entry point's scratch on this device (a failed lookup only
+  // disables that entry point, which then returns HPS_EDEVICE)
+  if (scratch_address(pl->device, &pl->scratch) != hipSuccess) pl->scratch = nullptr;
   *out = pl;
   return HPS_OK;
 }
@@ -452,9 +483,9 @@ size_t interior_scratch_bytes(const Geom& g, int nbox) { return 8 * (size_t)nbox
 
 hps_status interior_solve(hps_plan pl, int nbox, const void* LU, const int32_t* perm, const void* dinv,
                           const double* b, const double* anorm, const double* f, const double* u_b, double* u_i,
-                          int steps, double* berr, double* scratch, hipStream_t st) {
+                          int steps, double* berr, double* work, hipStream_t st) {
   const Geom& g = pl->g;
-  double* r = scratch;
+  double* r = work;
   double* r0max = r + (size_t)nbox * g.n;
   double* rmax = r0max + nbox;
   double* umax = rmax + nbox;
@@ -498,6 +529,19 @@ hps_status hps_leaf_interior_solve(hps_plan pl, int32_t nbox, const void* LU, co
   if (nbox == 0) return HPS_OK;
   if (!ws) return HPS_EINVAL;
   return interior_solve(pl, nbox, LU, perm, dinv, b, anorm, f, u_b, u_i, steps, berr, static_cast<double*>(ws), st);
+}
+
+hps_status hps_leaf_interior_solve_noalloc(hps_plan pl, int32_t nbox, const void* LU, const int32_t* perm,
+                                          const void* dinv, const double* b, const double* anorm, const double* f,
+                                          const double* u_b, double* u_i, int32_t steps, double* berr,
+                                          hipStream_t st) {
+  const hps_status a = interior_args(pl, nbox, LU, perm, dinv, b, anorm, u_b, u_i, steps, berr);
+  if (a != HPS_OK) return a;
+  if (nbox == 0) return HPS_OK;
+  if (8 * (size_t)nbox * ((size_t)pl->g.n + 3) > kNoAllocScratchBytes) return HPS_EINVAL;
+  if (!pl->scratch) return HPS_EDEVICE;
+  return interior_solve(pl, nbox, LU, perm, dinv, b, anorm, f, u_b, u_i, steps, berr,
+                        static_cast<double*>(pl->scratch), st);
 }
 
 hps_status hps_leaf_flux(hps_plan pl, int32_t nbox, const double* u_i, const double* u_b, double* flux,

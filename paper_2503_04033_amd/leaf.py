@@ -181,6 +181,13 @@ class LeafPlan:
             _ptr(berr, torch.float64, nbox, "berr"), _ptr(ws, torch.uint8, 8 * nbox * (i.n_i + 3), "ws"),
             _stream()), "hps_leaf_interior_solve")
 
+    def hps_leaf_interior_solve_noalloc(self, nbox: int, LU, perm, dinv, b, anorm, f, u_b, u_i, steps: int,
+                                        berr):
+        """hps_leaf_interior_solve with the library's fixed device scratch (allocates nothing)."""
+        check(self.lib.hps_leaf_interior_solve_noalloc(
+            *self._interior_args(nbox, LU, perm, dinv, b, anorm, f, u_b, u_i, berr), int(steps),
+            _ptr(berr, torch.float64, nbox, "berr"), _stream()), "hps_leaf_interior_solve_noalloc")
+
     def hps_leaf_flux(self, nbox: int, u_i, u_b, flux):
         i = self.info
         check(self.lib.hps_leaf_flux(self.handle, nbox, _ptr(u_i, torch.float64, nbox * i.n_i, "u_i"),
