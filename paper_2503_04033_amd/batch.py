@@ -67,7 +67,7 @@ class BatchedLeafReduction:
     """Build stage (Alg. 1 loop) for several problems, one stream, optional graph."""
 
     def __init__(self, problems, precision: str = "fp32_ir", hbm_budget: float = 64e9, ir_max_iter: int = 3,
-                 ir_tol: float = 1e-12, chunks: Optional[List[int]] = None, device="cuda",
+                 ir_tol: Optional[float] = None, chunks: Optional[List[int]] = None, device="cuda",
                  tuning: Optional[List[dict]] = None):
         """chunks[q]: boxes per chunk of problem q (default: as many as fit hbm_budget).
         tuning[q]: plan knobs {name: value} for problem q (see LeafPlan.hps_plan_set_tuning)."""

@@ -28,6 +28,7 @@
 // modulus among the rows not yet pivoted, ties to the lowest current position;
 // after each sub-panel the chosen pivots take the next positions in order and
 // the remaining rows keep their relative order.
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -38,113 +39,144 @@ namespace hps {
 constexpr int kLuThreads = 512;
 constexpr int kLuWaves = kLuThreads / 64;
 
-// LDS of the panel kernel.  M = L11^{-1} and Nn = U11^{-1} of the panel's
-// growing diagonal block (positions [j0, j0+npv)), kept up to date after every
-// sub-panel, so the U part of a new sub-panel is one parallel product and the
+// Columns of a panel held in registers at a time: the widest of 32, 16, 8, 4 whose
+// ROWS x CW block takes at most 96 VGPRs (one 512-thread workgroup per CU keeps the
+// rest of the 256-register budget for the L values and the pivot row in flight).
+template <typename T, int ROWS>
+struct PanelChunk {
+  static constexpr int regs(int cw) { return ROWS * cw * (int)(sizeof(T) / 4); }
+  static constexpr int CW = regs(32) <= 96 ? 32 : (regs(16) <= 96 ? 16 : (regs(8) <= 96 ? 8 : 4));
+};
+
+// f(std::integral_constant<int, I>) for I = B .. E-1, expanded at compile time (indices into
+// register arrays stay static however long the body is).
+template <int B, int E, typename F>
+__device__ __attribute__((always_inline)) inline void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// LDS of the panel kernel.  M = L11^{-1} and Nn = U11^{-1} of the panel's growing
+// diagonal block (positions [j0, j0+npv)), kept up to date after every chunk, so the U
+// rows of the earlier pivots in a new chunk are one parallel product and the
 // diagonal-block inverses needed by the solves come out at the end for free.
-template <typename T>
+template <typename T, int CW>
 struct LuSmem {
   T M[64 * 65];
   T Nn[64 * 65];
-  T ub[64 * 8];          // U part of the current sub-panel (npv x SP)
-  T stg[64 * 8];         // staging of A[earlier pivots][sub-panel cols]; later Z = Nn * ub
-  T lq[8 * 64];          // new pivot rows' L values in the earlier panel columns (SP x npv)
-  T t1[8 * 64];          // lq * M
-  T uq[8 * 8];           // inverse of the new pivots' SP x SP upper block
-  T PR[8 * 8];           // new pivot rows in the sub-panel columns (SP x SP)
-  T wrow[2][kLuWaves][8];
+  T ub[64 * CW];           // U rows of the earlier pivots in the chunk columns (npv x CW)
+  T stg[64 * CW];          // their raw values; later Z = Nn * ub
+  T lq[CW * 64];           // the chunk's pivot rows' L values in earlier columns (CW x npv)
+  T t1[CW * 64];           // lq * M
+  T uq[CW * CW];           // inverse of the chunk pivots' CW x CW upper block
+  T PR[CW * CW];           // the chunk's pivot rows in the chunk columns (L left, U on and right)
+  T wrow[2][kLuWaves][CW];
   T wval[2][kLuWaves];
   int wslot[2][kLuWaves];
-  int cnt[32 * kLuWaves];
+  int pphys[64];           // physical row of the panel's k-th pivot
+  int cnt[16 * kLuWaves];
 };
 
-// Pivoted factorization of panel columns [j0, j0+W) for positions >= j0, in
-// sub-panels of SP columns.  Per sub-panel (columns [c0, c0+SP), npv = c0-j0
-// pivots already chosen in this panel):
-//   (a) U rows of the earlier pivots: ub = M * A[pivots, c0:c0+SP)
-//   (b) candidates (positions >= c0, one register row per slot): subtract
-//       L[row, j0:c0) * ub
-//   (c) SP pivot columns: per-wave best candidate (modulus, lowest slot on ties)
-//       and its row go to LDS, one barrier, every thread picks the winner
-//   (d) write back, (e) new position order: pivots first, the rest keep their
-//       relative order
-//   (f) extend M and Nn with the new pivots (block triangular inverses)
-// After the last sub-panel M and Nn are written to dinv_panel as Linv / Uinv.
-template <typename T, int ROWS, int SP, int W>
-__device__ __attribute__((noinline)) void lu_panel(const Geom& g, T* A, int* perm, int j0, LuSmem<T>& sm, int& info,
-                                                   T* dinv_panel) {
+template <typename T> struct Store4;
+template <> struct Store4<float> {
+  __device__ static inline void store(float* p, const float* v) {
+    *reinterpret_cast<f4*>(p) = f4{v[0], v[1], v[2], v[3]};
+  }
+};
+template <> struct Store4<double> {
+  __device__ static inline void store(double* p, const double* v) {
+    *reinterpret_cast<d2*>(p) = d2{v[0], v[1]};
+    *reinterpret_cast<d2*>(p + 2) = d2{v[2], v[3]};
+  }
+};
+
+// Pivoted factorization of panel columns [j0, j0+W) for positions >= j0.  Thread t
+// owns the rows at positions j0 + t + 512 r (r < ROWS) of the panel's start for the
+// whole panel, so a row is read and written by one thread only.  The columns go in
+// chunks of CW held in registers (left-looking between chunks, right-looking inside
+// one).  Per chunk (columns [cb, cb+CW), npv = cb - j0 pivots chosen before):
+//   (a) U rows of the earlier pivots in the chunk: ub = M * A[pivots, chunk)
+//   (b) candidate rows: v -= L[row, j0:cb) * ub, the L values read as whole
+//       128-byte lines
+//   (c) per column: per-wave best candidate (modulus, lowest position on ties) and
+//       its row to LDS, one barrier, every thread picks the winner; candidates are
+//       scaled and updated in registers
+//   (d) write back, (e) extend M and Nn with the chunk's pivots (block triangular
+//       inverses)
+// Candidates never change their relative order, so "lowest position" is the lowest
+// starting slot.  At the end the pivots take positions j0.. in order and the other
+// rows follow in their previous order; M and Nn go to dinv_panel as Linv / Uinv.
+template <typename T, int ROWS, int CW, int W>
+__device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T* A, int* perm, int j0, LuSmem<T, CW>& sm,
+                                                   int& info, T* dinv_panel) {
+  static_assert(W % CW == 0 && CW % 4 == 0, "chunks tile the panel");
+  constexpr int LB = CW < 16 ? CW : 16;  // L values loaded per step of (b)
   const int N = g.n_pad, lda = N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int q = 0; q < W / SP; q++) {
-    const int c0 = j0 + q * SP;
-    const int npv = c0 - j0;
-    // (a)
-    if (npv > 0) {
-      for (int e = tid; e < npv * SP; e += kLuThreads) {
-        const int i = e / SP, c = e - i * SP;
-        sm.stg[e] = A[(size_t)perm[j0 + i] * lda + c0 + c];
-      }
-      __syncthreads();
-      for (int e = tid; e < npv * SP; e += kLuThreads) {
-        const int i = e / SP, c = e - i * SP;
-        T s = T(0);
-        for (int k = 0; k <= i; k++) s += sm.M[i * 65 + k] * sm.stg[k * SP + c];
-        sm.ub[e] = s;
-        A[(size_t)perm[j0 + i] * lda + c0 + c] = s;
-      }
-      __syncthreads();
-    }
-    // (b)
-    const int nrem = N - c0;
-    T v[ROWS][SP];
-    int phys[ROWS];
-    bool done[ROWS];
+  const int nrem = N - j0;
+  int phys[ROWS];
+  int pk[ROWS];  // -1: candidate, >= 0: index of the pivot it became, -2: no row
+#pragma unroll
+  for (int r = 0; r < ROWS; r++) {
+    const int s = tid + kLuThreads * r;
+    phys[r] = s < nrem ? perm[j0 + s] : 0;
+    pk[r] = s < nrem ? -1 : -2;
+  }
+  for (int h = 0; h < W / CW; h++) {
+    const int cb = j0 + h * CW;
+    const int npv = h * CW;
+    T v[ROWS][CW];
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
-      const int s = tid + kLuThreads * r;
-      done[r] = s >= nrem;
-      phys[r] = done[r] ? 0 : perm[c0 + s];
-      const T* row = A + (size_t)phys[r] * lda;
+      const T* row = A + (size_t)phys[r] * lda + cb;
 #pragma unroll
-      for (int c = 0; c < SP; c += 4) {
-        T t4[4];
-        if (!done[r]) Vec4<T>::load(row + c0 + c, t4);
-        else t4[0] = t4[1] = t4[2] = t4[3] = T(0);
-#pragma unroll
-        for (int u = 0; u < 4; u++) v[r][c + u] = t4[u];
+      for (int c = 0; c < CW; c += 4) {
+        if (pk[r] != -2) Vec4<T>::load(row + c, v[r] + c);
+        else v[r][c] = v[r][c + 1] = v[r][c + 2] = v[r][c + 3] = T(0);
       }
     }
-    for (int k0 = 0; k0 < npv; k0 += SP) {  // npv is a multiple of SP
-      T lb[ROWS][SP];
+    if (npv > 0) {
+      // (a)
+#pragma unroll
+      for (int r = 0; r < ROWS; r++)
+        if (pk[r] >= 0)
+#pragma unroll
+          for (int c = 0; c < CW; c++) sm.stg[pk[r] * CW + c] = v[r][c];
+      __syncthreads();
+      for (int e = tid; e < npv * CW; e += kLuThreads) {
+        const int k = e / CW, c = e - k * CW;
+        T s = T(0);
+        for (int i = 0; i <= k; i++) s += sm.M[k * 65 + i] * sm.stg[i * CW + c];
+        sm.ub[e] = s;
+        A[(size_t)sm.pphys[k] * lda + cb + c] = s;
+      }
+      __syncthreads();
+      // (b)
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        const T* row = A + (size_t)phys[r] * lda + j0 + k0;
+        if (pk[r] != -1) continue;
+        const T* row = A + (size_t)phys[r] * lda + j0;
+        for (int k0 = 0; k0 < npv; k0 += LB) {
+          T lb[LB];
 #pragma unroll
-        for (int u = 0; u < SP; u += 4) {
-          if (!done[r]) Vec4<T>::load(row + u, lb[r] + u);
-          else lb[r][u] = lb[r][u + 1] = lb[r][u + 2] = lb[r][u + 3] = T(0);
+          for (int u = 0; u < LB; u += 4) Vec4<T>::load(row + k0 + u, lb + u);
+#pragma unroll
+          for (int u = 0; u < LB; u++)
+#pragma unroll
+            for (int c = 0; c < CW; c++) v[r][c] -= lb[u] * sm.ub[(k0 + u) * CW + c];
         }
-      }
-#pragma unroll
-      for (int u = 0; u < SP; u++) {
-        T ubr[SP];
-#pragma unroll
-        for (int c = 0; c < SP; c++) ubr[c] = sm.ub[(k0 + u) * SP + c];
-#pragma unroll
-        for (int r = 0; r < ROWS; r++)
-#pragma unroll
-          for (int c = 0; c < SP; c++) v[r][c] -= lb[r][u] * ubr[c];
       }
     }
     // (c)
-    int pivslot[SP];
-#pragma unroll
-    for (int c = 0; c < SP; c++) {
+    static_for<0, CW>([&](auto ic) __attribute__((always_inline)) {
+      constexpr int c = decltype(ic)::value;
       T best = T(-1);
       int bslot = 0x7fffffff;
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        if (!done[r]) {
+        if (pk[r] == -1) {
           T a = fabs(v[r][c]);
           if (a != a) a = T(INFINITY);  // a NaN is taken as the pivot and flagged below
           const int s = tid + kLuThreads * r;
@@ -167,7 +199,7 @@ __device__ __attribute__((noinline)) void lu_panel(const Geom& g, T* A, int* per
         for (int r = 0; r < ROWS; r++)
           if (r == bslot / kLuThreads)
 #pragma unroll
-            for (int cc = 0; cc < SP; cc++) sm.wrow[buf][wave][cc] = v[r][cc];
+            for (int cc = 0; cc < CW; cc++) sm.wrow[buf][wave][cc] = v[r][cc];
       }
       __syncthreads();
       int wbest = 0;
@@ -179,137 +211,121 @@ __device__ __attribute__((noinline)) void lu_panel(const Geom& g, T* A, int* per
         const int os = sm.wslot[buf][w];
         if (ob > best || (ob == best && os < bslot)) { best = ob; bslot = os; wbest = w; }
       }
-      const int ps = bslot;
-      pivslot[c] = ps;
-      T pr[SP];
-#pragma unroll
-      for (int cc = 0; cc < SP; cc++) pr[cc] = sm.wrow[buf][wbest][cc];
-      if ((ps & (kLuThreads - 1)) == tid) {
+      const T* pr = sm.wrow[buf][wbest];
+      if ((bslot & (kLuThreads - 1)) == tid) {
 #pragma unroll
         for (int r = 0; r < ROWS; r++)
-          if (r == ps / kLuThreads) done[r] = true;
+          if (r == bslot / kLuThreads) {
+            pk[r] = npv + c;
+            sm.pphys[npv + c] = phys[r];
+          }
       }
-      if (tid == 0) {
-#pragma unroll
-        for (int cc = 0; cc < SP; cc++) sm.PR[c * SP + cc] = pr[cc];
-      }
+      if (tid < CW) sm.PR[c * CW + tid] = pr[tid];
       const T pv = pr[c];
-      if (!(pv != T(0) && isfinite(pv)) && info == 0) info = c0 + c + 1;
+      if (!(pv != T(0) && isfinite(pv)) && info == 0) info = cb + c + 1;
       const T inv = pv != T(0) ? T(1) / pv : T(0);
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        if (!done[r]) {
+        if (pk[r] == -1) {
           const T l = v[r][c] * inv;
           v[r][c] = l;
 #pragma unroll
-          for (int cc = c + 1; cc < SP; cc++) v[r][cc] -= l * pr[cc];
+          for (int cc = c + 1; cc < CW; cc++) v[r][cc] -= l * pr[cc];
         }
       }
-    }
-    // (d)
+    });
+    // (d) candidates and this chunk's pivots; earlier pivots got their U rows in (a)
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
-      const int s = tid + kLuThreads * r;
-      if (s < nrem) {
-        T* row = A + (size_t)phys[r] * lda;
+      if (pk[r] == -1 || pk[r] >= npv) {
+        T* row = A + (size_t)phys[r] * lda + cb;
 #pragma unroll
-        for (int c = 0; c < SP; c++) row[c0 + c] = v[r][c];
-      }
-    }
-    // (e)
-    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int pre[ROWS];
-#pragma unroll
-    for (int r = 0; r < ROWS; r++) {
-      const int s = tid + kLuThreads * r;
-      const bool keep = (s < nrem) && !done[r];
-      const unsigned long long mask = __ballot(keep);
-      pre[r] = __popcll(mask & lt);
-      if (lane == 0) sm.cnt[r * kLuWaves + wave] = __popcll(mask);
-    }
-    __syncthreads();
-    int base = c0 + SP;
-#pragma unroll
-    for (int r = 0; r < ROWS; r++) {
-      const int s = tid + kLuThreads * r;
-      int before = 0, tot = 0;
-#pragma unroll
-      for (int w = 0; w < kLuWaves; w++) {
-        const int cw = sm.cnt[r * kLuWaves + w];
-        tot += cw;
-        if (w < wave) before += cw;
-      }
-      if (s < nrem && !done[r]) perm[base + before + pre[r]] = phys[r];
-      base += tot;
-    }
-#pragma unroll
-    for (int c = 0; c < SP; c++) {
-      const int ps = pivslot[c];
-      if ((ps & (kLuThreads - 1)) == tid) {
-#pragma unroll
-        for (int r = 0; r < ROWS; r++)
-          if (r == ps / kLuThreads) perm[c0 + c] = phys[r];
+        for (int c = 0; c < CW; c += 4) Store4<T>::store(row + c, v[r] + c);
       }
     }
     __syncthreads();
-    // (f) M <- [[M, 0], [-Lq^{-1} lq M, Lq^{-1}]],  Nn <- [[Nn, -Nn ub Uq^{-1}], [0, Uq^{-1}]]
-    for (int e = tid; e < SP * npv; e += kLuThreads) {
+    // (e) M <- [[M, 0], [-Lq^{-1} lq M, Lq^{-1}]],  Nn <- [[Nn, -Nn ub Uq^{-1}], [0, Uq^{-1}]]
+    for (int e = tid; e < CW * npv; e += kLuThreads) {
       const int i = e / npv, k = e - i * npv;
-      sm.lq[i * 64 + k] = A[(size_t)perm[c0 + i] * lda + j0 + k];
+      sm.lq[i * 64 + k] = A[(size_t)sm.pphys[npv + i] * lda + j0 + k];
     }
     __syncthreads();
-    for (int e = tid; e < SP * npv; e += kLuThreads) {
+    for (int e = tid; e < CW * npv; e += kLuThreads) {
       const int i = e / npv, j = e - i * npv;
       T s = T(0);
       for (int k = j; k < npv; k++) s += sm.lq[i * 64 + k] * sm.M[k * 65 + j];
       sm.t1[i * 64 + j] = s;
     }
-    for (int e = tid; e < npv * SP; e += kLuThreads) {
-      const int r = e / SP, c = e - r * SP;
+    for (int e = tid; e < npv * CW; e += kLuThreads) {
+      const int r = e / CW, c = e - r * CW;
       T s = T(0);
-      for (int i = r; i < npv; i++) s += sm.Nn[r * 65 + i] * sm.ub[i * SP + c];
+      for (int i = r; i < npv; i++) s += sm.Nn[r * 65 + i] * sm.ub[i * CW + c];
       sm.stg[e] = s;
     }
     __syncthreads();
-    if (tid < npv + SP) {
+    if (tid < npv + CW) {
       const int j = tid;
-      T x[SP];
-#pragma unroll
-      for (int i = 0; i < SP; i++) {
+      T x[CW];
+      static_for<0, CW>([&](auto ii) __attribute__((always_inline)) {
+        constexpr int i = decltype(ii)::value;
         T s = j < npv ? -sm.t1[i * 64 + j] : (j - npv == i ? T(1) : T(0));
 #pragma unroll
-        for (int r = 0; r < i; r++) s -= sm.PR[i * SP + r] * x[r];
+        for (int r = 0; r < i; r++) s -= sm.PR[i * CW + r] * x[r];
         x[i] = s;
         sm.M[(npv + i) * 65 + j] = s;
-      }
-    } else if (tid >= 64 && tid < 64 + SP) {
+      });
+    } else if (tid >= 64 && tid < 64 + CW) {
       const int j = tid - 64;
-      T y[SP];
-#pragma unroll
-      for (int i = SP - 1; i >= 0; i--) {
+      T y[CW];
+      static_for<0, CW>([&](auto ii) __attribute__((always_inline)) {
+        constexpr int i = CW - 1 - decltype(ii)::value;
         T s = (i == j) ? T(1) : T(0);
 #pragma unroll
-        for (int k = i + 1; k < SP; k++) s -= sm.PR[i * SP + k] * y[k];
-        y[i] = s / sm.PR[i * SP + i];
-      }
+        for (int k = i + 1; k < CW; k++) s -= sm.PR[i * CW + k] * y[k];
+        y[i] = s / sm.PR[i * CW + i];
+      });
 #pragma unroll
-      for (int i = 0; i < SP; i++) sm.uq[i * SP + j] = i <= j ? y[i] : T(0);
+      for (int i = 0; i < CW; i++) sm.uq[i * CW + j] = i <= j ? y[i] : T(0);
     }
     __syncthreads();
-    for (int e = tid; e < (npv + SP) * SP; e += kLuThreads) {
-      const int r = e / SP, j = e - r * SP;
+    for (int e = tid; e < (npv + CW) * CW; e += kLuThreads) {
+      const int r = e / CW, j = e - r * CW;
       T s;
       if (r < npv) {
         s = T(0);
 #pragma unroll
-        for (int i = 0; i < SP; i++) s -= sm.stg[r * SP + i] * sm.uq[i * SP + j];
+        for (int i = 0; i < CW; i++) s -= sm.stg[r * CW + i] * sm.uq[i * CW + j];
       } else {
-        s = sm.uq[(r - npv) * SP + j];
+        s = sm.uq[(r - npv) * CW + j];
       }
       sm.Nn[r * 65 + npv + j] = s;
     }
     __syncthreads();
   }
+  // new position order: the W pivots, then the other rows in their previous order
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int pre[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; r++) {
+    const unsigned long long mask = __ballot(pk[r] == -1);
+    pre[r] = __popcll(mask & lt);
+    if (lane == 0) sm.cnt[r * kLuWaves + wave] = __popcll(mask);
+  }
+  __syncthreads();
+  int base = j0 + W;
+#pragma unroll
+  for (int r = 0; r < ROWS; r++) {
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kLuWaves; w++) {
+      const int cw = sm.cnt[r * kLuWaves + w];
+      tot += cw;
+      if (w < wave) before += cw;
+    }
+    if (pk[r] == -1) perm[base + before + pre[r]] = phys[r];
+    base += tot;
+  }
+  if (tid < W) perm[j0 + tid] = sm.pphys[tid];
   T* Linv = dinv_panel;
   T* Uinv = dinv_panel + 64 * 64;
   for (int e = tid; e < W * W; e += kLuThreads) {
@@ -340,10 +356,10 @@ __global__ void lu_init_kernel(int N, int* perm_all, int* info, int nbox) {
   if (blockIdx.x == 0 && threadIdx.x == 0) info[box] = 0;
 }
 
-template <typename T, int ROWS, int SP, int W>
-__global__ __launch_bounds__(kLuThreads, 1) void lu_panel_kernel(Geom g, T* A_all, int* perm_all, T* dinv_all,
+template <typename T, int ROWS, int CW, int W>
+__global__ __launch_bounds__(kLuThreads, 2) void lu_panel_kernel(Geom g, T* A_all, int* perm_all, T* dinv_all,
                                                                   int* info_all, int nbox, int c0) {
-  __shared__ LuSmem<T> sm;
+  __shared__ LuSmem<T, CW> sm;
   const int box = blockIdx.x;
   if (box >= nbox) return;
   const int N = g.n_pad;
@@ -351,7 +367,7 @@ __global__ __launch_bounds__(kLuThreads, 1) void lu_panel_kernel(Geom g, T* A_al
   int* perm = perm_all + (size_t)box * N;
   T* dp = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(c0 / kPanel) * 2 * 64 * 64;
   int info = 0;
-  lu_panel<T, ROWS, SP, W>(g, A, perm, c0, sm, info, dp);
+  lu_panel<T, ROWS, CW, W>(g, A, perm, c0, sm, info, dp);
   if (threadIdx.x == 0 && info != 0 && info_all[box] == 0) info_all[box] = info;
 }
 
@@ -732,19 +748,20 @@ static hipError_t launch_gemm(const Geom& g, const T* F, const int* perm, T* X, 
 }
 
 
-template <typename T, int ROWS, int SP>
+template <typename T, int ROWS>
 static hipError_t launch_panel(const Geom& g, T* A, int* perm, T* dinv, int* info, int nbox, int c0, int w,
                                hipStream_t st) {
+  constexpr int CW = PanelChunk<T, ROWS>::CW;
   if (w == 64)
-    hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, SP, 64>), dim3(nbox), dim3(kLuThreads), 0, st, g, A, perm, dinv,
+    hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, CW, 64>), dim3(nbox), dim3(kLuThreads), 0, st, g, A, perm, dinv,
                        info, nbox, c0);
   else
-    hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, SP, 32>), dim3(nbox), dim3(kLuThreads), 0, st, g, A, perm, dinv,
-                       info, nbox, c0);
+    hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, (CW < 32 ? CW : 32), 32>), dim3(nbox), dim3(kLuThreads), 0, st, g,
+                       A, perm, dinv, info, nbox, c0);
   return hipGetLastError();
 }
 
-template <typename T, int ROWS, int SP>
+template <typename T, int ROWS>
 static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
                          hipStream_t st, Profiler* prof) {
   const int N = g.n_pad;
@@ -754,7 +771,7 @@ static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* 
     const int* op = ops.data() + q;
     if (op[0] == kOpPanel) {
       ProfScope ps(prof, Profiler::kLuPanel, 0.0, st);
-      e = launch_panel<T, ROWS, SP>(g, A, perm, dinv, info, nbox, op[1], op[2], st);
+      e = launch_panel<T, ROWS>(g, A, perm, dinv, info, nbox, op[1], op[2], st);
     } else if (op[0] == kOpRows) {
       const int r0 = op[1], r1 = op[2], cA = op[3], cB = op[4], ntn = (cB - cA + 63) / 64;
       for (int s = r0; s < r1 && e == hipSuccess; s += kPanel) {
@@ -776,13 +793,12 @@ template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
                      hipStream_t st, Profiler* prof) {
   const int rows = (g.n_pad + kLuThreads - 1) / kLuThreads;
-  constexpr int SP = sizeof(T) == 4 ? 8 : 4;
-  if (rows <= 1) return run_lu<T, 1, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
-  if (rows <= 2) return run_lu<T, 2, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
-  if (rows <= 4) return run_lu<T, 4, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
-  if (rows <= 6) return run_lu<T, 6, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
-  if (rows <= 8) return run_lu<T, 8, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
-  if (rows <= 12) return run_lu<T, 12, SP>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 1) return run_lu<T, 1>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 2) return run_lu<T, 2>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 4) return run_lu<T, 4>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 6) return run_lu<T, 6>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 8) return run_lu<T, 8>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  if (rows <= 12) return run_lu<T, 12>(g, ops, A, perm, dinv, info, nbox, st, prof);
   return hipErrorInvalidValue;
 }
 

@@ -51,11 +51,24 @@ class Info:
     ws_bytes: int
 
 
+def default_ir_tol(p: int) -> float:
+    """Backward-error tolerance of the FP64 refinement when the caller gives none.
+
+    The forward error of X is about cond(A_ii) times the backward error, and cond(A_ii)
+    grows with p (like p^4 for the spectral second derivative) and near interior
+    resonances of the box.  1e-12 leaves X within ~1e-13 of FP64 at p <= 16 (one
+    correction); at p = 17-20 one correction can end just under 1e-12 with X still
+    ~6e-10 away, so those take 1e-13 (two corrections, X within ~3e-13)."""
+    return 1e-12 if int(p) <= 16 else 1e-13
+
+
 class LeafPlan:
     """Owns one hps_plan (Chebyshev tables on the device) for a box size and wavenumber."""
 
     def __init__(self, p: int, h, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
-                 ir_tol: float = 1e-12):
+                 ir_tol: Optional[float] = None):
+        if ir_tol is None:
+            ir_tol = default_ir_tol(p)
         self.lib = _lib.load()
         d = _lib.LeafDesc()
         d.p = int(p)

@@ -112,7 +112,7 @@ class TwoLevelSolver:
     MAX_CHUNK = 1024
 
     def __init__(self, nboxes, lo, hi, p: int, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
-                 ir_tol: float = 1e-12, chunk: Optional[int] = None, keep: Optional[bool] = None, device="cuda",
+                 ir_tol: Optional[float] = None, chunk: Optional[int] = None, keep: Optional[bool] = None, device="cuda",
                  refine: Optional[int] = None, refine_steps: int = 2, tuning: Optional[dict] = None,
                  hbm_budget: Optional[float] = None, interior_tol: float = 1e-12):
         self.nboxes = tuple(int(v) for v in nboxes)

@@ -4,7 +4,10 @@ Tolerances.  FP64 path: the kernels and the oracle evaluate the same exact
 algebra in different orders; with kappa(A_ii) <= ~1e4 the forward error is
 bounded by kappa * O(n u64) ~ 1e-11, so 1e-10 relative (Frobenius, per box)
 is used for X and T.  FP32 + FP64 refinement: the metric's bar, 1e-9 relative.
-Solutions: relative l2 over all nodes, same bars.
+Solutions: relative l2 over all nodes, same bars.  Boxes of the headline grids
+(h = 1/16 at p = 16, h = 1/8 at p = 12) also meet a regression guard of 1e-11, the
+level this path measures there (1e-13 to 1e-12); large boxes (h = 1/2 to 1) are worse
+conditioned and land at up to ~5e-11 in FP32 + refinement.
 """
 import numpy as np
 import pytest
@@ -18,9 +21,10 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-10
 IR_TOL = 1e-9
+GUARD = 1e-11
 
 
-def _check_leaf(prob, box_ids, precision, tol, f_on=True, tuning=None):
+def _check_leaf(prob, box_ids, precision, tol, f_on=True, tuning=None, guard=None):
     say(f"case {prob.name} p={prob.p} boxes={list(box_ids)} {precision} tuning={tuning}")
     gout = gpu_leaf_boxes(prob, box_ids, precision, f_on=f_on, tuning=tuning)
     ored = oracle_leaf_boxes(prob, box_ids, f_on=f_on)
@@ -34,6 +38,8 @@ def _check_leaf(prob, box_ids, precision, tol, f_on=True, tuning=None):
     say(f"  errors X {eX:.2e} T {eT:.2e} g {eg:.2e} iters {gout['iters'].tolist()[:8]} "
         f"berr max {gout['berr'].max():.2e}")
     assert eX < tol and eT < tol and eg < tol
+    if guard is not None:  # regression guard at the level measured for this case
+        assert max(eX, eT, eg) < guard, f"X {eX:.2e} T {eT:.2e} g {eg:.2e} above {guard}"
     return gout
 
 
@@ -131,12 +137,12 @@ def test_factorization_property(gpu):
 def test_leaf_p12_sampled(gpu, precision, tol):
     # configuration-2 boxes (p = 12, kappa = 20, single bump); oracle on 4 boxes
     prob = W.config2()
-    _check_leaf(prob, [0, 63, 300, 511], precision, tol, f_on=False)
+    _check_leaf(prob, [0, 63, 300, 511], precision, tol, f_on=False, guard=GUARD)
 
 
 def test_leaf_p16_sampled_fp32_ir(gpu):
     prob = W.config3()
-    _check_leaf(prob, [0, 2047], "fp32_ir", IR_TOL, f_on=False)
+    _check_leaf(prob, [0, 2047], "fp32_ir", IR_TOL, f_on=False, guard=GUARD)
 
 
 def _pipeline(prob, precision, tol):
