@@ -75,43 +75,45 @@ def host_cpu() -> dict:
             "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
-def solve_stage(torch, prob, precision: str) -> dict:
-    """Build and solve stages end to end on a grid whose interface system the host solves
-    (paper Alg. 1 and Alg. 2): GPU build (a1-a4), copy of T and the loads, host factorization
-    of the interface matrix, interface solve, and the GPU interiors with the solve stage's
-    outer refinement (FP32+IR).  Wall-clock seconds per part; inputs resident in HBM."""
+def solve_stage(torch, prob, precision: str, interface: str) -> dict:
+    """Build and solve stages end to end on a grid whose interface system also fits the host
+    (paper Alg. 1 and Alg. 2): GPU build (a1-a4), factorization of the interface matrix
+    (interface 'gpu': nested dissection with dense fronts in HBM; 'host': copy of T and LAPACK
+    on the host cores), interface solve, and the GPU interiors with the solve stage's outer
+    refinement (FP32+IR).  Wall-clock seconds per part; inputs resident in HBM."""
     from paper_2503_04033_amd import interface as itf
+    from paper_2503_04033_amd.nested import NestedDissection
     from paper_2503_04033_amd.solver import TwoLevelSolver
-    s = TwoLevelSolver.for_problem(prob, precision=precision)
+    s = TwoLevelSolver.for_problem(prob, precision=precision, interface=interface)
     bv, fv, gv, _, _ = s.sample(prob.b, prob.f, prob.g)
-    s.build(bv, fv, gv)  # warm-up (kernel loading, allocator)
+    br = s.build(bv, fv, gv)  # warm-up (kernel loading, allocator)
+    if interface == "gpu":
+        s.interface_solver(br)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     br = s.build(bv, fv, gv)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    T_host = br.T_vals.cpu().numpy()
-    t2 = time.perf_counter()
-    isolver = itf.InterfaceSolver(s.layout, T_host)
+    if interface == "gpu":
+        isolver = NestedDissection(s.layout, s.device)
+        t2 = time.perf_counter()
+        isolver.factor(br.T_vals)
+        torch.cuda.synchronize()
+        method, mem = "gpu nested dissection", isolver.memory_bytes()
+    else:
+        T_host = br.T_vals.cpu().numpy()
+        t2 = time.perf_counter()
+        isolver = itf.InterfaceSolver(s.layout, T_host)
+        method, mem = "host " + isolver.method, None
     t3 = time.perf_counter()
     u_face, ub, ui, _ = s.solve(br, gv, isolver, b=bv, f=fv)
     torch.cuda.synchronize()
     t4 = time.perf_counter()
-    # one pass of the GPU interiors alone (what the solve stage repeats per refinement round)
-    ub_d = torch.tensor(ub, device=s.device)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    if s.refine > 0 or br.X is None:
-        s._interiors(br, ub_d, bv, fv, want_flux=False)
-    else:
-        s.plan.hps_leaf_reconstruct(s.nbox, br.X, ub_d, torch.empty_like(ui))
-    e1.record()
-    torch.cuda.synchronize()
-    return {"precision": precision, "nbox": s.nbox, "interface_unknowns": int(s.layout.nunknown),
-            "interface_method": isolver.method, "keep": s.keep, "chunk": s.chunk, "refine_rounds": s.refine,
-            "build_s": round(t1 - t0, 4), "copy_T_s": round(t2 - t1, 4), "interface_factor_s": round(t3 - t2, 4),
-            "solve_stage_s": round(t4 - t3, 4), "interiors_gpu_ms": round(e0.elapsed_time(e1), 3),
-            "end_to_end_s": round(t4 - t0, 4), "u_i": ui, "u_face": u_face,
+    return {"precision": precision, "interface": method, "nbox": s.nbox,
+            "interface_unknowns": int(s.layout.nunknown), "interface_device_bytes": mem, "keep": s.keep,
+            "chunk": s.chunk, "refine_rounds": s.refine, "build_s": round(t1 - t0, 4),
+            "interface_setup_s": round(t2 - t1, 4), "interface_factor_s": round(t3 - t2, 4),
+            "solve_stage_s": round(t4 - t3, 4), "end_to_end_s": round(t4 - t0, 4), "u_i": ui, "u_face": u_face,
             "interior_fp64_boxes": len(br.extra.get("interior_fp64", [])),
             "build_fp64_fallback_boxes": len(br.extra.get("fp64_fallback", []))}
 
@@ -405,19 +407,21 @@ def main():
         # interface solve fits: the same family at 4x4x4 boxes, p = 16, kappa = 40
         small = W.multi_bump((4, 4, 4), 16, 40.0, 3, name="cfg3_4x4x4_p16")
         legs = {}
-        for prec in ("fp32_ir", "fp64"):
-            legs[prec] = solve_stage(torch, small, prec)
+        for prec, itf_kind in (("fp32_ir", "gpu"), ("fp64", "gpu"), ("fp64", "host")):
+            key = f"{prec}_{itf_kind}"
+            legs[key] = solve_stage(torch, small, prec, itf_kind)
             torch.cuda.empty_cache()
-            log(f"solve stage {prec}: { {k: v for k, v in legs[prec].items() if k not in ('u_i', 'u_face')} }")
-        du = float(torch.linalg.norm(legs["fp32_ir"]["u_i"] - legs["fp64"]["u_i"]) /
-                   torch.linalg.norm(legs["fp64"]["u_i"]))
-        df = float(np.linalg.norm(legs["fp32_ir"]["u_face"] - legs["fp64"]["u_face"]) /
-                   np.linalg.norm(legs["fp64"]["u_face"]))
+            log(f"solve stage {key}: { {k: v for k, v in legs[key].items() if k not in ('u_i', 'u_face')} }")
+        ref = legs["fp64_host"]
+        du = {k: float(torch.linalg.norm(v["u_i"] - ref["u_i"]) / torch.linalg.norm(ref["u_i"]))
+              for k, v in legs.items() if k != "fp64_host"}
+        df = {k: float(np.linalg.norm(v["u_face"] - ref["u_face"]) / np.linalg.norm(ref["u_face"]))
+              for k, v in legs.items() if k != "fp64_host"}
         for v in legs.values():
             v.pop("u_i")
             v.pop("u_face")
-        result["solve_stage_4x4x4_p16"] = {"legs": legs, "rel_diff_u_i_fp32ir_vs_fp64": du,
-                                           "rel_diff_u_face_fp32ir_vs_fp64": df}
+        result["solve_stage_4x4x4_p16"] = {"legs": legs, "rel_diff_u_i_vs_fp64_host": du,
+                                           "rel_diff_u_face_vs_fp64_host": df}
     if not a.no_cpu:
         result["cpu_baseline"] = cpu_baseline(prob, a.cpu_sample)
         log(f"cpu baseline {result['cpu_baseline']}")

@@ -230,6 +230,59 @@ hps_status hps_leaf_adjoint_solve(hps_plan plan, int32_t nbox, const void* LU, c
 hps_status hps_leaf_adjoint_grad(hps_plan plan, int32_t nbox, const double* lam_i, const double* u_i,
                                  double* grad, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Interface system T u_F = rhs on the GPU (the sparse factorization that the paper
+ * hands to a multifrontal CPU solver, Sec. 3.1 and Sec. 3.3; its cost dominates the
+ * build stage, Sec. 4.2).  Nested dissection over the box grid with dense fronts: a
+ * front holds the n_P separator unknowns its two halves share (first, padded to n_piv)
+ * and the unknowns of its outer boundary (after them), F = [[A_PP, A_PB],
+ * [A_BP, A_BB]], assembled by the caller from the halves' Schur complements (a single
+ * box contributes its DtN blocks T^tau).  Fronts are FP64, row-major n x n, stored
+ * back to back; perm [nfront][n] int32; dinv [nfront][hps_front_dinv_elems] FP64.
+ * ------------------------------------------------------------------------- */
+typedef struct hps_front_plan_s* hps_front_plan;
+
+/* A plan for fronts of n rows (64 <= n <= 12288, a multiple of 32) whose first n_piv
+ * rows and columns (a multiple of 64, <= n) are eliminated.  HPS_EINVAL for other
+ * sizes, HPS_EDEVICE if the solve kernel's LDS limit cannot be raised. */
+hps_status hps_front_plan_create(hps_front_plan* plan, int32_t n, int32_t n_piv);
+hps_status hps_front_plan_destroy(hps_front_plan plan);
+/* Elements of dinv per front (0 for a null plan). */
+size_t hps_front_dinv_elems(hps_front_plan plan);
+
+/* F = 0 for nfront fronts of n x n, with ones on the diagonal at positions [d0, d1)
+ * and [d2, d3) (the padding of the separator and boundary blocks). */
+hps_status hps_front_init(int32_t nfront, int32_t n, int32_t d0, int32_t d1, int32_t d2, int32_t d3, double* F,
+                          hipStream_t stream);
+
+/* Extend-add of bm x bm blocks: for each task t = tasks[4t .. 4t+3] = (dst offset, src
+ * offset, dst row stride, src row stride), in elements, dst[d + i ld_d + j] += src[s +
+ * i ld_s + j].  Tasks of one call must write disjoint blocks (the caller adds the two
+ * halves of a front in two calls, so that sums have a fixed order). */
+hps_status hps_front_block_add(int32_t ntask, const int64_t* tasks, int32_t bm, double* dst, const double* src,
+                               hipStream_t stream);
+
+/* Segments of len doubles: for each task (dst offset, src offset) = tasks[2t .. 2t+1],
+ * dst[d + i] = src[s + i] (add = 0), dst[d + i] += src[s + i] (add = 1) or
+ * dst[d + i] -= src[s + i] (add = -1).  Tasks of one call must write disjoint segments. */
+hps_status hps_front_segments(int32_t ntask, const int64_t* tasks, int32_t len, double* dst, const double* src,
+                              int32_t add, hipStream_t stream);
+
+/* Partial LU of nfront fronts in place: row pivoting among the first n_piv rows (the
+ * leaf LU's panel rule), P_r A_PP = L11 U11, L21 = A_BP U11^{-1}, U12 = L11^{-1} P_r A_PB,
+ * and the Schur complement S = A_BB - L21 U12 in rows and columns [n_piv, n).  Rows past
+ * n_piv keep their places (perm[i] = i there).  info[f] = 0, or k > 0 if the k-th pivot
+ * (1-based) is zero or not finite. */
+hps_status hps_front_factor(hps_front_plan plan, int32_t nfront, double* F, int32_t* perm, double* dinv,
+                            int32_t* info, hipStream_t stream);
+
+/* One vector per front, vec [nfront][n] FP64, in place.  mode 0 (upward): vec holds r
+ * in unknown order; on return positions [0, n_piv) hold y = L11^{-1} P_r r_P and
+ * [n_piv, n) hold r_B - L21 y.  mode 1 (downward): vec holds y (as mode 0 left it) and
+ * u_B in [n_piv, n); on return [0, n_piv) holds u_P = U11^{-1}(y - U12 u_B). */
+hps_status hps_front_solve(hps_front_plan plan, int32_t nfront, const double* F, const int32_t* perm,
+                           const double* dinv, double* vec, int32_t mode, hipStream_t stream);
+
 /* Run-time tuning of a plan.  A knob changes how the work is scheduled, never
  * what is computed: every setting gives bitwise the same results.
  *   HPS_TUNE_TRSM_SCHEDULE: the interior solves of hps_leaf_dtn (Alg. 1, the

@@ -16,7 +16,8 @@ EXPORTS = (
     "hps_leaf_factor", "hps_leaf_dtn", "hps_interface_reduce", "hps_leaf_reconstruct", "hps_leaf_adjoint_solve",
     "hps_leaf_adjoint_grad", "hps_status_string", "hps_plan_profile_enable", "hps_plan_profile_read",
     "hps_leaf_interior_solve", "hps_leaf_flux", "hps_plan_set_tuning", "hps_plan_get_tuning",
-    "hps_leaf_interior_solve_noalloc",
+    "hps_leaf_interior_solve_noalloc", "hps_front_plan_create", "hps_front_plan_destroy", "hps_front_dinv_elems",
+    "hps_front_init", "hps_front_block_add", "hps_front_segments", "hps_front_factor", "hps_front_solve",
 )
 
 # HPS_NOALLOC_SCRATCH_BYTES: the fixed scratch of hps_leaf_interior_solve_noalloc
@@ -82,11 +83,20 @@ def load() -> C.CDLL:
         "hps_plan_profile_read": [P, C.POINTER(Profile)],
         "hps_plan_set_tuning": [P, I32, I32],
         "hps_plan_get_tuning": [P, I32, C.POINTER(C.c_int32)],
+        "hps_front_plan_create": [C.POINTER(P), I32, I32],
+        "hps_front_plan_destroy": [P],
+        "hps_front_init": [I32, I32, I32, I32, I32, I32, P, P],
+        "hps_front_block_add": [I32, P, I32, P, P, P],
+        "hps_front_segments": [I32, P, I32, P, P, I32, P],
+        "hps_front_factor": [P, I32, P, P, P, P, P],
+        "hps_front_solve": [P, I32, P, P, P, P, I32, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    lib.hps_front_dinv_elems.argtypes = [P]
+    lib.hps_front_dinv_elems.restype = SZ
     lib.hps_status_string.argtypes = [C.c_int]
     lib.hps_status_string.restype = C.c_char_p
     _lib = lib

@@ -86,9 +86,12 @@ struct ProfScope {
 };
 
 // lu.hip: one kernel launch per schedule record (records of 8 ints, see common.h)
+// pivot_end >= 0: rows at positions >= pivot_end are never pivots (partial factorization of
+// an interface front; the schedule then stops after the pivot columns and its trailing
+// update); -1: every row may be a pivot.
 template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
-                     hipStream_t st, Profiler* prof);
+                     hipStream_t st, Profiler* prof, int pivot_end = -1);
 // Flops of one solve for the profiler (set by the caller when profiling is on): algorithmic
 // n_i^2 (n_b + 1) per active box and sweep, and what the kernels execute per sweep.
 struct SolveFlops {

@@ -76,7 +76,7 @@ struct LuSmem {
   T wval[2][kLuWaves];
   int wslot[2][kLuWaves];
   int pphys[64];           // physical row of the panel's k-th pivot
-  int cnt[16 * kLuWaves];
+  int cnt[24 * kLuWaves];  // per (row slot r < 24, wave): rows that stay candidates
 };
 
 template <typename T> struct Store4;
@@ -106,23 +106,26 @@ template <> struct Store4<double> {
 //   (d) write back, (e) extend M and Nn with the chunk's pivots (block triangular
 //       inverses)
 // Candidates never change their relative order, so "lowest position" is the lowest
-// starting slot.  At the end the pivots take positions j0.. in order and the other
+// starting slot.  Rows at positions >= pivot_end are eliminated like the others but never
+// become pivots (a partial factorization whose trailing block is a Schur complement).  At the end the pivots take positions j0.. in order and the other
 // rows follow in their previous order; M and Nn go to dinv_panel as Linv / Uinv.
 template <typename T, int ROWS, int CW, int W>
-__device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T* A, int* perm, int j0, LuSmem<T, CW>& sm,
-                                                   int& info, T* dinv_panel) {
+__device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T* A, int* perm, int j0, int pivot_end,
+                                                               LuSmem<T, CW>& sm, int& info, T* dinv_panel) {
   static_assert(W % CW == 0 && CW % 4 == 0, "chunks tile the panel");
   constexpr int LB = CW < 16 ? CW : 16;  // L values loaded per step of (b)
   const int N = g.n_pad, lda = N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nrem = N - j0;
   int phys[ROWS];
-  int pk[ROWS];  // -1: candidate, >= 0: index of the pivot it became, -2: no row
+  // -1: candidate, >= 0: index of the pivot it became, -2: no row, -3: a row at or past
+  // pivot_end (updated like a candidate, never chosen as a pivot)
+  int pk[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; r++) {
     const int s = tid + kLuThreads * r;
     phys[r] = s < nrem ? perm[j0 + s] : 0;
-    pk[r] = s < nrem ? -1 : -2;
+    pk[r] = s < nrem ? (j0 + s < pivot_end ? -1 : -3) : -2;
   }
   for (int h = 0; h < W / CW; h++) {
     const int cb = j0 + h * CW;
@@ -156,7 +159,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
       // (b)
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        if (pk[r] != -1) continue;
+        if (pk[r] != -1 && pk[r] != -3) continue;
         const T* row = A + (size_t)phys[r] * lda + j0;
         for (int k0 = 0; k0 < npv; k0 += LB) {
           T lb[LB];
@@ -226,7 +229,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
       const T inv = pv != T(0) ? T(1) / pv : T(0);
 #pragma unroll
       for (int r = 0; r < ROWS; r++) {
-        if (pk[r] == -1) {
+        if (pk[r] == -1 || pk[r] == -3) {
           const T l = v[r][c] * inv;
           v[r][c] = l;
 #pragma unroll
@@ -237,7 +240,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
     // (d) candidates and this chunk's pivots; earlier pivots got their U rows in (a)
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
-      if (pk[r] == -1 || pk[r] >= npv) {
+      if (pk[r] == -1 || pk[r] == -3 || pk[r] >= npv) {
         T* row = A + (size_t)phys[r] * lda + cb;
 #pragma unroll
         for (int c = 0; c < CW; c += 4) Store4<T>::store(row + c, v[r] + c);
@@ -307,7 +310,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
   int pre[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; r++) {
-    const unsigned long long mask = __ballot(pk[r] == -1);
+    const unsigned long long mask = __ballot(pk[r] == -1 || pk[r] == -3);
     pre[r] = __popcll(mask & lt);
     if (lane == 0) sm.cnt[r * kLuWaves + wave] = __popcll(mask);
   }
@@ -322,7 +325,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
       tot += cw;
       if (w < wave) before += cw;
     }
-    if (pk[r] == -1) perm[base + before + pre[r]] = phys[r];
+    if (pk[r] == -1 || pk[r] == -3) perm[base + before + pre[r]] = phys[r];
     base += tot;
   }
   if (tid < W) perm[j0 + tid] = sm.pphys[tid];
@@ -340,8 +343,14 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
 // ---------------------------------------------------------------------------
 __device__ inline bool map_box_tile(int nbox, int ntile, int& box, int& tile) {
   // consecutive workgroup ids go round-robin to the 8 XCDs: give all tiles of a
-  // box ids on one XCD so they share its L2
+  // box ids on one XCD so they share its L2.  Fewer than 8 boxes (the large interface
+  // fronts): a box's tiles spread over every XCD instead.
   const int id = blockIdx.x;
+  if (nbox < 8) {
+    box = id / ntile;
+    tile = id - box * ntile;
+    return box < nbox;
+  }
   const int xcd = id & 7, slot = id >> 3;
   const int lb = slot / ntile;
   tile = slot - lb * ntile;
@@ -358,7 +367,7 @@ __global__ void lu_init_kernel(int N, int* perm_all, int* info, int nbox) {
 
 template <typename T, int ROWS, int CW, int W>
 __global__ __launch_bounds__(kLuThreads, 2) void lu_panel_kernel(Geom g, T* A_all, int* perm_all, T* dinv_all,
-                                                                  int* info_all, int nbox, int c0) {
+                                                                  int* info_all, int nbox, int c0, int pivot_end) {
   __shared__ LuSmem<T, CW> sm;
   const int box = blockIdx.x;
   if (box >= nbox) return;
@@ -367,7 +376,7 @@ __global__ __launch_bounds__(kLuThreads, 2) void lu_panel_kernel(Geom g, T* A_al
   int* perm = perm_all + (size_t)box * N;
   T* dp = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(c0 / kPanel) * 2 * 64 * 64;
   int info = 0;
-  lu_panel<T, ROWS, CW, W>(g, A, perm, c0, sm, info, dp);
+  lu_panel<T, ROWS, CW, W>(g, A, perm, c0, pivot_end, sm, info, dp);
   if (threadIdx.x == 0 && info != 0 && info_all[box] == 0) info_all[box] = info;
 }
 
@@ -728,7 +737,7 @@ __global__ __launch_bounds__(256, OCC) void trsm_sweep_kernel(Geom g, const T* F
 // ---------------------------------------------------------------------------
 // host-side sequencing
 // ---------------------------------------------------------------------------
-static int grid_for(int nbox, int ntile) { return 8 * ((nbox + 7) / 8) * ntile; }
+static int grid_for(int nbox, int ntile) { return (nbox < 8 ? nbox : 8 * ((nbox + 7) / 8)) * ntile; }
 
 // algorithmic flops of one schedule record over nbox boxes (for the profiler)
 static double gemm_flops(const int* op, int nbox) {
@@ -750,20 +759,20 @@ static hipError_t launch_gemm(const Geom& g, const T* F, const int* perm, T* X, 
 
 template <typename T, int ROWS>
 static hipError_t launch_panel(const Geom& g, T* A, int* perm, T* dinv, int* info, int nbox, int c0, int w,
-                               hipStream_t st) {
+                               int pivot_end, hipStream_t st) {
   constexpr int CW = PanelChunk<T, ROWS>::CW;
   if (w == 64)
     hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, CW, 64>), dim3(nbox), dim3(kLuThreads), 0, st, g, A, perm, dinv,
-                       info, nbox, c0);
+                       info, nbox, c0, pivot_end);
   else
     hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, (CW < 32 ? CW : 32), 32>), dim3(nbox), dim3(kLuThreads), 0, st, g,
-                       A, perm, dinv, info, nbox, c0);
+                       A, perm, dinv, info, nbox, c0, pivot_end);
   return hipGetLastError();
 }
 
 template <typename T, int ROWS>
 static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
-                         hipStream_t st, Profiler* prof) {
+                         hipStream_t st, Profiler* prof, int pivot_end) {
   const int N = g.n_pad;
   hipLaunchKernelGGL(lu_init_kernel, dim3((N + 255) / 256, nbox), dim3(256), 0, st, N, perm, info, nbox);
   hipError_t e = hipGetLastError();
@@ -771,7 +780,7 @@ static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* 
     const int* op = ops.data() + q;
     if (op[0] == kOpPanel) {
       ProfScope ps(prof, Profiler::kLuPanel, 0.0, st);
-      e = launch_panel<T, ROWS>(g, A, perm, dinv, info, nbox, op[1], op[2], st);
+      e = launch_panel<T, ROWS>(g, A, perm, dinv, info, nbox, op[1], op[2], pivot_end, st);
     } else if (op[0] == kOpRows) {
       const int r0 = op[1], r1 = op[2], cA = op[3], cB = op[4], ntn = (cB - cA + 63) / 64;
       for (int s = r0; s < r1 && e == hipSuccess; s += kPanel) {
@@ -791,14 +800,20 @@ static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* 
 
 template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
-                     hipStream_t st, Profiler* prof) {
+                     hipStream_t st, Profiler* prof, int pivot_end) {
   const int rows = (g.n_pad + kLuThreads - 1) / kLuThreads;
-  if (rows <= 1) return run_lu<T, 1>(g, ops, A, perm, dinv, info, nbox, st, prof);
-  if (rows <= 2) return run_lu<T, 2>(g, ops, A, perm, dinv, info, nbox, st, prof);
-  if (rows <= 4) return run_lu<T, 4>(g, ops, A, perm, dinv, info, nbox, st, prof);
-  if (rows <= 6) return run_lu<T, 6>(g, ops, A, perm, dinv, info, nbox, st, prof);
-  if (rows <= 8) return run_lu<T, 8>(g, ops, A, perm, dinv, info, nbox, st, prof);
-  if (rows <= 12) return run_lu<T, 12>(g, ops, A, perm, dinv, info, nbox, st, prof);
+  const int pe = pivot_end < 0 ? g.n_pad : pivot_end;
+  if (rows <= 1) return run_lu<T, 1>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
+  if (rows <= 2) return run_lu<T, 2>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
+  if (rows <= 4) return run_lu<T, 4>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
+  if (rows <= 6) return run_lu<T, 6>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
+  if (rows <= 8) return run_lu<T, 8>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
+  if (rows <= 12) return run_lu<T, 12>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
+  if constexpr (sizeof(T) == 8) {  // interface fronts (FP64 only) up to 12288 rows
+    if (rows <= 16) return run_lu<T, 16>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
+    if (rows <= 20) return run_lu<T, 20>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
+    if (rows <= 24) return run_lu<T, 24>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
+  }
   return hipErrorInvalidValue;
 }
 
@@ -868,9 +883,9 @@ hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, 
   return e;
 }
 template hipError_t getrf_run<float>(const Geom&, const std::vector<int>&, float*, int*, float*, int*, int, hipStream_t,
-                                     Profiler*);
+                                     Profiler*, int);
 template hipError_t getrf_run<double>(const Geom&, const std::vector<int>&, double*, int*, double*, int*, int,
-                                      hipStream_t, Profiler*);
+                                      hipStream_t, Profiler*, int);
 template hipError_t getrs_run<float>(const Geom&, const float*,
                                      const int*, const float*, const float*, float*, int, const int*, hipStream_t,
                                      Profiler*, double*, int, int, int, const int*, int, const float*,

@@ -45,6 +45,7 @@ import torch
 
 from . import interface as itf
 from .leaf import LeafPlan, hps_interface_reduce
+from .nested import NestedDissection
 
 
 def _box_origins(nboxes, lo, h) -> np.ndarray:
@@ -114,7 +115,7 @@ class TwoLevelSolver:
     def __init__(self, nboxes, lo, hi, p: int, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
                  ir_tol: Optional[float] = None, chunk: Optional[int] = None, keep: Optional[bool] = None, device="cuda",
                  refine: Optional[int] = None, refine_steps: int = 2, tuning: Optional[dict] = None,
-                 hbm_budget: Optional[float] = None, interior_tol: float = 1e-12):
+                 hbm_budget: Optional[float] = None, interior_tol: float = 1e-12, interface: str = "auto"):
         self.nboxes = tuple(int(v) for v in nboxes)
         self.nbox = int(np.prod(self.nboxes))
         self.lo = tuple(float(v) for v in lo)
@@ -131,6 +132,9 @@ class TwoLevelSolver:
         self.refine_steps = int(refine_steps)
         self.interior_tol = float(interior_tol)
         self.precision = precision
+        if interface not in ("auto", "gpu", "host"):
+            raise ValueError("interface must be 'auto', 'gpu' or 'host'")
+        self.interface = interface
         self._plan64 = None
         self._plan_memory(chunk, keep, hbm_budget)
         self.origins = torch.tensor(_box_origins(self.nboxes, self.lo, self.h), device=self.device)
@@ -267,8 +271,24 @@ class TwoLevelSolver:
         fp64_redo(self._fp64_plan(), ids, b, f, g_dir, self.slot_map, T_vals, g_loads, berr, self.chunk,
                   self.device, keep_x)
 
+    # ---- interface factorization (Alg. 1 step 3) ---------------------------------
+    def interface_solver(self, br: BuildResult):
+        """Factor the interface matrix: on the GPU by nested dissection with dense fronts
+        (NestedDissection) when interface is 'gpu', or 'auto' and its fronts fit the free
+        device memory and the kernels' size limit; else on the host (InterfaceSolver)."""
+        use_gpu = self.interface == "gpu"
+        if self.interface == "auto" and self.device.type == "cuda" and self.layout.nface > 0:
+            free = torch.cuda.mem_get_info(self.device)[0]
+            use_gpu = (NestedDissection.supported(self.layout) and
+                       NestedDissection.estimate_bytes(self.layout) < 0.8 * free)
+        if use_gpu:
+            nd = NestedDissection(self.layout, self.device)
+            nd.factor(br.T_vals)
+            return nd
+        return itf.InterfaceSolver(self.layout, br.T_vals.cpu().numpy())
+
     # ---- solve stage (Alg. 2) ---------------------------------------------------
-    def solve(self, br: BuildResult, g_dir: torch.Tensor, isolver: Optional[itf.InterfaceSolver] = None,
+    def solve(self, br: BuildResult, g_dir: torch.Tensor, isolver=None,
               b: Optional[torch.Tensor] = None, f: Optional[torch.Tensor] = None):
         """Return (u_face, u_b [nbox, n_b], u_i [nbox, n_i], interface solver).
 
@@ -277,7 +297,9 @@ class TwoLevelSolver:
         which needs b and f again.
         """
         if isolver is None:
-            isolver = itf.InterfaceSolver(self.layout, br.T_vals.cpu().numpy())
+            isolver = self.interface_solver(br)
+        if isinstance(isolver, NestedDissection):
+            return self._solve_gpu(br, g_dir, isolver, b, f)
         rhs = itf.interface_rhs(self.layout, br.g_loads.cpu().numpy())
         u_face = isolver.solve(rhs)
         gd = g_dir.cpu().numpy()
@@ -304,6 +326,31 @@ class TwoLevelSolver:
             raise ValueError("recompute mode needs b (and f) again")
         ui, _ = self._interiors(br, ub_d, b, f, want_flux=False)
         return u_face, ub, ui, isolver
+
+    def _solve_gpu(self, br: BuildResult, g_dir: torch.Tensor, nd: NestedDissection, b, f):
+        """The solve stage with the interface factorization on the GPU: every step stays in
+        HBM (loads, interface solve, face values, refinement, interiors)."""
+        u = nd.solve(br.g_loads)
+        ub_d = nd.face_values(u, g_dir)
+        self.refine_history = []
+        if self.refine > 0 and self.layout.nface > 0:
+            if b is None:
+                raise ValueError("the outer refinement needs b (and f) again")
+            for _ in range(self.refine):
+                _, flux = self._interiors(br, ub_d, b, f, want_flux=True)
+                du = nd.solve(flux)  # T du = rhs(flux); the correction is -du
+                self.refine_history.append(float(torch.linalg.norm(du) / max(float(torch.linalg.norm(u)), 1e-300)))
+                nd.axpy(u, du, -1)
+                ub_d = nd.face_values(u, g_dir)
+            ui, _ = self._interiors(br, ub_d, b, f, want_flux=False)
+        elif br.X is not None:
+            ui = torch.empty(self.nbox, self.info.n_i, dtype=torch.float64, device=self.device)
+            self.plan.hps_leaf_reconstruct(self.nbox, br.X, ub_d, ui)
+        else:
+            if b is None:
+                raise ValueError("recompute mode needs b (and f) again")
+            ui, _ = self._interiors(br, ub_d, b, f, want_flux=False)
+        return u.cpu().numpy(), ub_d.cpu().numpy(), ui, nd
 
     def _interiors(self, br: BuildResult, ub_d: torch.Tensor, b, f, want_flux: bool):
         """u_i = A_ii^{-1} (f_i - A_ib u_b) of every box from its factors, refined in FP64

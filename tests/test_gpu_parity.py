@@ -145,10 +145,10 @@ def test_leaf_p16_sampled_fp32_ir(gpu):
     _check_leaf(prob, [0, 2047], "fp32_ir", IR_TOL, f_on=False, guard=GUARD)
 
 
-def _pipeline(prob, precision, tol):
+def _pipeline(prob, precision, tol, interface="auto"):
     from paper_2503_04033_amd.solver import TwoLevelSolver
-    say(f"pipeline {prob.name} p={prob.p} {precision}")
-    s = TwoLevelSolver.for_problem(prob, precision=precision)
+    say(f"pipeline {prob.name} p={prob.p} {precision} interface={interface}")
+    s = TwoLevelSolver.for_problem(prob, precision=precision, interface=interface)
     out = s.solve_problem(prob)
     torch.cuda.synchronize()
     ref = oi.solve(prob)
@@ -159,20 +159,22 @@ def _pipeline(prob, precision, tol):
     return out, ref
 
 
+@pytest.mark.parametrize("interface", ["gpu", "host"])
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32_ir", IR_TOL)])
-def test_pipeline_config1(gpu, precision, tol):
+def test_pipeline_config1(gpu, precision, tol, interface):
     prob = W.config1()
-    out, ref = _pipeline(prob, precision, tol)
+    out, ref = _pipeline(prob, precision, tol, interface)
     exact = prob.u_exact(out["xi"]).reshape(out["u_i"].shape)
     err = rel(out["u_i"].cpu().numpy(), exact)
     say(f"  vs exact {err:.2e}")
     assert err < 2e-6  # p = 6 discretisation error of the manufactured plane wave
 
 
+@pytest.mark.parametrize("interface", ["gpu", "host"])
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32_ir", IR_TOL)])
-def test_pipeline_ragged_grid(gpu, precision, tol):
+def test_pipeline_ragged_grid(gpu, precision, tol, interface):
     prob = W.multi_bump((3, 2, 2), 8, 9.0, 21, gaussian_source=True, name="grid3x2x2_p8")
-    _pipeline(prob, precision, tol)
+    _pipeline(prob, precision, tol, interface)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32_ir", IR_TOL)])
@@ -335,7 +337,7 @@ def test_pipeline_4cubed_p16(gpu, precision):
     from paper_2503_04033_amd.solver import TwoLevelSolver
     prob = W.multi_bump((4, 4, 4), 16, 40.0, 3, name="grid4_p16")
     say(f"pipeline {prob.name} {precision}")
-    s = TwoLevelSolver.for_problem(prob, precision=precision, chunk=32)
+    s = TwoLevelSolver.for_problem(prob, precision=precision, chunk=32, interface="gpu")
     out = s.solve_problem(prob)
     torch.cuda.synchronize()
     ref = _oracle_solution(prob)

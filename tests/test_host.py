@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_symbols():
     src = open(os.path.join(ROOT, "include", "hps_leaf.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:hps_status|const char\*)\s+(hps_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:hps_status|const char\*|size_t)\s+(hps_\w+)\s*\(", src, re.M)))
 
 
 def test_header_and_binding_agree():
