@@ -20,6 +20,8 @@ Modules
              solved directly (the pin for the static condensation).
   adjoint    gradient of a data misfit with respect to b through transposed
              solves of the factorization in eq. factor2.
+  parabolic  Crank-Nicolson time stepping (Sec. 4.4) of u_t = nu Lap u +
+             kappa^2 b u on the global collocation system of brute.
 
 Parity status: every function here is pinned by tests/test_oracle_*.py
 against closed forms, polynomial exactness, invariants, manufactured

@@ -279,3 +279,76 @@ def helmholtz_greens(nboxes=(2, 2, 2), p=8, kappa=16.0, name="greens") -> Proble
 
     return Problem(name=name, nboxes=tuple(nboxes), p=p, kappa=kappa, b=_one, f=_zero, g=u,
                    lo=(-1.1, 1.0, 1.2), hi=(0.1, 2.0, 2.2), u_exact=u)
+
+
+@dataclass
+class ParabolicProblem:
+    """u_t = nu Lap u + kappa^2 b(x) u on a box grid, u = 0 on the boundary, u(x, 0) = u0(x)
+    (paper Sec. 4.4 steps a parabolic problem with Crank-Nicolson; its example also has a
+    convection term, which the operator class here, -Lap u - kappa^2 b u, does not cover:
+    this family keeps diffusion and adds a variable reaction term instead).
+
+    u_exact(x, t), when given, is the exact solution of the continuous problem.
+    """
+
+    name: str
+    nboxes: Tuple[int, int, int]
+    p: int
+    nu: float
+    dt: float
+    kappa: float
+    b: Field
+    u0: Field
+    lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    hi: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    u_exact: Optional[Callable[[Array, float], Array]] = None
+    params: dict = field(default_factory=dict)
+
+    @property
+    def nbox(self) -> int:
+        return int(self.nboxes[0] * self.nboxes[1] * self.nboxes[2])
+
+    @property
+    def h(self) -> Tuple[float, float, float]:
+        return tuple((self.hi[a] - self.lo[a]) / self.nboxes[a] for a in range(3))
+
+    def box_origins(self) -> Array:
+        n1, n2, n3 = self.nboxes
+        t = np.arange(n1 * n2 * n3)
+        bx, rem = t % n1, t // n1
+        by, bz = rem % n2, rem // n2
+        h = self.h
+        return np.stack([self.lo[0] + bx * h[0], self.lo[1] + by * h[1], self.lo[2] + bz * h[2]], axis=1)
+
+
+def heat_sine(nboxes=(2, 2, 2), p=10, nu=0.1, dt=0.05, name="heat_sine") -> ParabolicProblem:
+    """u_t = nu Lap u on [0,1]^3 with u = exp(-3 pi^2 nu t) sin(pi x) sin(pi y) sin(pi z)
+    (zero on the boundary, exact).  No random draws."""
+
+    def s(x: Array) -> Array:
+        return np.sin(np.pi * x[..., 0]) * np.sin(np.pi * x[..., 1]) * np.sin(np.pi * x[..., 2])
+
+    def u_exact(x: Array, t: float) -> Array:
+        return np.exp(-3.0 * np.pi ** 2 * nu * t) * s(x)
+
+    return ParabolicProblem(name=name, nboxes=tuple(nboxes), p=p, nu=nu, dt=dt, kappa=0.0, b=_one, u0=s,
+                            u_exact=u_exact)
+
+
+def diffusion_reaction(nboxes=(2, 2, 2), p=8, nu=0.05, dt=0.02, kappa=1.0, seed=9, nbump=3, amp=0.5,
+                       width2=0.02, name="diffusion_reaction") -> ParabolicProblem:
+    """On [-0.5, 0.5]^3: reaction coefficient b = 1 + amp * (seeded Gaussian bumps, width 0.1)
+    and a Gaussian initial blob below the centre, u0 = exp(-(x^2 + (y + 0.3)^2 + z^2)/width2)
+    (the paper's initial condition has width2 = 0.002 and, as printed, a positive exponent;
+    the decaying blob is meant).  u = 0 on the boundary.
+
+    Draws: centers = uniform(-0.5, 0.5, size=(nbump, 3))."""
+    rng = np.random.default_rng(seed)
+    centers = rng.uniform(-0.5, 0.5, size=(nbump, 3))
+
+    def u0(x: Array) -> Array:
+        return np.exp(-(x[..., 0] ** 2 + (x[..., 1] + 0.3) ** 2 + x[..., 2] ** 2) / width2)
+
+    return ParabolicProblem(name=name, nboxes=tuple(nboxes), p=p, nu=nu, dt=dt, kappa=kappa,
+                            b=_bumps(centers, amp, BUMP_DENOM), u0=u0, lo=(-0.5, -0.5, -0.5), hi=(0.5, 0.5, 0.5),
+                            params={"centers": centers, "seed": seed})
