@@ -189,6 +189,15 @@ hps_status hps_leaf_interior_solve(hps_plan plan, int32_t nbox, const void* LU, 
                                   const double* u_b, double* u_i, int32_t steps, double* berr, void* ws,
                                   hipStream_t stream);
 
+/* Crank-Nicolson right-hand side (Sec. 4.4: the previous step is the body load of the
+ * interior solves, through I + (dt/2) A): f = c u_i - (A_ii u_i + A_ib u_b) for every box,
+ * with the plan's operator A = -Lap - kappa^2 diag(b) (eq. Aentries, interior rows).  For
+ * u_t = nu Lap u + k^2 b' u the plan is built with kappa = 1 and b = k^2 b'/nu - 2/(nu dt),
+ * and c = 4/(nu dt); then the step is A u^{n+1} = f.  b, u_i, f: [nbox][n_i]; u_b
+ * [nbox][n_b] (the face values of u^n, Dirichlet data on boundary faces); FP64. */
+hps_status hps_leaf_cn_rhs(hps_plan plan, int32_t nbox, const double* b, double c, const double* u_i,
+                           const double* u_b, double* f, hipStream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc): hps_leaf_interior_solve
  * without the ws argument.  Its scratch (8 nbox (n_i + 3) bytes) lives in a

@@ -18,6 +18,7 @@ EXPORTS = (
     "hps_leaf_interior_solve", "hps_leaf_flux", "hps_plan_set_tuning", "hps_plan_get_tuning",
     "hps_leaf_interior_solve_noalloc", "hps_front_plan_create", "hps_front_plan_destroy", "hps_front_dinv_elems",
     "hps_front_init", "hps_front_block_add", "hps_front_segments", "hps_front_factor", "hps_front_solve",
+    "hps_leaf_cn_rhs",
 )
 
 # HPS_NOALLOC_SCRATCH_BYTES: the fixed scratch of hps_leaf_interior_solve_noalloc
@@ -83,6 +84,7 @@ def load() -> C.CDLL:
         "hps_plan_profile_read": [P, C.POINTER(Profile)],
         "hps_plan_set_tuning": [P, I32, I32],
         "hps_plan_get_tuning": [P, I32, C.POINTER(C.c_int32)],
+        "hps_leaf_cn_rhs": [P, I32, P, D, P, P, P, P],
         "hps_front_plan_create": [C.POINTER(P), I32, I32],
         "hps_front_plan_destroy": [P],
         "hps_front_init": [I32, I32, I32, I32, I32, I32, P, P],

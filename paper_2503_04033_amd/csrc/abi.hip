@@ -544,6 +544,14 @@ hps_status hps_leaf_interior_solve_noalloc(hps_plan pl, int32_t nbox, const void
                         static_cast<double*>(pl->scratch), st);
 }
 
+hps_status hps_leaf_cn_rhs(hps_plan pl, int32_t nbox, const double* b, double c, const double* u_i,
+                          const double* u_b, double* f, hipStream_t st) {
+  if (bad_plan(pl) || nbox < 0 || nbox > 65535 || !std::isfinite(c)) return HPS_EINVAL;
+  if (nbox == 0) return HPS_OK;
+  if (!b || !u_i || !u_b || !f) return HPS_EINVAL;
+  return dev(hps::launch_box_residual(pl->g, nbox, b, nullptr, u_b, u_i, f, nullptr, nullptr, st, c));
+}
+
 hps_status hps_leaf_flux(hps_plan pl, int32_t nbox, const double* u_i, const double* u_b, double* flux,
                          hipStream_t st) {
   if (bad_plan(pl) || nbox < 0 || nbox > 65535 || (nbox > 0 && (!u_i || !u_b || !flux))) return HPS_EINVAL;

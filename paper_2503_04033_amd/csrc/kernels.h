@@ -148,8 +148,10 @@ hipError_t launch_getrs_t(const Geom& g, int nbox, const double* LU, const int* 
 hipError_t launch_adjoint_yb(const Geom& g, int nbox, const double* z, double* yb, hipStream_t st);
 hipError_t launch_compact(const Geom& g, int nbox, const double* in, double* out, hipStream_t st);
 // r = f - A_ib u_b - A_ii u per box (u null: u = 0); rmax/umax optional per-box max|r|, max|u|
+// r = f - A_ii u - A_ib u_b per box (f null: fscale * u instead of f)
 hipError_t launch_box_residual(const Geom& g, int nbox, const double* b, const double* f, const double* ub,
-                               const double* u, double* r, double* rmax, double* umax, hipStream_t st);
+                               const double* u, double* r, double* rmax, double* umax, hipStream_t st,
+                               double fscale = 0.0);
 hipError_t launch_interior_berr(int nbox, const double* anorm, const double* r0max, const double* rmax,
                                 const double* umax, double* berr, hipStream_t st);
 template <typename T>

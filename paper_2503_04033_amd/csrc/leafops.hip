@@ -1102,10 +1102,11 @@ __device__ inline double block_max_256(double v, double* red) {
   return m;
 }
 
-// rmax/umax (optional, [nbox]): max|r| and max|u| of the box; a NaN counts as +inf.
+// rmax/umax (optional, [nbox]): max|r| and max|u| of the box; a NaN counts as +inf.  With
+// f null the load is fscale * u (the Crank-Nicolson right-hand side c u^n - L u^n).
 __global__ __launch_bounds__(256) void box_residual_kernel(Geom g, int nbox, const double* b, const double* f,
-                                                           const double* ub_all, const double* u_all, double* r_all,
-                                                           double* rmax, double* umax) {
+                                                           double fscale, const double* ub_all, const double* u_all,
+                                                           double* r_all, double* rmax, double* umax) {
   extern __shared__ double us[];  // u [n], then D2 [p][p]
   __shared__ double red[4];
   const int box = blockIdx.x;
@@ -1132,7 +1133,7 @@ __global__ __launch_bounds__(256) void box_residual_kernel(Geom g, int nbox, con
       ly += d2[(jj + 1) * p + l + 1] * us[node + m * (l - jj)];
       lz += d2[(kk + 1) * p + l + 1] * us[node + mm * (l - kk)];
     }
-    const double fv = f ? f[(size_t)box * n + node] : 0.0;
+    const double fv = f ? f[(size_t)box * n + node] : (fscale != 0.0 ? fscale * us[node] : 0.0);
     const double r = fv + g.s2[0] * lx + g.s2[1] * ly + g.s2[2] * lz + g.kappa2 * b[(size_t)box * n + node] * us[node];
     r_all[(size_t)box * n + node] = r;
     const double a = fabs(r);
@@ -1223,9 +1224,11 @@ __global__ __launch_bounds__(256) void getrs_vec_kernel(Geom g, int nbox, const 
 }
 
 hipError_t launch_box_residual(const Geom& g, int nbox, const double* b, const double* f, const double* ub,
-                               const double* u, double* r, double* rmax, double* umax, hipStream_t st) {
+                               const double* u, double* r, double* rmax, double* umax, hipStream_t st,
+                               double fscale) {
   const size_t shm = sizeof(double) * ((size_t)g.n + (size_t)g.p * g.p);
-  hipLaunchKernelGGL(box_residual_kernel, dim3(nbox), dim3(256), shm, st, g, nbox, b, f, ub, u, r, rmax, umax);
+  hipLaunchKernelGGL(box_residual_kernel, dim3(nbox), dim3(256), shm, st, g, nbox, b, f, fscale, ub, u, r, rmax,
+                     umax);
   return hipGetLastError();
 }
 

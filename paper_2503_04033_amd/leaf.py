@@ -201,6 +201,13 @@ class LeafPlan:
             *self._interior_args(nbox, LU, perm, dinv, b, anorm, f, u_b, u_i, berr), int(steps),
             _ptr(berr, torch.float64, nbox, "berr"), _stream()), "hps_leaf_interior_solve_noalloc")
 
+    def hps_leaf_cn_rhs(self, nbox: int, b, c: float, u_i, u_b, f):
+        i = self.info
+        check(self.lib.hps_leaf_cn_rhs(self.handle, nbox, _ptr(b, torch.float64, nbox * i.n_i, "b"), float(c),
+                                       _ptr(u_i, torch.float64, nbox * i.n_i, "u_i"),
+                                       _ptr(u_b, torch.float64, nbox * i.n_b, "u_b"),
+                                       _ptr(f, torch.float64, nbox * i.n_i, "f"), _stream()), "hps_leaf_cn_rhs")
+
     def hps_leaf_flux(self, nbox: int, u_i, u_b, flux):
         i = self.info
         check(self.lib.hps_leaf_flux(self.handle, nbox, _ptr(u_i, torch.float64, nbox * i.n_i, "u_i"),

@@ -355,9 +355,12 @@ class NestedDissection:
         self.factored = True
 
     # ---- solve -------------------------------------------------------------------------
-    def solve(self, box_vectors: torch.Tensor) -> torch.Tensor:
-        """u_F with T_FF u_F = sum over the two boxes of each face of box_vectors [nbox, n_b]
-        (the lifted loads, or any per-box face vectors).  Returns u_F [nface * m^2] (device)."""
+    def solve(self, box_vectors: torch.Tensor, sign: int = 1) -> torch.Tensor:
+        """u_F with T_FF u_F = sign * (sum over the two boxes of each face of box_vectors
+        [nbox, n_b]) (the lifted loads, or any per-box face vectors; sign +1 or -1).
+        Returns u_F [nface * m^2] (device)."""
+        if sign not in (1, -1):
+            raise ValueError("sign must be +1 or -1")
         if not self.factored:
             raise RuntimeError("factor() first")
         lib, st, mm = self.lib, _stream(), self.mm
@@ -372,7 +375,7 @@ class NestedDissection:
             for side in (0, 1):
                 u_leaf, u_int = self.up_tasks[gi][side]
                 if u_leaf.shape[0]:
-                    check(lib.hps_front_segments(u_leaf.shape[0], u_leaf.data_ptr(), mm, Vp, Bp, 1, st),
+                    check(lib.hps_front_segments(u_leaf.shape[0], u_leaf.data_ptr(), mm, Vp, Bp, sign, st),
                           "hps_front_segments")
                 if u_int.shape[0]:
                     check(lib.hps_front_segments(u_int.shape[0], u_int.data_ptr(), mm, Vp, Vp, 1, st),

@@ -115,7 +115,8 @@ class TwoLevelSolver:
     def __init__(self, nboxes, lo, hi, p: int, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
                  ir_tol: Optional[float] = None, chunk: Optional[int] = None, keep: Optional[bool] = None, device="cuda",
                  refine: Optional[int] = None, refine_steps: int = 2, tuning: Optional[dict] = None,
-                 hbm_budget: Optional[float] = None, interior_tol: float = 1e-12, interface: str = "auto"):
+                 hbm_budget: Optional[float] = None, interior_tol: float = 1e-12, interface: str = "auto",
+                 keep_what: Optional[str] = None):
         self.nboxes = tuple(int(v) for v in nboxes)
         self.nbox = int(np.prod(self.nboxes))
         self.lo = tuple(float(v) for v in lo)
@@ -135,6 +136,9 @@ class TwoLevelSolver:
         if interface not in ("auto", "gpu", "host"):
             raise ValueError("interface must be 'auto', 'gpu' or 'host'")
         self.interface = interface
+        if keep_what not in (None, "X", "factors"):
+            raise ValueError("keep_what must be None, 'X' or 'factors'")
+        self.keep_what = keep_what or ("factors" if self.refine > 0 else "X")
         self._plan64 = None
         self._plan_memory(chunk, keep, hbm_budget)
         self.origins = torch.tensor(_box_origins(self.nboxes, self.lo, self.h), device=self.device)
@@ -156,7 +160,7 @@ class TwoLevelSolver:
         mm = i.m * i.m
         # interface matrix, loads and per-box scalars, and the host-facing copies made on the device
         resident = 8 * (self.layout.nslot_total * mm * mm + 1) + 8 * self.nbox * (3 * i.n_b + 4)
-        per_box_keep = factor_bytes_per_box(i) if self.refine > 0 else i.x_bytes
+        per_box_keep = factor_bytes_per_box(i) if self.keep_what == "factors" else i.x_bytes
         keep_total = per_box_keep * self.nbox
         per_chunk_box = chunk_bytes_per_box(i)
         fits_keep = resident + keep_total + per_chunk_box <= self.hbm_budget
@@ -177,8 +181,8 @@ class TwoLevelSolver:
             self.chunk = int(chunk)
         else:
             self.chunk = min(self.nbox, fit, self.MAX_CHUNK)
-        self.keep_X = self.keep and self.refine == 0
-        self.keep_factors = self.keep and self.refine > 0
+        self.keep_X = self.keep and self.keep_what == "X"
+        self.keep_factors = self.keep and self.keep_what == "factors"
 
     # ---- problem data at the collocation nodes --------------------------------
     def nodes(self):
@@ -328,9 +332,16 @@ class TwoLevelSolver:
         return u_face, ub, ui, isolver
 
     def _solve_gpu(self, br: BuildResult, g_dir: torch.Tensor, nd: NestedDissection, b, f):
-        """The solve stage with the interface factorization on the GPU: every step stays in
-        HBM (loads, interface solve, face values, refinement, interiors)."""
-        u = nd.solve(br.g_loads)
+        u, ub_d, ui = self.solve_device(br, g_dir, nd, b, f)
+        return u.cpu().numpy(), ub_d.cpu().numpy(), ui, nd
+
+    def solve_device(self, br: BuildResult, g_dir: torch.Tensor, nd: NestedDissection, b, f,
+                     loads: Optional[torch.Tensor] = None, sign: int = 1):
+        """The solve stage with the interface factorization on the GPU; every step stays in
+        HBM (interface solve, face values, refinement, interiors).  The interface load is
+        sign * loads per box ([nbox, n_b]; default the build's lifted loads).  Returns
+        (u_F, u_b [nbox, n_b], u_i [nbox, n_i]) on the device."""
+        u = nd.solve(br.g_loads if loads is None else loads, sign)
         ub_d = nd.face_values(u, g_dir)
         self.refine_history = []
         if self.refine > 0 and self.layout.nface > 0:
@@ -350,7 +361,7 @@ class TwoLevelSolver:
             if b is None:
                 raise ValueError("recompute mode needs b (and f) again")
             ui, _ = self._interiors(br, ub_d, b, f, want_flux=False)
-        return u.cpu().numpy(), ub_d.cpu().numpy(), ui, nd
+        return u, ub_d, ui
 
     def _interiors(self, br: BuildResult, ub_d: torch.Tensor, b, f, want_flux: bool):
         """u_i = A_ii^{-1} (f_i - A_ib u_b) of every box from its factors, refined in FP64
