@@ -288,7 +288,10 @@ hps_status hps_front_factor(hps_front_plan plan, int32_t nfront, double* F, int3
 /* One vector per front, vec [nfront][n] FP64, in place.  mode 0 (upward): vec holds r
  * in unknown order; on return positions [0, n_piv) hold y = L11^{-1} P_r r_P and
  * [n_piv, n) hold r_B - L21 y.  mode 1 (downward): vec holds y (as mode 0 left it) and
- * u_B in [n_piv, n); on return [0, n_piv) holds u_P = U11^{-1}(y - U12 u_B). */
+ * u_B in [n_piv, n); on return [0, n_piv) holds u_P = U11^{-1}(y - U12 u_B).
+ * Modes 2 and 3 do the same for the transposed system (adjoint solves): mode 2 leaves
+ * z = U11^{-T} r_P in [0, n_piv) and r_B - U12^T z; mode 3 takes z and lam_B and leaves
+ * lam_P = P_r^T L11^{-T}(z - L21^T lam_B) in [0, n_piv), in unknown order. */
 hps_status hps_front_solve(hps_front_plan plan, int32_t nfront, const double* F, const int32_t* perm,
                            const double* dinv, double* vec, int32_t mode, hipStream_t stream);
 

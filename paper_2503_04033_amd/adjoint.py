@@ -5,7 +5,8 @@ u = A(b)^{-1} rhs is the two-level solution (eq. factor2).  b enters A only as
 J(u_i):  dJ/db_n = kappa^2 lambda_n u_n  with  A^T lambda = dJ/du  (interior nodes).
 The transpose of eq. factor2, A^{-T} = Atil^{-T} L^{-T} D^{-T} U^{-T}, gives per box
     z = A_ii^{-T} w_i,  y_b = -A_ib^T z     (GPU, hps_leaf_adjoint_solve)
-    lambda_F = T_FF^{-T} sum_boxes y_b      (host sparse LU, transposed)
+    lambda_F = T_FF^{-T} sum_boxes y_b      (transposed interface solve: GPU nested
+                                             dissection, or the host LU)
     lambda_i = A_ii^{-T} (w_i - A_bi^T lambda_b)   (GPU)
     grad = kappa^2 lambda_i * u_i           (GPU, hps_leaf_adjoint_grad)
 
@@ -25,6 +26,7 @@ import torch
 
 from . import interface as itf
 from .leaf import hps_interface_reduce
+from .nested import NestedDissection
 from .solver import TwoLevelSolver, chunk_bytes_per_box, factor_bytes_per_box
 
 
@@ -107,10 +109,15 @@ class AdjointSolve:
         triples = torch.tensor(s.layout.reduce_triples, device=s.device)
         if triples.shape[0]:
             hps_interface_reduce(triples, (i.m * i.m) ** 2, self.T_vals)
-        self.isolver = itf.InterfaceSolver(s.layout, self.T_vals.cpu().numpy())
-        rhs = itf.interface_rhs(s.layout, self.g_loads.cpu().numpy())
-        u_face = self.isolver.solve(rhs)
-        ub = torch.tensor(itf.box_face_values(s.layout, u_face, g_dir.cpu().numpy()), device=s.device)
+        self.isolver = s.factor_interface(self.T_vals)
+        if isinstance(self.isolver, NestedDissection):
+            u_d = self.isolver.solve(self.g_loads)
+            ub = self.isolver.face_values(u_d, g_dir.contiguous())
+            u_face = u_d.cpu().numpy()
+        else:
+            rhs = itf.interface_rhs(s.layout, self.g_loads.cpu().numpy())
+            u_face = self.isolver.solve(rhs)
+            ub = torch.tensor(itf.box_face_values(s.layout, u_face, g_dir.cpu().numpy()), device=s.device)
         ui = torch.empty(nbox, i.n_i, dtype=torch.float64, device=s.device)
         for c0, nb in self._chunks():
             sl = slice(c0, c0 + nb)
@@ -133,9 +140,13 @@ class AdjointSolve:
             sl = slice(c0, c0 + nb)
             A, perm, dinv = self._factors(c0, nb, self.b)
             plan.hps_leaf_adjoint_solve(nb, A, perm, dinv, self.b[sl], w_i[sl], None, z, yb[sl], self.bufs["ws"])
-        y_face = itf.interface_rhs(s.layout, yb.cpu().numpy())
-        lam_face = self.isolver.solve(y_face, trans="T")
-        lam_b = torch.tensor(itf.box_face_values(s.layout, lam_face, np.zeros((nbox, i.n_b))), device=dev)
+        if isinstance(self.isolver, NestedDissection):
+            lam = self.isolver.solve(yb, trans=True)
+            lam_b = self.isolver.face_values(lam, torch.zeros(nbox, i.n_b, dtype=torch.float64, device=dev))
+        else:
+            y_face = itf.interface_rhs(s.layout, yb.cpu().numpy())
+            lam_face = self.isolver.solve(y_face, trans="T")
+            lam_b = torch.tensor(itf.box_face_values(s.layout, lam_face, np.zeros((nbox, i.n_b))), device=dev)
         lam_i = torch.empty(nbox, i.n_i, dtype=torch.float64, device=dev)
         for c0, nb in self._chunks():
             sl = slice(c0, c0 + nb)

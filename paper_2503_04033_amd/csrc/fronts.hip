@@ -67,6 +67,11 @@ __global__ __launch_bounds__(256) void segment_kernel(int ntask, const int64_t* 
 //         positions [0, n_piv) and r_B - L21 y in [n_piv, n).
 //  mode 1 (downward): on entry y in [0, n_piv) (as mode 0 left it) and u_B in [n_piv, n).
 //         Leaves u_P = U11^{-1} (y - U12 u_B) in [0, n_piv), in unknown order.
+// The transposed system (T^T = U^T L^T, for adjoint solves):
+//  mode 2 (upward): on entry r in unknown order.  Leaves z = U11^{-T} r_P in positions
+//         [0, n_piv) and r_B - U12^T z in [n_piv, n).
+//  mode 3 (downward): on entry z in [0, n_piv) and lam_B in [n_piv, n).  Leaves lam_P =
+//         P_r^T L11^{-T} (z - L21^T lam_B) in [0, n_piv), in unknown order.
 __global__ __launch_bounds__(256) void front_solve_kernel(int n, int n_piv, const double* F_all,
                                                           const int* perm_all, const double* dinv_all,
                                                           double* vec_all, int mode) {
@@ -102,7 +107,52 @@ __global__ __launch_bounds__(256) void front_solve_kernel(int n, int n_piv, cons
     }
     __syncthreads();
   };
+  // vs[s + t] = sum_k Inv[k][t] vs[s + k]: the transposed product with a stored inverse
+  auto block_inverse_t = [&](const double* Inv, int s, int w) {
+    if ((int)threadIdx.x < w) {
+      double acc = 0.0;
+      for (int k = 0; k < w; k++) acc += Inv[k * 64 + threadIdx.x] * vs[s + k];
+      tmp[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < w) vs[s + threadIdx.x] = tmp[threadIdx.x];
+    __syncthreads();
+  };
+  // columns [c0, c1) -= sum over positions i in [r0, r0+w) of F[perm[i]][col] vs[i]
+  auto col_update = [&](int r0, int w, int c0, int c1) {
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
+      double acc = 0.0;
+      for (int i = 0; i < w; i++) acc += F[(size_t)perm[r0 + i] * n + c] * vs[r0 + i];
+      vs[c] -= acc;
+    }
+    __syncthreads();
+  };
   const int np = n_piv / kPanel;
+  if (mode == 2) {
+    for (int bk = 0; bk < np; bk++) {
+      const int s = bk * kPanel;
+      block_inverse_t(dinv + (size_t)(2 * bk + 1) * 64 * 64, s, kPanel);
+      col_update(s, kPanel, s + kPanel, n);
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) vec[i] = vs[i];
+    return;
+  }
+  if (mode == 3) {
+    // z - L21^T lam_B: rows past n_piv hold L21 in the pivot columns (they never move)
+    for (int c = threadIdx.x; c < n_piv; c += blockDim.x) {
+      double acc = 0.0;
+      for (int r = n_piv; r < n; r++) acc += F[(size_t)r * n + c] * vs[r];
+      vs[c] -= acc;
+    }
+    __syncthreads();
+    for (int bk = np - 1; bk >= 0; bk--) {
+      const int s = bk * kPanel;
+      block_inverse_t(dinv + (size_t)(2 * bk) * 64 * 64, s, kPanel);
+      col_update(s, kPanel, 0, s);
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) vec[i < n_piv ? perm[i] : i] = vs[i];
+    return;
+  }
   if (mode == 0) {
     for (int bk = 0; bk < np; bk++) {
       const int s = bk * kPanel;
@@ -235,7 +285,7 @@ hps_status hps_front_factor(hps_front_plan pl, int32_t nfront, double* F, int32_
 
 hps_status hps_front_solve(hps_front_plan pl, int32_t nfront, const double* F, const int32_t* perm,
                            const double* dinv, double* vec, int32_t mode, hipStream_t st) {
-  if (!pl || nfront < 0 || nfront > 65535 || (mode != 0 && mode != 1)) return HPS_EINVAL;
+  if (!pl || nfront < 0 || nfront > 65535 || mode < 0 || mode > 3) return HPS_EINVAL;
   if (nfront == 0) return HPS_OK;
   if (!F || !perm || !dinv || !vec) return HPS_EINVAL;
   const int n = pl->g.n_pad;

@@ -355,10 +355,10 @@ class NestedDissection:
         self.factored = True
 
     # ---- solve -------------------------------------------------------------------------
-    def solve(self, box_vectors: torch.Tensor, sign: int = 1) -> torch.Tensor:
+    def solve(self, box_vectors: torch.Tensor, sign: int = 1, trans: bool = False) -> torch.Tensor:
         """u_F with T_FF u_F = sign * (sum over the two boxes of each face of box_vectors
-        [nbox, n_b]) (the lifted loads, or any per-box face vectors; sign +1 or -1).
-        Returns u_F [nface * m^2] (device)."""
+        [nbox, n_b]) (the lifted loads, or any per-box face vectors; sign +1 or -1), or with
+        T_FF^T when trans (the adjoint's solve).  Returns u_F [nface * m^2] (device)."""
         if sign not in (1, -1):
             raise ValueError("sign must be +1 or -1")
         if not self.factored:
@@ -380,14 +380,14 @@ class NestedDissection:
                 if u_int.shape[0]:
                     check(lib.hps_front_segments(u_int.shape[0], u_int.data_ptr(), mm, Vp, Vp, 1, st),
                           "hps_front_segments")
-            self._front_solve(gi, g, 0)
+            self._front_solve(gi, g, 2 if trans else 0)
         for gi in range(len(self.groups) - 1, -1, -1):  # downward
             g = self.groups[gi]
             gather, scatter = self.down_tasks[gi]
             if gather.shape[0]:
                 check(lib.hps_front_segments(gather.shape[0], gather.data_ptr(), mm, Vp, Up, 0, st),
                       "hps_front_segments")
-            self._front_solve(gi, g, 1)
+            self._front_solve(gi, g, 3 if trans else 1)
             check(lib.hps_front_segments(scatter.shape[0], scatter.data_ptr(), mm, Up, Vp, 0, st),
                   "hps_front_segments")
         return u[:self.layout.nface * mm]

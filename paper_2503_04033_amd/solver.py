@@ -280,6 +280,10 @@ class TwoLevelSolver:
         """Factor the interface matrix: on the GPU by nested dissection with dense fronts
         (NestedDissection) when interface is 'gpu', or 'auto' and its fronts fit the free
         device memory and the kernels' size limit; else on the host (InterfaceSolver)."""
+        return self.factor_interface(br.T_vals)
+
+    def factor_interface(self, T_vals: torch.Tensor):
+        """interface_solver() for interface blocks T_vals (the layout's slots)."""
         use_gpu = self.interface == "gpu"
         if self.interface == "auto" and self.device.type == "cuda" and self.layout.nface > 0:
             free = torch.cuda.mem_get_info(self.device)[0]
@@ -287,9 +291,9 @@ class TwoLevelSolver:
                        NestedDissection.estimate_bytes(self.layout) < 0.8 * free)
         if use_gpu:
             nd = NestedDissection(self.layout, self.device)
-            nd.factor(br.T_vals)
+            nd.factor(T_vals)
             return nd
-        return itf.InterfaceSolver(self.layout, br.T_vals.cpu().numpy())
+        return itf.InterfaceSolver(self.layout, T_vals.cpu().numpy())
 
     # ---- solve stage (Alg. 2) ---------------------------------------------------
     def solve(self, br: BuildResult, g_dir: torch.Tensor, isolver=None,

@@ -19,13 +19,13 @@ from tests.gpu_helpers import rel, say
 pytestmark = pytest.mark.gpu
 
 
-def _setup(nboxes, p, kappa, nobs, seed=5):
+def _setup(nboxes, p, kappa, nobs, seed=5, interface="auto"):
     from paper_2503_04033_amd.solver import TwoLevelSolver
     inv = W.config5(nboxes=nboxes, p=p, kappa=kappa, seed=seed, nobs=nobs)
     prob = inv.forward
     ref_obs = oi.solve(prob, b_field=inv.b_obs)
     data = oa.observe(ref_obs.u_i, inv.obs_nodes, p)
-    s = TwoLevelSolver.for_problem(prob, precision="fp64")
+    s = TwoLevelSolver.for_problem(prob, precision="fp64", interface=interface)
     bv, fv, gv, xi, xb = s.sample(prob.b, prob.f, prob.g)
     tl = oa.obs_local_index(inv.obs_nodes, p)
     return inv, prob, data, s, bv, fv, gv, xi, torch.tensor(tl, device="cuda")
@@ -42,10 +42,12 @@ def _gpu_grad(s, bv, fv, gv, tl, data, opts=None):
     return float(J), b.grad.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("nboxes,p,kappa,nobs", [((2, 2, 2), 6, 6.0, 40), ((4, 4, 4), 10, 15.0, 500)])
-def test_adjoint_gradient_matches_oracle(gpu, nboxes, p, kappa, nobs):
-    say(f"adjoint case nboxes={nboxes} p={p} kappa={kappa} nobs={nobs}")
-    inv, prob, data, s, bv, fv, gv, xi, tl = _setup(nboxes, p, kappa, nobs)
+@pytest.mark.parametrize("nboxes,p,kappa,nobs,interface", [((2, 2, 2), 6, 6.0, 40, "host"),
+                                                            ((2, 2, 2), 6, 6.0, 40, "gpu"),
+                                                            ((4, 4, 4), 10, 15.0, 500, "gpu")])
+def test_adjoint_gradient_matches_oracle(gpu, nboxes, p, kappa, nobs, interface):
+    say(f"adjoint case nboxes={nboxes} p={p} kappa={kappa} nobs={nobs} interface={interface}")
+    inv, prob, data, s, bv, fv, gv, xi, tl = _setup(nboxes, p, kappa, nobs, interface=interface)
     J, g = _gpu_grad(s, bv, fv, gv, tl, data)
     J0, g0, _ = oa.two_level_gradient(prob, inv.obs_nodes, data)
     e = rel(g, g0)
@@ -97,3 +99,40 @@ def test_adjoint_chunked_recompute_matches_resident(gpu):
     assert J0 == J1 and np.array_equal(g0, g1)
     Jo, go, _ = oa.two_level_gradient(prob, inv.obs_nodes, data)
     assert rel(g1, go) < 1e-9
+
+
+def test_adjoint_config5_full_size_central_differences(gpu):
+    # Configuration 5 at its full size: 8^3 boxes, p = 10, kappa = 15, 500 observation nodes.
+    # The oracle's host interface solve takes over 15 minutes here, so the gradient is held
+    # to central differences of the same misfit along smooth seeded directions (h = 1e-6;
+    # FD noise ~ eps |J| / h, so 1e-5 relative).  The observations are the GPU solution for
+    # b_obs, observation data only (they enter J, not any expected value).
+    from paper_2503_04033_amd.adjoint import AdjointSolve
+    from paper_2503_04033_amd.solver import TwoLevelSolver
+    inv = W.config5()
+    prob = inv.forward
+    s = TwoLevelSolver.for_problem(prob, precision="fp64", interface="gpu")
+    bv, fv, gv, xi, xb = s.sample(prob.b, prob.f, prob.g)
+    tl = torch.tensor(oa.obs_local_index(inv.obs_nodes, prob.p), device="cuda")
+    b_obs = torch.tensor(inv.b_obs(xi), device="cuda").contiguous()
+    u_obs, _ = AdjointSolve(s).forward(b_obs, fv, gv)
+    data = u_obs[tl[:, 0], tl[:, 1]].cpu().numpy()
+    say(f"config 5 full size: {prob.nbox} boxes, p={prob.p}, {s.layout.nunknown} interface unknowns")
+
+    def misfit(bb):
+        u, _ = AdjointSolve(s).forward(bb, fv, gv)
+        r = u[tl[:, 0], tl[:, 1]].cpu().numpy() - data
+        return 0.5 * float(r @ r)
+
+    J, g = _gpu_grad(s, bv, fv, gv, tl, data)
+    assert J == pytest.approx(misfit(bv), rel=1e-12)
+    rng = np.random.default_rng(55)
+    h = 1e-6
+    for k in range(2):
+        c = rng.uniform(size=3)
+        v = np.exp(-np.sum((xi - c) ** 2, axis=-1) / 0.05)
+        vd = torch.tensor(v, device="cuda")
+        fd = (misfit((bv + h * vd).contiguous()) - misfit((bv - h * vd).contiguous())) / (2 * h)
+        ad = float(np.sum(g * v))
+        say(f"  direction {k}: adjoint {ad:.8e}  central difference {fd:.8e}  rel {abs(ad - fd) / abs(fd):.2e}")
+        assert abs(ad - fd) <= 1e-5 * abs(fd)

@@ -48,12 +48,17 @@ def test_nested_random_blocks(gpu, nboxes, m):
     nd = NestedDissection(layout)
     say(f"  {len(nd.groups)} front groups, max front {nd.d.max_n}, {nd.memory_bytes() / 1e6:.1f} MB")
     nd.factor(torch.tensor(T_vals, device="cuda"))
-    u = nd.solve(torch.tensor(g, device="cuda")).cpu().numpy()
+    gd = torch.tensor(g, device="cuda")
+    u = nd.solve(gd).cpu().numpy()
+    lam = nd.solve(gd, trans=True).cpu().numpy()
     T = itf.bsr_matrix(layout, T_vals).toarray()
-    ref = np.linalg.solve(T, itf.interface_rhs(layout, g))
+    rhs = itf.interface_rhs(layout, g)
+    ref = np.linalg.solve(T, rhs)
+    ref_t = np.linalg.solve(T.T, rhs)
     err = np.abs(u - ref).max() / np.abs(ref).max()
-    say(f"  max rel err {err:.2e}")
-    assert err < 1e-12
+    err_t = np.abs(lam - ref_t).max() / np.abs(ref_t).max()
+    say(f"  max rel err {err:.2e}, transposed {err_t:.2e}")
+    assert err < 1e-12 and err_t < 1e-12
 
 
 def test_nested_dtn_4cubed_p16(gpu):
