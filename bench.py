@@ -118,6 +118,104 @@ def solve_stage(torch, prob, precision: str, interface: str) -> dict:
             "build_fp64_fallback_boxes": len(br.extra.get("fp64_fallback", []))}
 
 
+def time_stepping(torch, pp, precision: str, nsteps: int) -> dict:
+    """Crank-Nicolson stepping (paper Sec. 4.4): setup (leaf factorizations and the GPU
+    interface factorization, once) and the per-step time (right-hand side, loads, interface
+    solve, interiors), device-synchronized wall clock."""
+    from paper_2503_04033_amd.stepping import CrankNicolson
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cn = CrankNicolson(pp, precision)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cn.step()  # first step (allocator warm-up)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(nsteps):
+        a = time.perf_counter()
+        cn.step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - a)
+    return {"precision": precision, "nbox": pp.nbox, "p": pp.p, "interface_unknowns": int(cn.s.layout.nunknown),
+            "setup_s": round(t1 - t0, 4), "step_ms_median": round(1e3 * float(np.median(times)), 3),
+            "step_ms_min": round(1e3 * min(times), 3), "steps": nsteps,
+            "refine_rounds": cn.s.refine}
+
+
+def adjoint_timing(torch, reps: int = 3) -> dict:
+    """Forward solve and misfit gradient dJ/db (FP64) at the configuration-5 size, 8x8x8
+    boxes, p = 10, kappa = 15, 500 observation nodes: device-synchronized wall clock of the
+    forward pass (build, GPU interface factorization, solve, interiors) and of the backward
+    pass (transposed box solves, transposed interface solve, gradient), median of reps."""
+    import workloads as W
+    from paper_2503_04033_amd.adjoint import AdjointSolve
+    from paper_2503_04033_amd.solver import TwoLevelSolver
+    inv = W.config5()
+    prob = inv.forward
+    s = TwoLevelSolver.for_problem(prob, precision="fp64", interface="gpu")
+    bv, fv, gv, xi, _ = s.sample(prob.b, prob.f, prob.g)
+    m = prob.p - 2
+    t, i, j, k = inv.obs_nodes.T
+    tl = torch.tensor(np.stack([t, (i - 1) + m * (j - 1) + m * m * (k - 1)], axis=1), device=s.device)
+    fw, bw = [], []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        adj = AdjointSolve(s)
+        u, _ = adj.forward(bv, fv, gv)
+        torch.cuda.synchronize()
+        b0 = time.perf_counter()
+        w = torch.zeros_like(u)
+        w[tl[:, 0], tl[:, 1]] = u[tl[:, 0], tl[:, 1]]  # dJ/du of 0.5 |P u|^2
+        adj.gradient(w)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        fw.append(b0 - a)
+        bw.append(c - b0)
+    return {"workload": "8x8x8 boxes, p=10, kappa=15, 500 observation nodes (FP64)", "nbox": prob.nbox,
+            "interface_unknowns": int(s.layout.nunknown), "resident_factors": adj.resident,
+            "forward_s_median": round(float(np.median(fw[1:])), 4),
+            "gradient_s_median": round(float(np.median(bw[1:])), 4)}
+
+
+def batch_config4(torch, reps: int = 3) -> dict:
+    """Three independent problems in one captured stream (12^3 boxes p=8 kappa=10, 8^3 p=12
+    kappa=20, 6^3 p=16 kappa=30; FP32+IR): device time of a graph replay with the size groups
+    back to back, and with each group on its own stream (parallel graph branches)."""
+    import workloads as W
+    from paper_2503_04033_amd.batch import BatchedLeafReduction
+    probs = W.config4()
+    nbox = sum(p.nbox for p in probs)
+    out = {"workload": "; ".join(f"{p.nboxes[0]}^3 boxes p={p.p} kappa={p.kappa:g}" for p in probs),
+           "nbox": nbox}
+    ref = None
+    for mode in ("sequential", "concurrent"):
+        br = BatchedLeafReduction(probs, "fp32_ir", hbm_budget=64e9)
+        for q, pr in enumerate(probs):
+            br.sample_inputs(q, pr)
+        br.allocate()
+        br.capture(concurrent=(mode == "concurrent"))
+        br.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            br.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        vals = [g.T_vals.clone() for g in br.groups]
+        if ref is None:
+            ref = vals
+        else:
+            out["concurrent_bitwise_equal"] = all(torch.equal(a, b) for a, b in zip(ref, vals))
+        out[mode] = {"ms": round(ms, 3), "boxes_per_s": round(nbox / (ms / 1e3), 1),
+                     "chunks": [g.chunk for g in br.groups]}
+        del br
+        torch.cuda.empty_cache()
+    return out
+
+
 class Runner:
     """Buffers and the per-chunk ABI call sequence for one precision."""
 
@@ -422,6 +520,20 @@ def main():
             v.pop("u_face")
         result["solve_stage_4x4x4_p16"] = {"legs": legs, "rel_diff_u_i_vs_fp64_host": du,
                                            "rel_diff_u_face_vs_fp64_host": df}
+    if not a.no_solve_stage and not a.nbox:
+        # time stepping with one build: diffusion-reaction on 4x4x4 boxes, p = 16
+        pp = W.diffusion_reaction((4, 4, 4), 16, nu=0.05, dt=0.01, kappa=1.0, seed=9, width2=0.02)
+        ts = {}
+        for prec in ("fp32_ir", "fp64"):
+            ts[prec] = time_stepping(torch, pp, prec, 10)
+            torch.cuda.empty_cache()
+            log(f"crank-nicolson {prec}: {ts[prec]}")
+        result["crank_nicolson_4x4x4_p16"] = ts
+        result["batch_config4"] = batch_config4(torch)
+        log(f"config 4 batch: {result['batch_config4']}")
+        result["adjoint_8x8x8_p10"] = adjoint_timing(torch)
+        torch.cuda.empty_cache()
+        log(f"adjoint: {result['adjoint_8x8x8_p10']}")
     if not a.no_cpu:
         result["cpu_baseline"] = cpu_baseline(prob, a.cpu_sample)
         log(f"cpu baseline {result['cpu_baseline']}")

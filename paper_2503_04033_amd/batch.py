@@ -120,39 +120,59 @@ class BatchedLeafReduction:
             gr.slot_map = torch.tensor(gr.layout.slot_map, device=self.device)
             gr.triples = torch.tensor(gr.layout.reduce_triples, device=self.device)
 
-    def enqueue(self) -> None:
-        """All launches of the build stage for every group, on the current stream."""
-        for gr in self.groups:
-            plan, B, C, mm = gr.plan, gr.bufs, gr.chunk, gr.plan.info.m ** 2
-            for c0 in range(0, gr.nbox, C):
-                nb = min(C, gr.nbox - c0)
-                sl = slice(c0, c0 + nb)
-                plan.hps_leaf_operators(nb, gr.b[sl], B["A"], B["anorm"])
-                plan.hps_leaf_factor(nb, B["A"], B["perm"], B["dinv"], gr.info[sl])
-                plan.hps_leaf_dtn(nb, B["A"], B["perm"], B["dinv"], gr.b[sl], B["anorm"],
-                                  gr.f[sl] if gr.f is not None else None, gr.g_dir[sl], gr.slot_map[sl],
-                                  gr.T_vals, gr.g_loads[sl], B["X"], gr.iters[sl], gr.berr[sl], B["ws"])
-            if gr.triples.shape[0]:
-                hps_interface_reduce(gr.triples, mm * mm, gr.T_vals)
+    @staticmethod
+    def _enqueue_group(gr: Group) -> None:
+        plan, B, C, mm = gr.plan, gr.bufs, gr.chunk, gr.plan.info.m ** 2
+        for c0 in range(0, gr.nbox, C):
+            nb = min(C, gr.nbox - c0)
+            sl = slice(c0, c0 + nb)
+            plan.hps_leaf_operators(nb, gr.b[sl], B["A"], B["anorm"])
+            plan.hps_leaf_factor(nb, B["A"], B["perm"], B["dinv"], gr.info[sl])
+            plan.hps_leaf_dtn(nb, B["A"], B["perm"], B["dinv"], gr.b[sl], B["anorm"],
+                              gr.f[sl] if gr.f is not None else None, gr.g_dir[sl], gr.slot_map[sl],
+                              gr.T_vals, gr.g_loads[sl], B["X"], gr.iters[sl], gr.berr[sl], B["ws"])
+        if gr.triples.shape[0]:
+            hps_interface_reduce(gr.triples, mm * mm, gr.T_vals)
 
-    def capture(self) -> None:
+    def enqueue(self, concurrent: bool = False) -> None:
+        """All launches of the build stage for every group.  Sequential: one after another
+        on the current stream.  Concurrent: each group on a stream of its own (default
+        priority), forked from the current stream and joined back to it, so that the groups'
+        kernels overlap (in a captured graph they become parallel branches); every group has
+        its own plan and buffers, so the results are bitwise those of the sequential order."""
+        if not concurrent or len(self.groups) < 2:
+            for gr in self.groups:
+                self._enqueue_group(gr)
+            return
+        main = torch.cuda.current_stream()
+        if getattr(self, "_streams", None) is None:
+            self._streams = [torch.cuda.Stream(device=self.device) for _ in self.groups]
+        for st in self._streams:
+            st.wait_stream(main)
+        for gr, st in zip(self.groups, self._streams):
+            with torch.cuda.stream(st):
+                self._enqueue_group(gr)
+        for st in self._streams:
+            main.wait_stream(st)
+
+    def capture(self, concurrent: bool = False) -> None:
         """Record the whole build stage in a HIP graph (after one eager warm-up run)."""
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            self.enqueue()
+            self.enqueue(concurrent)
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self.enqueue()
+            self.enqueue(concurrent)
         torch.cuda.synchronize()
 
-    def run(self) -> None:
+    def run(self, concurrent: bool = False) -> None:
         if self.graph is not None:
             self.graph.replay()
         else:
-            self.enqueue()
+            self.enqueue(concurrent)
 
     def fallback(self) -> dict:
         """After run(): boxes whose FP64 refinement ended above ir_tol (ir_iters < 0) are

@@ -66,6 +66,87 @@ template <> struct Vec4<double> {
 };
 
 // ---------------------------------------------------------------------------
+// One FP64 vector in LDS against a stored factor (the one-vector-per-matrix solves:
+// interior solves, adjoint solves, interface fronts), one 1024-thread workgroup per
+// matrix.  Row updates use 16 lanes per row and keep 8 rows in flight per 16-lane group
+// (512 row reads outstanding per workgroup), so that a single workgroup per matrix is
+// not held to a few GB/s by memory latency.
+// ---------------------------------------------------------------------------
+constexpr int kVecThreads = 1024;
+
+// v[j] -= sum_{c < w} A_j[c] v[c0 + c] for rows j in [j0, j1), A_j = rowptr(j) + c0, w <= 64.
+// The rows updated lie outside [c0, c0 + w).
+template <typename T, typename RowPtr>
+__device__ inline void vec_rows_update(double* v, int j0, int j1, int c0, int w, RowPtr rowptr) {
+  constexpr int RB = 8;
+  const int lane16 = threadIdx.x & 15, grp = threadIdx.x >> 4, ngrp = blockDim.x >> 4;
+  double xv[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int c = lane16 + 16 * q;
+    xv[q] = c < w ? v[c0 + c] : 0.0;
+  }
+  for (int jb = j0 + grp * RB; jb < j1; jb += ngrp * RB) {
+    T a[RB][4];
+#pragma unroll
+    for (int r = 0; r < RB; r++) {
+      const bool ok = jb + r < j1;
+      const T* row = ok ? rowptr(jb + r) + c0 : nullptr;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int c = lane16 + 16 * q;
+        a[r][q] = (ok && c < w) ? row[c] : T(0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; r++) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; q++) acc += (double)a[r][q] * xv[q];
+      for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+      if (lane16 == 0 && jb + r < j1) v[jb + r] -= acc;
+    }
+  }
+  __syncthreads();
+}
+
+// v[c] -= sum_{i < w} A_{r0+i}[c] v[r0 + i] for columns c in [c0, c1), A_i = rowptr(i)
+// (the transposed update: consecutive threads read consecutive columns of a row).
+template <typename T, typename RowPtr>
+__device__ inline void vec_cols_update(double* v, int r0, int w, int c0, int c1, RowPtr rowptr) {
+  for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < w; i += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; u++)
+        if (i + u < w) acc[u] += (double)rowptr(r0 + i + u)[c] * v[r0 + i + u];
+    }
+    v[c] -= ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  }
+  __syncthreads();
+}
+
+// v[s + t] = sum_{k < w} Inv[t][k] v[s + k] (or Inv[k][t] when trans) for t < w, Inv a
+// stored 64 x 64 block (row stride 64): 16 lanes per output, 1024 threads.
+template <typename T>
+__device__ inline void vec_block_inverse(double* v, double* tmp, const T* Inv, int s, int w, bool trans) {
+  const int lane16 = threadIdx.x & 15, t = threadIdx.x >> 4;
+  if (t < w) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int k = lane16 + 16 * q;
+      if (k < w) acc += (double)(trans ? Inv[k * 64 + t] : Inv[t * 64 + k]) * v[s + k];
+    }
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    if (lane16 == 0) tmp[t] = acc;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < w) v[s + threadIdx.x] = tmp[threadIdx.x];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Geometry of one plan, passed to kernels by value.
 // ---------------------------------------------------------------------------
 struct Geom {

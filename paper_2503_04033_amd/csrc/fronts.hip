@@ -72,9 +72,9 @@ __global__ __launch_bounds__(256) void segment_kernel(int ntask, const int64_t* 
 //         [0, n_piv) and r_B - U12^T z in [n_piv, n).
 //  mode 3 (downward): on entry z in [0, n_piv) and lam_B in [n_piv, n).  Leaves lam_P =
 //         P_r^T L11^{-T} (z - L21^T lam_B) in [0, n_piv), in unknown order.
-__global__ __launch_bounds__(256) void front_solve_kernel(int n, int n_piv, const double* F_all,
-                                                          const int* perm_all, const double* dinv_all,
-                                                          double* vec_all, int mode) {
+__global__ __launch_bounds__(kVecThreads) void front_solve_kernel(int n, int n_piv, const double* F_all,
+                                                                  const int* perm_all, const double* dinv_all,
+                                                                  double* vec_all, int mode) {
   extern __shared__ double vs[];  // [n], then 64 of scratch
   double* tmp = vs + n;
   const int f = blockIdx.x;
@@ -83,91 +83,41 @@ __global__ __launch_bounds__(256) void front_solve_kernel(int n, int n_piv, cons
   const int npanel = (n + kPanel - 1) / kPanel;
   const double* dinv = dinv_all + (size_t)f * npanel * 2 * 64 * 64;
   double* vec = vec_all + (size_t)f * n;
-  const int lane16 = threadIdx.x & 15, grp = threadIdx.x >> 4, ngrp = blockDim.x >> 4;
   for (int i = threadIdx.x; i < n; i += blockDim.x) vs[i] = (mode == 0 && i < n_piv) ? vec[perm[i]] : vec[i];
   __syncthreads();
-  auto block_inverse = [&](const double* Inv, int s, int w) {
-    if ((int)threadIdx.x < w) {
-      double acc = 0.0;
-      for (int k = 0; k < w; k++) acc += Inv[threadIdx.x * 64 + k] * vs[s + k];
-      tmp[threadIdx.x] = acc;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < w) vs[s + threadIdx.x] = tmp[threadIdx.x];
-    __syncthreads();
-  };
-  // rows [j0, j1) -= F[perm[row]][c0 .. c0+w) . vs[c0 .. c0+w)
-  auto update = [&](int j0, int j1, int c0, int w) {
-    for (int j = j0 + grp; j < j1; j += ngrp) {
-      const double* row = F + (size_t)perm[j] * n + c0;
-      double acc = 0.0;
-      for (int c = lane16; c < w; c += 16) acc += row[c] * vs[c0 + c];
-      for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
-      if (lane16 == 0) vs[j] -= acc;
-    }
-    __syncthreads();
-  };
-  // vs[s + t] = sum_k Inv[k][t] vs[s + k]: the transposed product with a stored inverse
-  auto block_inverse_t = [&](const double* Inv, int s, int w) {
-    if ((int)threadIdx.x < w) {
-      double acc = 0.0;
-      for (int k = 0; k < w; k++) acc += Inv[k * 64 + threadIdx.x] * vs[s + k];
-      tmp[threadIdx.x] = acc;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < w) vs[s + threadIdx.x] = tmp[threadIdx.x];
-    __syncthreads();
-  };
-  // columns [c0, c1) -= sum over positions i in [r0, r0+w) of F[perm[i]][col] vs[i]
-  auto col_update = [&](int r0, int w, int c0, int c1) {
-    for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
-      double acc = 0.0;
-      for (int i = 0; i < w; i++) acc += F[(size_t)perm[r0 + i] * n + c] * vs[r0 + i];
-      vs[c] -= acc;
-    }
-    __syncthreads();
-  };
+  auto row = [&](int j) { return F + (size_t)perm[j] * n; };
+  auto prow = [&](int j) { return F + (size_t)j * n; };  // rows past n_piv never move
   const int np = n_piv / kPanel;
-  if (mode == 2) {
-    for (int bk = 0; bk < np; bk++) {
-      const int s = bk * kPanel;
-      block_inverse_t(dinv + (size_t)(2 * bk + 1) * 64 * 64, s, kPanel);
-      col_update(s, kPanel, s + kPanel, n);
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) vec[i] = vs[i];
-    return;
-  }
-  if (mode == 3) {
-    // z - L21^T lam_B: rows past n_piv hold L21 in the pivot columns (they never move)
-    for (int c = threadIdx.x; c < n_piv; c += blockDim.x) {
-      double acc = 0.0;
-      for (int r = n_piv; r < n; r++) acc += F[(size_t)r * n + c] * vs[r];
-      vs[c] -= acc;
-    }
-    __syncthreads();
-    for (int bk = np - 1; bk >= 0; bk--) {
-      const int s = bk * kPanel;
-      block_inverse_t(dinv + (size_t)(2 * bk) * 64 * 64, s, kPanel);
-      col_update(s, kPanel, 0, s);
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) vec[i < n_piv ? perm[i] : i] = vs[i];
-    return;
-  }
   if (mode == 0) {
     for (int bk = 0; bk < np; bk++) {
       const int s = bk * kPanel;
-      block_inverse(dinv + (size_t)(2 * bk) * 64 * 64, s, kPanel);
-      update(s + kPanel, n, s, kPanel);
+      vec_block_inverse<double>(vs, tmp, dinv + (size_t)(2 * bk) * 64 * 64, s, kPanel, false);
+      vec_rows_update<double>(vs, s + kPanel, n, s, kPanel, row);
     }
-  } else {
-    if (n > n_piv) update(0, n_piv, n_piv, n - n_piv);
+  } else if (mode == 1) {
+    for (int c0 = n_piv; c0 < n; c0 += kPanel)  // y - U12 u_B, 64 columns at a time
+      vec_rows_update<double>(vs, 0, n_piv, c0, (n - c0) < kPanel ? (n - c0) : kPanel, row);
     for (int bk = np - 1; bk >= 0; bk--) {
       const int s = bk * kPanel;
-      block_inverse(dinv + (size_t)(2 * bk + 1) * 64 * 64, s, kPanel);
-      update(0, s, s, kPanel);
+      vec_block_inverse<double>(vs, tmp, dinv + (size_t)(2 * bk + 1) * 64 * 64, s, kPanel, false);
+      vec_rows_update<double>(vs, 0, s, s, kPanel, row);
+    }
+  } else if (mode == 2) {
+    for (int bk = 0; bk < np; bk++) {
+      const int s = bk * kPanel;
+      vec_block_inverse<double>(vs, tmp, dinv + (size_t)(2 * bk + 1) * 64 * 64, s, kPanel, true);
+      vec_cols_update<double>(vs, s, kPanel, s + kPanel, n, row);
+    }
+  } else {
+    for (int r0 = n_piv; r0 < n; r0 += kPanel)  // z - L21^T lam_B, 64 rows at a time
+      vec_cols_update<double>(vs, r0, (n - r0) < kPanel ? (n - r0) : kPanel, 0, n_piv, prow);
+    for (int bk = np - 1; bk >= 0; bk--) {
+      const int s = bk * kPanel;
+      vec_block_inverse<double>(vs, tmp, dinv + (size_t)(2 * bk) * 64 * 64, s, kPanel, true);
+      vec_cols_update<double>(vs, s, kPanel, 0, s, row);
     }
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) vec[i] = vs[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) vec[(mode == 3 && i < n_piv) ? perm[i] : i] = vs[i];
 }
 
 }  // namespace hps
@@ -290,8 +240,8 @@ hps_status hps_front_solve(hps_front_plan pl, int32_t nfront, const double* F, c
   if (!F || !perm || !dinv || !vec) return HPS_EINVAL;
   const int n = pl->g.n_pad;
   const size_t shm = sizeof(double) * ((size_t)n + 64);
-  hipLaunchKernelGGL(hps::front_solve_kernel, dim3(nfront), dim3(256), shm, st, n, pl->n_piv, F, perm, dinv, vec,
-                     (int)mode);
+  hipLaunchKernelGGL(hps::front_solve_kernel, dim3(nfront), dim3(hps::kVecThreads), shm, st, n, pl->n_piv, F, perm,
+                     dinv, vec, (int)mode);
   return hipGetLastError() == hipSuccess ? HPS_OK : HPS_EDEVICE;
 }
 

@@ -1028,8 +1028,9 @@ hipError_t launch_adjoint_rhs(const Geom& g, int nbox, const double* w, const do
 // z = A_ii^{-T} rhs with P A = L U:  A^T = U^T L^T P, so solve U^T y = rhs
 // (forward), L^T v = y (backward), z[perm[i]] = v[i].  One workgroup per box;
 // the vector lives in LDS, the factor rows are read coalesced (row-major).
-__global__ __launch_bounds__(256) void getrs_t_kernel(Geom g, int nbox, const double* LU_all, const int* perm_all,
-                                                      const double* dinv_all, const double* rhs_all, double* z_all) {
+__global__ __launch_bounds__(kVecThreads) void getrs_t_kernel(Geom g, int nbox, const double* LU_all,
+                                                              const int* perm_all, const double* dinv_all,
+                                                              const double* rhs_all, double* z_all) {
   extern __shared__ double vec[];
   double* tmp = vec + g.n_pad;
   const int box = blockIdx.x;
@@ -1039,43 +1040,18 @@ __global__ __launch_bounds__(256) void getrs_t_kernel(Geom g, int nbox, const do
   const double* dinv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64;
   for (int i = threadIdx.x; i < N; i += blockDim.x) vec[i] = rhs_all[(size_t)box * N + i];
   __syncthreads();
+  auto row = [&](int j) { return LU + (size_t)perm[j] * N; };
   // U^T y = r: block b, y_b = Uinv_b^T (r_b - sum_{k<b} U_kb^T y_k); right-looking updates
   for (int bk = 0; bk < g.npanel; bk++) {
     const int s = bk * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
-    const double* Uinv = dinv + (size_t)(2 * bk + 1) * 64 * 64;
-    if ((int)threadIdx.x < w) {
-      double acc = 0.0;
-      for (int k = 0; k < w; k++) acc += Uinv[k * 64 + threadIdx.x] * vec[s + k];
-      tmp[threadIdx.x] = acc;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
-    __syncthreads();
-    for (int j = s + w + threadIdx.x; j < N; j += blockDim.x) {
-      double acc = 0.0;
-      for (int i = 0; i < w; i++) acc += LU[(size_t)perm[s + i] * N + j] * vec[s + i];
-      vec[j] -= acc;
-    }
-    __syncthreads();
+    vec_block_inverse<double>(vec, tmp, dinv + (size_t)(2 * bk + 1) * 64 * 64, s, w, true);
+    vec_cols_update<double>(vec, s, w, s + w, N, row);
   }
   // L^T v = y: block b from the last, v_b = Linv_b^T (y_b - sum_{k>b} L_kb^T v_k)
   for (int bk = g.npanel - 1; bk >= 0; bk--) {
     const int s = bk * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
-    const double* Linv = dinv + (size_t)(2 * bk) * 64 * 64;
-    if ((int)threadIdx.x < w) {
-      double acc = 0.0;
-      for (int k = 0; k < w; k++) acc += Linv[k * 64 + threadIdx.x] * vec[s + k];
-      tmp[threadIdx.x] = acc;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
-    __syncthreads();
-    for (int j = threadIdx.x; j < s; j += blockDim.x) {
-      double acc = 0.0;
-      for (int i = 0; i < w; i++) acc += LU[(size_t)perm[s + i] * N + j] * vec[s + i];
-      vec[j] -= acc;
-    }
-    __syncthreads();
+    vec_block_inverse<double>(vec, tmp, dinv + (size_t)(2 * bk) * 64 * 64, s, w, true);
+    vec_cols_update<double>(vec, s, w, 0, s, row);
   }
   for (int i = threadIdx.x; i < N; i += blockDim.x) z_all[(size_t)box * N + perm[i]] = vec[i];
 }
@@ -1083,7 +1059,7 @@ __global__ __launch_bounds__(256) void getrs_t_kernel(Geom g, int nbox, const do
 hipError_t launch_getrs_t(const Geom& g, int nbox, const double* LU, const int* perm, const double* dinv,
                           const double* rhs, double* z, hipStream_t st) {
   const size_t shm = sizeof(double) * (g.n_pad + 64);
-  hipLaunchKernelGGL(getrs_t_kernel, dim3(nbox), dim3(256), shm, st, g, nbox, LU, perm, dinv, rhs, z);
+  hipLaunchKernelGGL(getrs_t_kernel, dim3(nbox), dim3(kVecThreads), shm, st, g, nbox, LU, perm, dinv, rhs, z);
   return hipGetLastError();
 }
 
@@ -1171,9 +1147,9 @@ hipError_t launch_interior_berr(int nbox, const double* anorm, const double* r0m
 // the rows below (forward) or above (backward) are updated, 16 lanes per row.  The
 // factors may be FP32; the vector is carried in FP64.
 template <typename T>
-__global__ __launch_bounds__(256) void getrs_vec_kernel(Geom g, int nbox, const T* LU_all, const int* perm_all,
-                                                        const T* dinv_all, const double* r_all, double* x_all,
-                                                        int accumulate) {
+__global__ __launch_bounds__(kVecThreads) void getrs_vec_kernel(Geom g, int nbox, const T* LU_all,
+                                                                const int* perm_all, const T* dinv_all,
+                                                                const double* r_all, double* x_all, int accumulate) {
   extern __shared__ double vec[];  // [n_pad], then 64 of scratch
   double* tmp = vec + g.n_pad;
   const int box = blockIdx.x;
@@ -1182,42 +1158,21 @@ __global__ __launch_bounds__(256) void getrs_vec_kernel(Geom g, int nbox, const 
   const int* perm = perm_all + (size_t)box * N;
   const T* dinv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64;
   const double* r = r_all + (size_t)box * n;
-  const int lane16 = threadIdx.x & 15, grp = threadIdx.x >> 4, ngrp = blockDim.x >> 4;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const int pr = perm[i];
     vec[i] = pr < n ? r[pr] : 0.0;
   }
   __syncthreads();
-  auto block_inverse = [&](const T* Inv, int s, int w) {
-    if ((int)threadIdx.x < w) {
-      double acc = 0.0;
-      for (int k = 0; k < w; k++) acc += (double)Inv[threadIdx.x * 64 + k] * vec[s + k];
-      tmp[threadIdx.x] = acc;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < w) vec[s + threadIdx.x] = tmp[threadIdx.x];
-    __syncthreads();
-  };
-  // rows [j0, j1) -= LU[perm[row]][s .. s+w) . vec[s .. s+w)
-  auto update = [&](int j0, int j1, int s, int w) {
-    for (int j = j0 + grp; j < j1; j += ngrp) {
-      const T* row = LU + (size_t)perm[j] * N + s;
-      double acc = 0.0;
-      for (int c = lane16; c < w; c += 16) acc += (double)row[c] * vec[s + c];
-      for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
-      if (lane16 == 0) vec[j] -= acc;
-    }
-    __syncthreads();
-  };
+  auto row = [&](int j) { return LU + (size_t)perm[j] * N; };
   for (int bk = 0; bk < g.npanel; bk++) {  // L y = P r
     const int s = bk * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
-    block_inverse(dinv + (size_t)(2 * bk) * 64 * 64, s, w);
-    update(s + w, N, s, w);
+    vec_block_inverse<T>(vec, tmp, dinv + (size_t)(2 * bk) * 64 * 64, s, w, false);
+    vec_rows_update<T>(vec, s + w, N, s, w, row);
   }
   for (int bk = g.npanel - 1; bk >= 0; bk--) {  // U x = y
     const int s = bk * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
-    block_inverse(dinv + (size_t)(2 * bk + 1) * 64 * 64, s, w);
-    update(0, s, s, w);
+    vec_block_inverse<T>(vec, tmp, dinv + (size_t)(2 * bk + 1) * 64 * 64, s, w, false);
+    vec_rows_update<T>(vec, 0, s, s, w, row);
   }
   double* x = x_all + (size_t)box * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = accumulate ? x[i] + vec[i] : vec[i];
@@ -1236,7 +1191,8 @@ template <typename T>
 hipError_t launch_getrs_vec(const Geom& g, int nbox, const T* LU, const int* perm, const T* dinv, const double* r,
                             double* x, int accumulate, hipStream_t st) {
   const size_t shm = sizeof(double) * (g.n_pad + 64);
-  hipLaunchKernelGGL(getrs_vec_kernel<T>, dim3(nbox), dim3(256), shm, st, g, nbox, LU, perm, dinv, r, x, accumulate);
+  hipLaunchKernelGGL(getrs_vec_kernel<T>, dim3(nbox), dim3(kVecThreads), shm, st, g, nbox, LU, perm, dinv, r, x,
+                     accumulate);
   return hipGetLastError();
 }
 template hipError_t launch_getrs_vec<float>(const Geom&, int, const float*, const int*, const float*, const double*,

@@ -114,7 +114,7 @@ class TwoLevelSolver:
 
     def __init__(self, nboxes, lo, hi, p: int, kappa: float, precision: str = "fp64", ir_max_iter: int = 3,
                  ir_tol: Optional[float] = None, chunk: Optional[int] = None, keep: Optional[bool] = None, device="cuda",
-                 refine: Optional[int] = None, refine_steps: int = 2, tuning: Optional[dict] = None,
+                 refine: Optional[int] = None, refine_steps: Optional[int] = None, tuning: Optional[dict] = None,
                  hbm_budget: Optional[float] = None, interior_tol: float = 1e-12, interface: str = "auto",
                  keep_what: Optional[str] = None):
         self.nboxes = tuple(int(v) for v in nboxes)
@@ -130,7 +130,9 @@ class TwoLevelSolver:
         self.info = self.plan.info
         self.layout = itf.build_layout(self.nboxes, self.info.m)
         self.refine = (1 if precision == "fp32_ir" else 0) if refine is None else int(refine)
-        self.refine_steps = int(refine_steps)
+        # FP64 refinement steps of the interior solves: FP32 factors gain ~6 digits a step (2
+        # reach FP64 rounding); FP64 factors are at FP64 rounding already
+        self.refine_steps = (2 if precision == "fp32_ir" else 0) if refine_steps is None else int(refine_steps)
         self.interior_tol = float(interior_tol)
         self.precision = precision
         if interface not in ("auto", "gpu", "host"):
@@ -434,7 +436,7 @@ class TwoLevelSolver:
             plan.hps_leaf_operators(nb, bb, bufs["A"], bufs["anorm"])
             plan.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], bufs["info"])
             plan.hps_leaf_interior_solve(nb, bufs["A"], bufs["perm"], bufs["dinv"], bb, bufs["anorm"], ff,
-                                         ub_d[idx].contiguous(), u, self.refine_steps, e, bufs["ws"])
+                                         ub_d[idx].contiguous(), u, 1, e, bufs["ws"])
             ui[idx] = u
             berr[idx] = e
 

@@ -91,6 +91,28 @@ def test_three_problem_batch(gpu):
             assert torch.equal(g.T_vals, eager[q][0]), f"replay {rep} group {q}: T differs"
             assert torch.equal(g.g_loads, eager[q][1]), f"replay {rep} group {q}: g differs"
         say(f"  graph replay {rep}: bitwise equal to the eager run")
+    # the three groups on concurrent streams: eagerly, then as a captured graph whose branches
+    # overlap, each replay bitwise the sequential results
+    for g in br.groups:
+        g.T_vals[:-1].fill_(-1.0)
+        g.g_loads.fill_(-1.0)
+    br.graph = None
+    br.run(concurrent=True)
+    torch.cuda.synchronize()
+    for q, g in enumerate(br.groups):
+        assert torch.equal(g.T_vals, eager[q][0]) and torch.equal(g.g_loads, eager[q][1])
+    br.capture(concurrent=True)
+    for rep in range(3):
+        for g in br.groups:
+            g.T_vals[:-1].fill_(-1.0)
+            g.g_loads.fill_(-1.0)
+        torch.cuda.synchronize()
+        br.run()
+        torch.cuda.synchronize()
+        for q, g in enumerate(br.groups):
+            assert torch.equal(g.T_vals, eager[q][0]), f"concurrent replay {rep} group {q}: T differs"
+            assert torch.equal(g.g_loads, eager[q][1]), f"concurrent replay {rep} group {q}: g differs"
+        say(f"  concurrent-branch graph replay {rep}: bitwise equal to the eager run")
 
 
 def test_autotune_config4(gpu, tmp_path):
