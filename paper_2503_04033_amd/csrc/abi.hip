@@ -175,13 +175,15 @@ hipError_t scratch_address(int device, void** out) {
 
 // Profiling only (synchronizes the stream): the flops of one solve over nbox boxes.
 // Algorithmic: n_i^2 (n_b + 1) per sweep and active box.  Executed: per 64-column tile
-// and 64-row block row, (2 w K + w^2) times the tile's columns that are real right-hand
+// and block row of w rows, (2 w K + w^2) times the tile's columns that are real right-hand
 // sides, K the rows the block row's product runs over; the forward sweep of a tile with
 // first nonzero row ks stores block rows that end above ks as zeros and starts K at ks.
 hps::SolveFlops solve_flops(const hps_plan_s* pl, int nbox, const int* kstart_dev, const int* active_dev,
                             hipStream_t st) {
   const Geom& g = pl->g;
   const int ntn = g.ldx / 64, N = g.n_pad;
+  // rows per block row of the solves (hps::solve_block_rows): 128 for FP32 plans, 64 for FP64
+  const int br = pl->desc.precision == HPS_FP32_IR ? 128 : 64;
   std::vector<int> act(nbox, 1), ks;
   if (active_dev) (void)hipMemcpyAsync(act.data(), active_dev, sizeof(int) * nbox, hipMemcpyDeviceToHost, st);
   if (kstart_dev) {
@@ -209,8 +211,8 @@ hps::SolveFlops solve_flops(const hps_plan_s* pl, int nbox, const int* kstart_de
     for (int tn = 0; tn < ntn; tn++) {
       const int k0 = ks[(size_t)b * ntn + tn];
       double t = 0.0;
-      for (int s = 0; s < N; s += 64) {
-        const int w = std::min(64, N - s);
+      for (int s = 0; s < N; s += br) {
+        const int w = std::min(br, N - s);
         if (s + w <= k0) continue;
         t += 2.0 * w * std::max(0, s - k0) + (double)w * w;
       }

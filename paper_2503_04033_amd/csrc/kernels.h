@@ -92,6 +92,10 @@ struct ProfScope {
 template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
                      hipStream_t st, Profiler* prof, int pivot_end = -1);
+// Rows per block row of the triangular solves of getrs_run: 128 in FP32 (two 64-row LU
+// panels per launch), 64 in FP64.
+template <typename T>
+constexpr int solve_block_rows() { return sizeof(T) == 4 ? 128 : 64; }
 // Flops of one solve for the profiler (set by the caller when profiling is on): algorithmic
 // n_i^2 (n_b + 1) per active box and sweep, and what the kernels execute per sweep.
 struct SolveFlops {

@@ -589,6 +589,228 @@ __device__ __attribute__((always_inline)) inline void solve_block_row(const Geom
     }
 }
 
+// ---------------------------------------------------------------------------
+// 128-row block rows (FP32 solves): twice the rows per launch, so the finished rows Y of
+// a tile are read once per 128 rows instead of per 64 and a sweep takes half the launches.
+// The 128 x 64 output tile is the tile GEMM with the four waves stacked (32 rows x 64
+// columns each); the 128 x 128 diagonal block is applied as its two stored 64 x 64
+// inverses and the coupling block between them:
+//   forward (L):  Y0 = Linv0 Z0;  Z1 -= L10 Y0;  Y1 = Linv1 Z1
+//   backward (U): Y1 = Uinv1 Z1;  Z0 -= U01 Y1;  Y0 = Uinv0 Z0
+// ---------------------------------------------------------------------------
+constexpr int kBlockRows = 128;
+template <typename T> struct GemmCfg128;
+template <> struct GemmCfg128<float> { typedef TileGemm<float, 2, 4, 4, 1, 16, 2> G; };
+template <> struct GemmCfg128<double> { typedef TileGemm<double, 2, 4, 4, 1, 16, 2> G; };
+template <typename T>
+constexpr int smem128() {
+  return GemmCfg128<T>::G::SMEM > kBlockRows * kLeafLd ? GemmCfg128<T>::G::SMEM : kBlockRows * kLeafLd;
+}
+
+// out = Inv Z for one 64-row half: wave w forms rows [16w, 16w + 16) x 64 columns; Inv is a
+// stored 64 x 64 inverse (row stride 64), Z the LDS rows [z0, z0 + 64) (stride kLeafLd),
+// k < wk (the half's width; LDS rows past it hold zeros).
+template <typename T>
+__device__ inline void half_inverse(const T* Inv, const T* zs, int z0, int wk, typename Mfma<T>::acc (&out)[4]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g4 = lane >> 4, c16 = lane & 15;
+  const T* irow = Inv + (wave * 16 + c16) * 64 + 4 * g4;
+  T ia[4];
+  Vec4<T>::load(irow, ia);
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++) out[ct] = Mfma<T>::zero();
+#pragma unroll
+  for (int kc = 0; kc < 4; kc++) {
+    T ib[4];
+    if (kc + 1 < 4) Vec4<T>::load(irow + (kc + 1) * 16, ib);
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int k = kc * 16 + 4 * g4 + t;
+      const T a = k < wk ? ia[t] : T(0);
+      const T* zr = zs + (z0 + k) * kLeafLd + c16;
+#pragma unroll
+      for (int ct = 0; ct < 4; ct++) out[ct] = Mfma<T>::op(a, zr[ct * 16], out[ct]);
+    }
+    if (kc + 1 < 4)
+#pragma unroll
+      for (int t = 0; t < 4; t++) ia[t] = ib[t];
+  }
+}
+
+// cor = -C Yh for one 64-row half: C rows from the factor (rowp(r) + c0, r < wr, k < wk),
+// Yh the LDS rows [y0, y0 + 64); wave w forms rows [16w, 16w + 16).
+template <typename T, typename RowP>
+__device__ inline void half_couple(RowP rowp, int wr, int c0, int wk, const T* zs, int y0,
+                                   typename Mfma<T>::acc (&cor)[4]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g4 = lane >> 4, c16 = lane & 15;
+  const int r = wave * 16 + c16;
+  const T* arow = r < wr ? rowp(r) + c0 : nullptr;
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++) cor[ct] = Mfma<T>::zero();
+#pragma unroll
+  for (int kc = 0; kc < 4; kc++) {
+    T a[4];
+    if (arow && kc * 16 + 4 * g4 < wk) Vec4<T>::load(arow + kc * 16 + 4 * g4, a);  // never past column c0 + wk
+    else a[0] = a[1] = a[2] = a[3] = T(0);
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int k = kc * 16 + 4 * g4 + t;
+      const T av = k < wk ? -a[t] : T(0);
+      const T* yr = zs + (y0 + k) * kLeafLd + c16;
+#pragma unroll
+      for (int ct = 0; ct < 4; ct++) cor[ct] = Mfma<T>::op(av, yr[ct * 16], cor[ct]);
+    }
+  }
+}
+
+template <typename T, bool UPPER, bool SEG>
+__device__ __attribute__((always_inline)) inline void solve_block_row128(
+    const Geom& g, const T* F, const int* perm, const T* Inv0, const T* Inv1, const T* B, T* Y, double* Xb, int xmode,
+    int s, int w, int nt, int ks, int bdirect, const T* Y0, T* smem) {
+  typedef typename GemmCfg128<T>::G G;
+  static_assert(G::MT == 128 && G::NT == 64, "one 128 x 64 tile per workgroup");
+  constexpr int WRT = 2, WCT = 4;
+  const int N = g.n_pad, ld = g.ldx;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, c16 = lane & 15;
+  if (!UPPER && s + w <= ks) {  // every row of this block row of the tile is zero
+    for (int e = threadIdx.x; e < w * 64; e += blockDim.x) Y[(size_t)(s + e / 64) * ld + nt + (e & 63)] = T(0);
+    return;
+  }
+  typename G::acc_t acc[WRT][WCT];
+#pragma unroll
+  for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+    for (int ct = 0; ct < WCT; ct++) acc[rt][ct] = Mfma<T>::zero();
+  auto arow = [&](int r) -> const T* { return r < w ? F + (size_t)perm[s + r] * N : nullptr; };
+  auto brow = [&](int k) -> const T* { return Y + (size_t)k * ld + nt; };
+  const int k0 = UPPER ? s + w : ks, k1 = UPPER ? N : s;
+  if constexpr (!SEG) {
+    G::run(acc, arow, brow, 64, k0, k1, smem);
+  } else {
+    typename G::acc_t part[WRT][WCT];
+#pragma unroll
+    for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < WCT; ct++) part[rt][ct] = Mfma<T>::zero();
+    const int nchunk = (k1 - k0) / G::KCHUNK;
+    auto fold = [&](int c) {
+      if ((c + 1) % (kTrsmSeg / G::KCHUNK) == 0 || c + 1 == nchunk) {
+#pragma unroll
+        for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+          for (int ct = 0; ct < WCT; ct++) {
+            acc[rt][ct] += part[rt][ct];
+            part[rt][ct] = Mfma<T>::zero();
+          }
+      }
+    };
+    G::run(part, arow, brow, 64, k0, k1, smem, fold);
+  }
+  __syncthreads();  // every wave is done with the staging buffer
+  T* zs = smem;     // Z [128][kLeafLd]; rows past w hold zeros
+#pragma unroll
+  for (int rt = 0; rt < WRT; rt++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int r = wave * 32 + rt * 16 + Mfma<T>::row(lane, i);
+      const T* rr =
+          r < w ? (UPPER ? Y + (size_t)(s + r) * ld : B + (size_t)(bdirect ? s + r : perm[s + r]) * ld) + nt : nullptr;
+#pragma unroll
+      for (int ct = 0; ct < WCT; ct++) {
+        const int c = ct * 16 + c16;
+        zs[r * kLeafLd + c] = rr ? rr[c] + acc[rt][ct][i] : T(0);
+      }
+    }
+  __syncthreads();
+  const int w0 = w < 64 ? w : 64, w1 = w - w0;
+  // rows [h0, h0 + wk) of the block: Y, and for the backward sweep X (1: X = Y, 2: X += Y,
+  // 3: X = Y0 + Y; X in the natural column order)
+  auto store = [&](typename Mfma<T>::acc (&out)[4], int h0, int wk) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int r = wave * 16 + Mfma<T>::row(lane, i);
+        if (r < wk) {
+          const size_t row = (size_t)(s + h0 + r) * ld;
+          Y[row + nt + ct * 16 + c16] = out[ct][i];
+          if (Xb) {
+            const size_t ex = row + g.gmap[(nt >> 4) + ct] * 16 + c16;
+            const double old = xmode == 2 ? Xb[ex] : (xmode == 3 ? (double)Y0[row + nt + ct * 16 + c16] : 0.0);
+            Xb[ex] = old + (double)out[ct][i];
+          }
+        }
+      }
+  };
+  // the finished half back into LDS (rows [z0, z0 + wk)), where the coupling reads it
+  auto to_lds = [&](typename Mfma<T>::acc (&out)[4], int z0, int wk) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int r = wave * 16 + Mfma<T>::row(lane, i);
+        if (r < wk) zs[(z0 + r) * kLeafLd + ct * 16 + c16] = out[ct][i];
+      }
+  };
+  auto add_lds = [&](typename Mfma<T>::acc (&cor)[4], int z0, int wk) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int r = wave * 16 + Mfma<T>::row(lane, i);
+        if (r < wk) zs[(z0 + r) * kLeafLd + ct * 16 + c16] += cor[ct][i];
+      }
+  };
+  typename Mfma<T>::acc out[4], cor[4];
+  if (!UPPER) {
+    half_inverse<T>(Inv0, zs, 0, w0, out);
+    store(out, 0, w0);
+    if (w1 > 0) {
+      __syncthreads();  // every wave has read Z0
+      to_lds(out, 0, w0);
+      __syncthreads();
+      half_couple<T>([&](int r) { return F + (size_t)perm[s + 64 + r] * N; }, w1, s, w0, zs, 0, cor);
+      add_lds(cor, 64, w1);
+      __syncthreads();
+      half_inverse<T>(Inv1, zs, 64, w1, out);
+      store(out, 64, w1);
+    }
+  } else {
+    if (w1 > 0) {
+      half_inverse<T>(Inv1, zs, 64, w1, out);
+      store(out, 64, w1);
+      __syncthreads();  // every wave has read Z1
+      to_lds(out, 64, w1);
+      __syncthreads();
+      half_couple<T>([&](int r) { return F + (size_t)perm[s + r] * N; }, w0, s + 64, w1, zs, 64, cor);
+      add_lds(cor, 0, w0);
+      __syncthreads();
+    }
+    half_inverse<T>(Inv0, zs, 0, w0, out);
+    store(out, 0, w0);
+  }
+}
+
+template <typename T, bool UPPER, bool SEG, int OCC>
+__global__ __launch_bounds__(256, OCC) void trsm_row128_kernel(Geom g, const T* F_all, const int* perm_all,
+                                                             const T* dinv_all, const T* B_all, T* Y_all, int s,
+                                                             int w, int nbox, int ntn, const int* active,
+                                                             double* X_all, int xmode, const int* kstart, int bdirect,
+                                                             const T* Y0_all) {
+  __shared__ T smem[smem128<T>()];
+  int box, tn;
+  if (!map_box_tile(nbox, ntn, box, tn)) return;
+  if (active && active[box] == 0) return;
+  const int N = g.n_pad;
+  const size_t xs = (size_t)N * g.ldx;
+  const T* Inv0 = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(s / kPanel) * 2 * 64 * 64 +
+                  (UPPER ? 64 * 64 : 0);
+  solve_block_row128<T, UPPER, SEG>(g, F_all + (size_t)box * N * N, perm_all + (size_t)box * N, Inv0,
+                                    Inv0 + 2 * 64 * 64, B_all + (size_t)box * xs, Y_all + (size_t)box * xs,
+                                    X_all ? X_all + (size_t)box * xs : nullptr, xmode, s, w, tn * 64,
+                                    kstart ? kstart[(size_t)box * ntn + tn] : 0, bdirect,
+                                    Y0_all ? Y0_all + (size_t)box * xs : nullptr, smem);
+}
+
 // One block row per launch: workgroup (box, 64-column tile).  OCC: waves per SIMD the
 // register allocation must allow (workgroups resident per CU, LDS permitting).
 template <typename T, bool UPPER, bool SEG, int OCC>
@@ -734,6 +956,39 @@ __global__ __launch_bounds__(256, OCC) void trsm_sweep_kernel(Geom g, const T* F
 }
 
 
+// The 128-row schedule of trsm_sweep_kernel: one workgroup per (box, 64-column tile) runs
+// every 128-row block row of its tile.
+template <typename T, bool UPPER, bool SEG, int OCC>
+__global__ __launch_bounds__(256, OCC) void trsm_sweep128_kernel(Geom g, const T* F_all, const int* perm_all,
+                                                               const T* dinv_all, const T* B_all, T* Y_all, int nbox,
+                                                               int ntn, const int* active, double* X_all, int xmode,
+                                                               const int* kstart, int bdirect, const T* Y0_all) {
+  __shared__ T smem[smem128<T>()];
+  int box, tn;
+  if (!map_box_tile(nbox, ntn, box, tn)) return;
+  if (active && active[box] == 0) return;
+  const int N = g.n_pad;
+  const size_t xs = (size_t)N * g.ldx;
+  const T* F = F_all + (size_t)box * N * N;
+  const int* perm = perm_all + (size_t)box * N;
+  const T* dinv = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (UPPER ? 64 * 64 : 0);
+  T* Y = Y_all + (size_t)box * xs;
+  const T* B = B_all + (size_t)box * xs;
+  double* Xb = X_all ? X_all + (size_t)box * xs : nullptr;
+  const T* Y0 = Y0_all ? Y0_all + (size_t)box * xs : nullptr;
+  const int nblk = (N + kBlockRows - 1) / kBlockRows;
+  const int ks = kstart ? kstart[(size_t)box * ntn + tn] : 0;
+#pragma unroll 1
+  for (int q = 0; q < nblk; q++) {
+    const int jb = UPPER ? nblk - 1 - q : q;
+    const int s = jb * kBlockRows, w = (N - s) < kBlockRows ? (N - s) : kBlockRows;
+    const T* Inv0 = dinv + (size_t)(s / kPanel) * 2 * 64 * 64;
+    solve_block_row128<T, UPPER, SEG>(g, F, perm, Inv0, Inv0 + 2 * 64 * 64, B, Y, Xb, xmode, s, w, tn * 64, ks,
+                                      bdirect, Y0, smem);
+    __syncthreads();  // Y_j stored before the next block row loads it
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host-side sequencing
 // ---------------------------------------------------------------------------
@@ -822,16 +1077,26 @@ static hipError_t launch_sweep(const Geom& g, const T* F, const int* perm, const
                                const int* active, hipStream_t st, double* X, int xmode, int sched,
                                const int* kstart, int bdirect, const T* Y0) {
   const int ntn = g.ldx / 64, N = g.n_pad;
+  constexpr bool R128 = solve_block_rows<T>() == kBlockRows;
   if (sched == kTrsmSweep) {
-    hipLaunchKernelGGL((trsm_sweep_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F,
-                       perm, dinv, B, Y, nbox, ntn, active, X, xmode, kstart, bdirect, Y0);
+    if constexpr (R128)
+      hipLaunchKernelGGL((trsm_sweep128_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g,
+                         F, perm, dinv, B, Y, nbox, ntn, active, X, xmode, kstart, bdirect, Y0);
+    else
+      hipLaunchKernelGGL((trsm_sweep_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F,
+                         perm, dinv, B, Y, nbox, ntn, active, X, xmode, kstart, bdirect, Y0);
     return hipGetLastError();
   }
-  const int nblk = (N + kPanel - 1) / kPanel;
+  constexpr int BR = solve_block_rows<T>();
+  const int nblk = (N + BR - 1) / BR;
   for (int q = 0; q < nblk; q++) {
-    const int s = (UPPER ? nblk - 1 - q : q) * kPanel, w = (N - s) < kPanel ? (N - s) : kPanel;
-    hipLaunchKernelGGL((trsm_row_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F,
-                       perm, dinv, B, Y, s, w, nbox, ntn, active, X, xmode, kstart, bdirect, Y0);
+    const int s = (UPPER ? nblk - 1 - q : q) * BR, w = (N - s) < BR ? (N - s) : BR;
+    if constexpr (R128)
+      hipLaunchKernelGGL((trsm_row128_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g,
+                         F, perm, dinv, B, Y, s, w, nbox, ntn, active, X, xmode, kstart, bdirect, Y0);
+    else
+      hipLaunchKernelGGL((trsm_row_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g, F,
+                         perm, dinv, B, Y, s, w, nbox, ntn, active, X, xmode, kstart, bdirect, Y0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -866,7 +1131,7 @@ template <typename T>
 hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, const T* B, T* Y, int nbox,
                      const int* active, hipStream_t st, Profiler* prof, double* X, int xmode, int sched, int waves,
                      const int* kstart, int bdirect, const T* Y0, const SolveFlops* sf) {
-  const int nlaunch = sched == kTrsmSweep ? 1 : (g.n_pad + kPanel - 1) / kPanel;
+  const int nlaunch = sched == kTrsmSweep ? 1 : (g.n_pad + solve_block_rows<T>() - 1) / solve_block_rows<T>();
   const double alg = sf ? sf->alg : 0.0;
   hipError_t e;
   {
