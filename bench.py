@@ -411,7 +411,7 @@ def main():
     solve_alg = (fams["solve_fwd"]["flops"] + fams["solve_bwd"]["flops"]) / a.steps
     solve_exec = (fams["solve_fwd"]["exec_flops"] + fams["solve_bwd"]["exec_flops"]) / a.steps
     tot_flops = lu_alg + solve_alg
-    KNAMES = {"solve_fwd": "trsm_row_kernel<float, false, false, 4>", "solve_bwd": "trsm_row_kernel<float, true, false, 4>",
+    KNAMES = {"solve_fwd": "trsm_row128_kernel<float, false, false, 4>", "solve_bwd": "trsm_row128_kernel<float, true, false, 4>",
               "lu_gemm": "gemm_op_kernel<float, true>", "lu_panel": "lu_panel_kernel<float, 6, 16, 64>",
               "residual": "residual_mfma_kernel<14, 2, 8, double>"}
     # the LU/TRSM phase: device time of the factorization and solve kernels (events around
