@@ -307,7 +307,7 @@ hps_status hps_front_solve(hps_front_plan plan, int32_t nfront, const double* F,
  *     at 4; the value is accepted and ignored there.
  *   HPS_TUNE_RESIDUAL_COLS: the FP64 refinement residual of FP32_IR plans (the
  *     Alg. 1 solves, refined), 6 <= p <= 18: right-hand-side columns per workgroup,
- *     8 (1024 threads, default) or 4 (512 threads, two workgroups per CU).  Other p
+ *     4 (512 threads, two workgroups per CU, default) or 8 (1024 threads).  Other p
  *     use one kernel and ignore the value.
  * set: HPS_EINVAL for an unknown key or value (the plan is left unchanged);
  * get: writes the current value to *value. */

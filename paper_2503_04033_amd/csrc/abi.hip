@@ -15,7 +15,7 @@ struct hps_plan_s {
   hps_leaf_desc desc;
   hps::Geom g;
   int device;
-  double* tables;  // device: t[p], D[p*p], D2[p*p]
+  double* tables;  // device: t[p], D[p*p], D2[p*p], s2z D2[p*p]
   int* coords;     // device: interior node coordinates (packed)
   std::vector<int> lu_ops;  // LU schedule (records of 8 ints)
   std::vector<int> gmap_h;  // host copy of g.gmap (internal -> natural 16-column group)
@@ -23,7 +23,7 @@ struct hps_plan_s {
   const double* t;
   int trsm_sched = hps::kTrsmRows;             // HPS_TUNE_TRSM_SCHEDULE
   int trsm_waves = 4;                          // HPS_TUNE_TRSM_WAVES
-  int res_cols = 8;                            // HPS_TUNE_RESIDUAL_COLS
+  int res_cols = 4;                            // HPS_TUNE_RESIDUAL_COLS
   void* scratch = nullptr;                     // this device's address of `scratch` (below)
 };
 
@@ -269,6 +269,7 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
   all.insert(all.end(), t.begin(), t.end());
   all.insert(all.end(), D.begin(), D.end());
   all.insert(all.end(), D2.begin(), D2.end());
+  for (double v : D2) all.push_back(g.s2[2] * v);  // s2z D2: the z-derivative coefficients
   if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return HPS_EDEVICE; }
   if (hipMalloc(&pl->tables, all.size() * sizeof(double)) != hipSuccess) { delete pl; return HPS_ENOMEM; }
   if (hipMemcpy(pl->tables, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
@@ -279,6 +280,7 @@ hps_status hps_plan_create(hps_plan* out, const hps_leaf_desc* d) {
   pl->t = pl->tables;
   g.D = pl->tables + g.p;
   g.D2 = pl->tables + g.p + (size_t)g.p * g.p;
+  g.D2z = g.D2 + (size_t)g.p * g.p;
   const int ngrp = g.ldx / 16;
   std::vector<int> coords(g.n + 2 * (size_t)ngrp);
   for (int node = 0; node < g.n; node++)
@@ -435,6 +437,8 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
     HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
     const int kmax = pl->desc.ir_max_iter;
     const double tol = pl->desc.ir_tol;
+    // After a correction most boxes pass the test, so the residual is first formed for the
+    // test alone (no R32); the boxes still above the tolerance form it again with R32.
     for (int it = 0; it <= kmax; it++) {
       const int last = it == kmax;
       {
@@ -443,13 +447,18 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
           HPS_TRY(hps::launch_residual<float>(g, nbox, b, f, L.Y32, B, L.pos, L.maxr, L.maxx, L.active, st,
                                               pl->res_cols));
         else
-          HPS_TRY(hps::launch_residual<double>(g, nbox, b, f, X, B, L.pos, L.maxr, L.maxx, L.active, st,
+          HPS_TRY(hps::launch_residual<double>(g, nbox, b, f, X, nullptr, nullptr, L.maxr, L.maxx, L.active, st,
                                                pl->res_cols));
       }
       HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
                                    st));
       if (it == 0) HPS_TRY(hps::launch_x_from_y(g, nbox, L.Y32, X, L.active, st));  // boxes done after 0 steps
       if (last) break;
+      if (it > 0) {
+        hps::ProfScope ps(&pl->prof, hps::Profiler::kResidual, 0.0, st);
+        HPS_TRY(hps::launch_residual<double>(g, nbox, b, f, X, B, L.pos, L.maxr, L.maxx, L.active, st,
+                                             pl->res_cols));
+      }
       hps::SolveFlops sfc{};
       if (pl->prof.on) sfc = solve_flops(pl, nbox, nullptr, L.active, st);
       HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, B, nbox, L.active, st, &pl->prof, X, it == 0 ? 3 : 2,

@@ -156,6 +156,7 @@ struct Geom {
   double kappa2;   // kappa^2
   const double* D;     // [p][p] Gauss-Lobatto differentiation matrix on [-1,1]
   const double* D2;    // [p][p] D*D
+  const double* D2z;   // [p][p] s2[2] D*D
   const int* coords;   // [n] interior node -> ii | jj << 8 | kk << 16
   // Right-hand-side columns inside the solves (B, Y, the FP32 residual) are kept in 16-column
   // groups in an internal order; X and everything outside the solves use the natural one.

@@ -419,9 +419,16 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox,
 // 16x16x4 FP64 MFMA chains into one 16x16 accumulator (rows ii, columns jj, zero
 // padded), by the wave that owns slab kk.  The z-derivative couples slabs: as each slab
 // q arrives every wave adds D2i[kk][q] X[.., q] to its accumulators of its slabs kk
-// (VALU).  X, b and f are read once: branch-free 8-byte loads run PD slabs ahead in
-// registers and pass through two LDS slab buffers.  R32 is written through LDS in
-// row segments of CB floats.
+// (VALU).
+// Column blocks run in the solves' internal column order (the order of the FP32 X and of
+// R32), so the CB columns of a block are one contiguous row segment of X and of R32 and
+// the blocks that share a 128-byte line are neighbours in the launch.  X is read once, in
+// two-element row segments (8 or 16 bytes, so that most threads of the workgroup load)
+// held PD slabs deep in registers (the bytes in flight that keep a CU streaming), then
+// converted into one of two LDS slab buffers; b (and f, in the block
+// that holds the load column) is staged in LDS once.  R32 may be null (check only: max
+// |R| and max |X| per box); otherwise it is written through LDS in row segments of CB
+// floats.
 constexpr int kRmLd = 17;                // row stride of a 16x16 slab tile in LDS
 constexpr int kRmTile = 16 * kRmLd + 4;  // doubles per tile plane
 
@@ -442,61 +449,111 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
   constexpr int m = M, mm = M * M;
   constexpr int kRmThreads = 64 * CB * NW;
   constexpr int H = (M + NW - 1) / NW;        // output slabs per wave
-  constexpr int PLANES = CB + 2;              // CB columns of X, then b and f
-  constexpr int BUF = PLANES * kRmTile;       // one slab buffer
-  constexpr int DISCARD = 2 * BUF;            // write slot of idle staging tasks
-  constexpr int NTK = ((CB + 2) * mm + kRmThreads - 1) / kRmThreads;  // staging tasks per thread
-  constexpr int PD = (NTK >= 3 || H >= 7) ? 2 : 3;  // slabs in flight
-  static_assert(16 % NW == 0 && 4 * mm * CB <= 2 * BUF * 2, "output staging must fit the slab buffers");
-  __shared__ double sm[2 * BUF + 2];
-  __shared__ double tz[16 * 16];     // s2z * D2i[kk][q] at [q][kk]
+  constexpr int VX = 2;                       // X elements per load (8 or 16 bytes)
+  constexpr int XT = CB / VX;                 // loads per row of the column block
+  constexpr int NX = mm * XT;                 // loads per slab
+  constexpr int NTK = (NX + kRmThreads - 1) / kRmThreads;  // loads per thread and slab
+  // slabs in flight: as deep as the registers left by the accumulators allow (no spills)
+  constexpr int PD0 = NTK > 1 ? 2 : (sizeof(TX) == 4 ? (M == 15 ? 4 : 8) : (M == 15 ? 2 : 4));
+  constexpr int PD = PD0 < M ? PD0 : M;
+  constexpr int BUF = CB * kRmTile;           // one slab buffer
+  static_assert(CB % VX == 0 && 16 % CB == 0, "a column block is whole load segments of one 16-column group");
+  static_assert(4 * mm * CB <= 2 * BUF * 2, "output staging must fit the slab buffers");
+  using V = TX __attribute__((ext_vector_type(VX)));
+  __shared__ double sm[2 * BUF];
+  __shared__ double sb[M * M * M];   // kappa^2 b of the box
+  __shared__ double sf[M * M * M];   // f of the box (the block with the load column only)
   __shared__ double te[2 * 16];      // D2[i+1][0] and D2[i+1][p-1]
-  __shared__ double td[2][16 * 16];  // s2x D2i and s2y D2i at [k][l], zero padded (MFMA operands)
   __shared__ int spos[M * M * M];    // R32 row of each node (pos, or the node itself)
   int box, cb;
   if (!map_box_chunk(nbox, ncb, box, cb)) return;
-  if (active && active[box] == 0) return;
   const int p = g.p, ldx = g.ldx;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the wave index in a scalar register: everything derived from it (column, run of slabs,
+  // the column's face) stays scalar and its branches are scalar branches
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wc = w % CB, part = w / CB;  // column within the block, run of slabs
-  const int c0 = cb * CB, col = c0 + wc;
+  const int c0 = cb * CB;                // first internal column of the block
+  const int col = rhs_ncol(g, c0 + wc);  // this wave's natural column
   const int lr = lane >> 4, lc = lane & 15;
-  const TX* X = X_all + (size_t)box * g.n_pad * ldx;
+  // the FP32 X is the solves' buffer (internal column order); an FP64 X has the natural order
+  const TX* X = X_all + (size_t)box * g.n_pad * ldx + (sizeof(TX) == 4 ? c0 : rhs_ncol(g, c0));
   const int* pos = pos_all ? pos_all + (size_t)box * g.n_pad : nullptr;
   const double* bb = b + (size_t)box * g.n;
-  const double* fb = f ? f + (size_t)box * g.n : bb;
-  for (int e = threadIdx.x; e < 2 * BUF + 2; e += kRmThreads) sm[e] = 0.0;
-  for (int e = threadIdx.x; e < m * mm; e += kRmThreads) spos[e] = pos ? pos[e] : e;
-  for (int e = threadIdx.x; e < mm; e += kRmThreads) tz[(e % m) * 16 + e / m] = g.s2[2] * g.D2[(e / m + 1) * p + e % m + 1];
-  for (int e = threadIdx.x; e < 2 * m; e += kRmThreads) te[e] = g.D2[(e % m + 1) * p + (e < m ? 0 : p - 1)];
-  for (int e = threadIdx.x; e < 256; e += kRmThreads) {
-    const int l = e & 15, k = e >> 4;
-    const double d = (l < m && k < m) ? g.D2[(l + 1) * p + k + 1] : 0.0;
-    td[0][e] = g.s2[0] * d;
-    td[1][e] = g.s2[1] * d;
-  }
-  // Staging task t of a slab: t < CB m^2 is X[row t / CB][c0 + t % CB], then b, then f,
-  // stored at tile [ii][jj] of their plane; other tasks reread X[0] and discard it.  Only
-  // the element offset is kept per task; kind, slab address and LDS slot are recomputed
-  // (cheap integer work) to leave the registers to the accumulators.
-  auto task_kind = [&](int s) {
-    const int t = threadIdx.x + s * kRmThreads;
-    return t < CB * mm ? 0 : (t < (CB + 1) * mm ? 1 : ((t < (CB + 2) * mm && f) ? 2 : 3));
-  };
-  auto task_loff = [&](int s) {
-    const int t = threadIdx.x + s * kRmThreads, k = task_kind(s);
-    const int r = k == 0 ? t / CB : t - (k == 1 ? CB : CB + 1) * mm;
-    const int plane = k == 0 ? t % CB : (k == 1 ? CB : CB + 1);
-    return k == 3 ? DISCARD : plane * kRmTile + (r % m) * kRmLd + r / m;
-  };
-  int off[NTK];
+  const bool fblock = f && rhs_icol(g, g.nb) / CB == cb;
+  // (the column-map loads above and this one are in flight together)
+  if (active && active[box] == 0) return;
+  // Load task t = threadIdx.x + s * threads (t < NX) of a slab: row t / XT, elements
+  // VX (t % XT) ..+VX-1 of the block; xo = offset in the slab, lo = LDS slot of its first
+  // element (tile [ii][jj] of plane VX (t % XT)).  Loads and LDS stores are branch-free
+  // (a load under a branch costs the wait for every load in flight): threads without a
+  // task reload row 0 of the slab (a cached line) and store into column 16 of a tile,
+  // which no reader touches.
+  int xo[NTK], lo[NTK];
 #pragma unroll
   for (int s = 0; s < NTK; s++) {
-    const int t = threadIdx.x + s * kRmThreads, k = task_kind(s);
-    // an FP32 X is the solve buffer: its columns are in the internal order
-    const int xc = sizeof(TX) == 4 ? rhs_icol(g, c0 + t % CB) : c0 + t % CB;
-    off[s] = k == 0 ? (t / CB) * ldx + xc : (k == 1 ? t - CB * mm : (k == 2 ? t - (CB + 1) * mm : 0));
+    const int t = threadIdx.x + s * kRmThreads;
+    const int r = t / XT, h = t % XT;
+    xo[s] = t < NX ? r * ldx + h * VX : 0;
+    lo[s] = t < NX ? (h * VX) * kRmTile + (r % m) * kRmLd + r / m : (lane & 15) * kRmLd + 16;
   }
+  V pf[PD][NTK];
+  auto fetch = [&](int q, int slot) {
+    const TX* Xq = X + (size_t)q * mm * ldx;
+#pragma unroll
+    for (int s = 0; s < NTK; s++) pf[slot][s] = *reinterpret_cast<const V*>(Xq + xo[s]);
+  };
+  auto stash = [&](int buf, int slot) {
+#pragma unroll
+    for (int s = 0; s < NTK; s++)
+#pragma unroll
+      for (int e = 0; e < VX; e++) sm[buf * BUF + lo[s] + e * kRmTile] = (double)pf[slot][s][e];
+  };
+  // The global loads of b, f, the R32 row positions and the operator tables are issued
+  // together and branch-free (one wait, not one per loop trip), ahead of the slab loads;
+  // their values go to LDS after the slab loads are on their way.
+  constexpr int NB = (M * M * M + kRmThreads - 1) / kRmThreads;
+  static_assert(2 * M <= kRmThreads, "one table entry per thread");
+  const double* fsrc = fblock ? f + (size_t)box * g.n : bb;  // (b: a valid, cached stand-in)
+  const int* psrc = pos ? pos : g.coords;
+  double rb[NB], rf[NB];
+  int rp[NB];
+#pragma unroll
+  for (int k = 0; k < NB; k++) {
+    const int e = threadIdx.x + k * kRmThreads, ec = e < m * mm ? e : 0;
+    rb[k] = bb[ec];
+    rf[k] = fsrc[ec];
+    const int pv = psrc[ec];
+    rp[k] = pos ? pv : ec;
+  }
+  const int e0 = threadIdx.x;
+  const double re = g.D2[e0 < 2 * m ? (e0 % m + 1) * p + (e0 < m ? 0 : p - 1) : 0];
+  // MFMA operand of both derivative terms, kept in registers: lane (lr, lc) holds, for k
+  // chunk kb, s2x D2[lc+1][lr+4kb+1] (zero outside m x m).  It is the A operand of the
+  // x term D2i S and, with the ratio s2y / s2x moved onto S, the B operand of the y term
+  // S D2i^T.
+  double dreg[4];
+#pragma unroll
+  for (int kb = 0; kb < 4; kb++) {
+    const bool in = lc < m && lr + 4 * kb < m;
+    const double v = g.D2[in ? (lc + 1) * p + lr + 4 * kb + 1 : 0];
+    dreg[kb] = in ? g.s2[0] * v : 0.0;
+  }
+  // (the slab loads stay behind these in issue order, so the wait for the values above
+  // does not also wait for the slabs)
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < PD; q++) fetch(q, q);
+  for (int e = threadIdx.x; e < 2 * BUF; e += kRmThreads) sm[e] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NB; k++) {
+    const int e = threadIdx.x + k * kRmThreads;
+    if (e < m * mm) {
+      sb[e] = g.kappa2 * rb[k];
+      sf[e] = rf[k];
+      spos[e] = rp[k];
+    }
+  }
+  if (e0 < 2 * m) te[e0] = re;
   // This wave's column of [A_ib | f].  A_ib column col is nonzero on the normal line of
   // face node (la, lb); bit i of emask marks this lane's node (lr + 4i, lc) on it, whose
   // entry is -s2[axis] D2[t+1][edge] with t the node's coordinate along the axis.
@@ -509,53 +566,29 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
     lb = qq / m;
   }
   const bool fcol = (col == g.nb) && f;
-  int emask = 0;
+  int emask = 0, inb = 0;  // inb: bit i marks node (lr + 4i, lc) inside the m x m slab
 #pragma unroll
   for (int i = 0; i < 4; i++) {
     const int ii = lr + 4 * i;
     bool on = false;
     if (ii < m && lc < m) {
+      inb |= 1 << i;
       if (axis == 0) on = lc == la;
       else if (axis == 1) on = ii == la;
       else if (axis == 2) on = ii == la && lc == lb;
     }
     emask |= on ? (1 << i) : 0;
   }
-  const double s2a = axis >= 0 ? -g.s2[axis] : 0.0;
-  const double* tes = te + side * m;
-  double pf[PD][NTK];
-  auto fetch = [&](int q, int slot) {
-    const size_t xq = (size_t)q * mm * ldx;
-#pragma unroll
-    for (int s = 0; s < NTK; s++) {
-      const int k = task_kind(s);
-      if constexpr (sizeof(TX) == 8) {
-        const double* base = k == 0 ? X + xq : (k == 1 ? bb + q * mm : (k == 2 ? fb + q * mm : X));
-        pf[slot][s] = base[k == 3 ? 0 : off[s]];
-      } else {  // FP32 X: both loads issued, the task's kind picks one (no branch around loads)
-        const float xv = X[k == 0 ? xq + off[s] : 0];
-        const double* base = k == 1 ? bb + q * mm : (k == 2 ? fb + q * mm : bb);
-        const double dv = base[(k == 1 || k == 2) ? off[s] : 0];
-        pf[slot][s] = k == 0 ? (double)xv : dv;
-      }
-    }
-  };
-  auto stash = [&](int buf, int slot) {
-#pragma unroll
-    for (int s = 0; s < NTK; s++) {
-      const int lo = task_loff(s);
-      sm[lo == DISCARD ? DISCARD : buf * BUF + lo] = pf[slot][s];
-    }
-  };
-#pragma unroll
-  for (int q = 0; q < PD && q < m; q++) fetch(q, q);
+  // (selects, not g.s2[axis]: a per-lane index into the argument block is a vector load,
+  // whose wait would also wait for the slab loads above)
+  const double s2a = axis == 0 ? -g.s2[0] : (axis == 1 ? -g.s2[1] : (axis == 2 ? -g.s2[2] : 0.0));
+  const double ry = g.s2[1] / g.s2[0];
   __syncthreads();  // zero fill and tables done
   stash(0, 0);
   d4 acc[H];
 #pragma unroll
   for (int k = 0; k < H; k++) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
   double mxv = 0.0;
-  const double k2 = g.kappa2;
 #pragma unroll
   for (int q = 0; q < m; q++) {
     __builtin_amdgcn_sched_barrier(0);  // keep each slab's work (and its registers) in place
@@ -570,47 +603,61 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
     for (int pt = 0; pt < NW; pt++) {
       if (part != pt) continue;  // wave-uniform: one static copy per run of slabs
       if (q >= pt * H && q < (pt + 1) * H) {
-        // x- and y-derivative terms of slab q, the diagonal term and the [A_ib | f] entries
-        const double* Sb = S + CB * kRmTile;
-        const double* Sf = Sb + kRmTile;
-        double ay[4], bv[4], fv[4];
+        // x- and y-derivative terms of slab q, the diagonal term and the load column
+        double ay[4];
 #pragma unroll
-        for (int kb = 0; kb < 4; kb++) {
-          ay[kb] = Sc[lc * kRmLd + lr + 4 * kb];
-          bv[kb] = Sb[(lr + 4 * kb) * kRmLd + lc];
-          fv[kb] = fcol ? Sf[(lr + 4 * kb) * kRmLd + lc] : 0.0;
-        }
+        for (int kb = 0; kb < 4; kb++) ay[kb] = ry * Sc[lc * kRmLd + lr + 4 * kb];
         d4 a = acc[q - pt * H];
 #pragma unroll
-        for (int kb = 0; kb < 4; kb++)
-          a = __builtin_amdgcn_mfma_f64_16x16x4f64(td[0][(lr + 4 * kb) * 16 + lc], bx[kb], a, 0, 0, 0);
+        for (int kb = 0; kb < 4; kb++) a = __builtin_amdgcn_mfma_f64_16x16x4f64(dreg[kb], bx[kb], a, 0, 0, 0);
 #pragma unroll
-        for (int kb = 0; kb < 4; kb++)
-          a = __builtin_amdgcn_mfma_f64_16x16x4f64(ay[kb], td[1][(lr + 4 * kb) * 16 + lc], a, 0, 0, 0);
-        const bool eslab = axis == 2 || q == lb;
+        for (int kb = 0; kb < 4; kb++) a = __builtin_amdgcn_mfma_f64_16x16x4f64(ay[kb], dreg[kb], a, 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-          const double ev = tes[axis == 0 ? lr + 4 * i : (axis == 1 ? lc : q)];
-          double r = k2 * bv[i] * bx[i] + fv[i];
-          r += (eslab && ((emask >> i) & 1)) ? s2a * ev : 0.0;
-          a[i] += r;
+          // (lanes outside the m x m slab hold X = 0: any node of the box serves there)
+          const int node = q * mm + ((inb >> i) & 1 ? lr + 4 * i + m * lc : 0);
+          a[i] += sb[node] * bx[i];
+        }
+        if (fcol) {
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+            if ((inb >> i) & 1) a[i] += sf[q * mm + lr + 4 * i + m * lc];
         }
         acc[q - pt * H] = a;
 #pragma unroll
         for (int i = 0; i < 4; i++) mxv = fmax(mxv, fabs(bx[i]));
       }
-      // z-derivative: slab q feeds this wave's slabs kk
+      // z-derivative: slab q feeds this wave's slabs kk (coefficients s2z D2i[kk][q]
+      // through the scalar cache: their address is the same in every lane)
 #pragma unroll
       for (int k = 0; k < H; k++) {
         const int kk = pt * H + k;
         if (kk < m) {
-          const double cz = wave_uniform(tz[q * 16 + kk]);
+          const double cz = g.D2z[(kk + 1) * p + q + 1];
 #pragma unroll
           for (int i = 0; i < 4; i++) acc[k][i] += cz * bx[i];
         }
       }
     }
     if (q + 1 < m) stash((q + 1) & 1, (q + 1) % PD);
+  }
+  // A_ib column: -s2[axis] D2[t+1][edge] on the normal line of face node (la, lb), t the
+  // node's coordinate along the axis
+#pragma unroll
+  for (int pt = 0; pt < NW; pt++) {
+    if (part != pt) continue;
+#pragma unroll
+    for (int k = 0; k < H; k++) {
+      const int kk = pt * H + k;
+      if (kk < m) {
+        const bool eslab = axis == 2 || kk == lb;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const double ev = te[side * m + (axis == 0 ? (lr + 4 * i < m ? lr + 4 * i : 0) : (axis == 1 ? lc % m : kk))];
+          acc[k][i] += (eslab && ((emask >> i) & 1)) ? s2a * ev : 0.0;
+        }
+      }
+    }
   }
   // max |R| (entries outside the m x m tile are exactly zero), then R32 through LDS,
   // four slabs at a time
@@ -621,7 +668,7 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
     for (int i = 0; i < 4; i++) mr = fmax(mr, fabs(acc[k][i]));
   if (R32_all) {
     float* O = reinterpret_cast<float*>(sm);  // [4 slabs][m^2 rows][CB]
-    float* R32 = R32_all + (size_t)box * g.n_pad * ldx;
+    float* R32 = R32_all + (size_t)box * g.n_pad * ldx + c0;
 #pragma unroll
     for (int k0 = 0; k0 < m; k0 += 4) {
       __syncthreads();  // LDS free (slab reads or the previous group's stores done)
@@ -641,12 +688,12 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
         }
       }
       __syncthreads();
-      constexpr int V = CB / 4;  // float4 per row segment
+      constexpr int V4 = CB / 4;  // float4 per row segment
       const int nk = (m - k0) < 4 ? (m - k0) : 4;
-      for (int t = threadIdx.x; t < nk * mm * V; t += kRmThreads) {
-        const int row = t / V, h = t % V;  // row = (slab - k0) * m^2 + r
+      for (int t = threadIdx.x; t < nk * mm * V4; t += kRmThreads) {
+        const int row = t / V4, h = t % V4;  // row = (slab - k0) * m^2 + r
         const f4 v = *reinterpret_cast<const f4*>(O + row * CB + 4 * h);
-        *reinterpret_cast<f4*>(R32 + (size_t)spos[k0 * mm + row] * ldx + rhs_icol(g, c0) + 4 * h) = v;
+        *reinterpret_cast<f4*>(R32 + (size_t)spos[k0 * mm + row] * ldx + 4 * h) = v;
       }
     }
   }
@@ -677,8 +724,10 @@ template <int NW, int CB, typename TX>
 static hipError_t launch_residual_mfma(const Geom& g, int nbox, int grid_boxes, const double* b, const double* f,
                                        const TX* X, float* R32, const int* pos, double* maxr, double* maxx,
                                        const int* active, hipStream_t st) {
-  // column blocks past the f column hold zeros in X and in R32 (left as the caller wrote them)
-  const int ncb = (g.nb + 1 + CB - 1) / CB;
+  // column blocks run over the internal order's 16-column groups that hold natural columns
+  // 0..nb (they come first); later groups hold zeros in X and in R32 (left as the caller
+  // wrote them)
+  const int ncb = 16 * ((g.nb + 1 + 15) / 16) / CB;
   const dim3 grid(grid_boxes * ncb), block(64 * CB * NW);
   switch (g.m) {
 #define HPS_RES_CASE(M)                                                                                        \
