@@ -309,9 +309,18 @@ hps_status hps_front_solve(hps_front_plan plan, int32_t nfront, const double* F,
  *     Alg. 1 solves, refined), 6 <= p <= 18: right-hand-side columns per workgroup,
  *     4 (512 threads, two workgroups per CU, default) or 8 (1024 threads).  Other p
  *     use one kernel and ignore the value.
+ *   HPS_TUNE_PANEL_THREADS: FP32_IR plans whose padded interior size is 2049..3072
+ *     (p = 15, 16): threads of the pivoted panel factorization of hps_leaf_factor,
+ *     512 (six rows per thread) or 1024 (default: three rows per thread, four waves
+ *     per SIMD).  Other plans accept the value and use 512.
  * set: HPS_EINVAL for an unknown key or value (the plan is left unchanged);
  * get: writes the current value to *value. */
-typedef enum { HPS_TUNE_TRSM_SCHEDULE = 0, HPS_TUNE_TRSM_WAVES = 1, HPS_TUNE_RESIDUAL_COLS = 2 } hps_tuning_key;
+typedef enum {
+  HPS_TUNE_TRSM_SCHEDULE = 0,
+  HPS_TUNE_TRSM_WAVES = 1,
+  HPS_TUNE_RESIDUAL_COLS = 2,
+  HPS_TUNE_PANEL_THREADS = 3
+} hps_tuning_key;
 hps_status hps_plan_set_tuning(hps_plan plan, int32_t key, int32_t value);
 hps_status hps_plan_get_tuning(hps_plan plan, int32_t key, int32_t* value);
 

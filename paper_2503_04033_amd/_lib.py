@@ -24,9 +24,9 @@ EXPORTS = (
 # HPS_NOALLOC_SCRATCH_BYTES: the fixed scratch of hps_leaf_interior_solve_noalloc
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
-HPS_TUNE_TRSM_SCHEDULE, HPS_TUNE_TRSM_WAVES, HPS_TUNE_RESIDUAL_COLS = 0, 1, 2
+HPS_TUNE_TRSM_SCHEDULE, HPS_TUNE_TRSM_WAVES, HPS_TUNE_RESIDUAL_COLS, HPS_TUNE_PANEL_THREADS = 0, 1, 2, 3
 TUNING_KEYS = {"trsm_schedule": HPS_TUNE_TRSM_SCHEDULE, "trsm_waves": HPS_TUNE_TRSM_WAVES,
-               "residual_cols": HPS_TUNE_RESIDUAL_COLS}
+               "residual_cols": HPS_TUNE_RESIDUAL_COLS, "panel_threads": HPS_TUNE_PANEL_THREADS}
 
 PROFILE_FAMILIES = ("lu_gemm", "lu_panel", "lu_leaf", "solve_fwd", "solve_bwd", "residual", "dtn", "operators")
 

@@ -24,6 +24,7 @@ struct hps_plan_s {
   int trsm_sched = hps::kTrsmRows;             // HPS_TUNE_TRSM_SCHEDULE
   int trsm_waves = 4;                          // HPS_TUNE_TRSM_WAVES
   int res_cols = 4;                            // HPS_TUNE_RESIDUAL_COLS
+  int panel_threads = 1024;                    // HPS_TUNE_PANEL_THREADS
   void* scratch = nullptr;                     // this device's address of `scratch` (below)
 };
 
@@ -387,7 +388,7 @@ hps_status hps_leaf_factor(hps_plan pl, int32_t nbox, void* A, int32_t* perm, vo
   if (nbox == 0) return HPS_OK;
   if (pl->desc.precision == HPS_FP32_IR)
     return dev(hps::getrf_run<float>(pl->g, pl->lu_ops, static_cast<float*>(A), perm, static_cast<float*>(dinv),
-                                     info, nbox, st, &pl->prof));
+                                     info, nbox, st, &pl->prof, -1, pl->panel_threads));
   return dev(hps::getrf_run<double>(pl->g, pl->lu_ops, static_cast<double*>(A), perm, static_cast<double*>(dinv),
                                     info, nbox, st, &pl->prof));
 }
@@ -603,6 +604,10 @@ hps_status hps_plan_set_tuning(hps_plan pl, int32_t key, int32_t value) {
     pl->res_cols = value;
     return HPS_OK;
   }
+  if (key == HPS_TUNE_PANEL_THREADS && (value == 512 || value == 1024)) {
+    pl->panel_threads = value;
+    return HPS_OK;
+  }
   return HPS_EINVAL;
 }
 
@@ -618,6 +623,10 @@ hps_status hps_plan_get_tuning(hps_plan pl, int32_t key, int32_t* value) {
   }
   if (key == HPS_TUNE_RESIDUAL_COLS) {
     *value = pl->res_cols;
+    return HPS_OK;
+  }
+  if (key == HPS_TUNE_PANEL_THREADS) {
+    *value = pl->panel_threads;
     return HPS_OK;
   }
   return HPS_EINVAL;

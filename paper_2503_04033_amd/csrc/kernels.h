@@ -88,10 +88,11 @@ struct ProfScope {
 // lu.hip: one kernel launch per schedule record (records of 8 ints, see common.h)
 // pivot_end >= 0: rows at positions >= pivot_end are never pivots (partial factorization of
 // an interface front; the schedule then stops after the pivot columns and its trailing
-// update); -1: every row may be a pivot.
+// update); -1: every row may be a pivot.  panel_threads: 512, or 1024 where a 1024-thread
+// panel kernel exists (FP32, 2049..3072 rows; elsewhere 512 is used).
 template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
-                     hipStream_t st, Profiler* prof, int pivot_end = -1);
+                     hipStream_t st, Profiler* prof, int pivot_end = -1, int panel_threads = 512);
 // Rows per block row of the triangular solves of getrs_run: 128 in FP32 (two 64-row LU
 // panels per launch), 64 in FP64.
 template <typename T>

@@ -40,12 +40,14 @@ constexpr int kLuThreads = 512;
 constexpr int kLuWaves = kLuThreads / 64;
 
 // Columns of a panel held in registers at a time: the widest of 32, 16, 8, 4 whose
-// ROWS x CW block takes at most 96 VGPRs (one 512-thread workgroup per CU keeps the
-// rest of the 256-register budget for the L values and the pivot row in flight).
-template <typename T, int ROWS>
+// ROWS x CW block takes at most 96 VGPRs with 512 threads (one workgroup per CU keeps the
+// rest of the 256-register budget for the L values and the pivot row in flight), 48 with
+// 1024 threads (128 registers per thread).
+template <typename T, int ROWS, int NT = 512>
 struct PanelChunk {
+  static constexpr int B = NT >= 1024 ? 48 : 96;
   static constexpr int regs(int cw) { return ROWS * cw * (int)(sizeof(T) / 4); }
-  static constexpr int CW = regs(32) <= 96 ? 32 : (regs(16) <= 96 ? 16 : (regs(8) <= 96 ? 8 : 4));
+  static constexpr int CW = regs(32) <= B ? 32 : (regs(16) <= B ? 16 : (regs(8) <= B ? 8 : 4));
 };
 
 // f(std::integral_constant<int, I>) for I = B .. E-1, expanded at compile time (indices into
@@ -62,7 +64,7 @@ __device__ __attribute__((always_inline)) inline void static_for(F&& f) {
 // diagonal block (positions [j0, j0+npv)), kept up to date after every chunk, so the U
 // rows of the earlier pivots in a new chunk are one parallel product and the
 // diagonal-block inverses needed by the solves come out at the end for free.
-template <typename T, int CW>
+template <typename T, int CW, int NWV>
 struct LuSmem {
   T M[64 * 65];
   T Nn[64 * 65];
@@ -72,11 +74,11 @@ struct LuSmem {
   T t1[CW * 64];           // lq * M
   T uq[CW * CW];           // inverse of the chunk pivots' CW x CW upper block
   T PR[CW * CW];           // the chunk's pivot rows in the chunk columns (L left, U on and right)
-  T wrow[2][kLuWaves][CW];
-  T wval[2][kLuWaves];
-  int wslot[2][kLuWaves];
+  T wrow[2][NWV][CW];
+  T wval[2][NWV];
+  int wslot[2][NWV];
   int pphys[64];           // physical row of the panel's k-th pivot
-  int cnt[24 * kLuWaves];  // per (row slot r < 24, wave): rows that stay candidates
+  int cnt[24 * NWV];  // per (row slot r < 24, wave): rows that stay candidates
 };
 
 template <typename T> struct Store4;
@@ -109,9 +111,9 @@ template <> struct Store4<double> {
 // starting slot.  Rows at positions >= pivot_end are eliminated like the others but never
 // become pivots (a partial factorization whose trailing block is a Schur complement).  At the end the pivots take positions j0.. in order and the other
 // rows follow in their previous order; M and Nn go to dinv_panel as Linv / Uinv.
-template <typename T, int ROWS, int CW, int W>
+template <typename T, int ROWS, int CW, int W, int NT>
 __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T* A, int* perm, int j0, int pivot_end,
-                                                               LuSmem<T, CW>& sm, int& info, T* dinv_panel) {
+                                                               LuSmem<T, CW, NT / 64>& sm, int& info, T* dinv_panel) {
   static_assert(W % CW == 0 && CW % 4 == 0, "chunks tile the panel");
   constexpr int LB = CW < 16 ? CW : 16;  // L values loaded per step of (b)
   const int N = g.n_pad, lda = N;
@@ -123,22 +125,21 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
   int pk[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; r++) {
-    const int s = tid + kLuThreads * r;
+    const int s = tid + NT * r;
     phys[r] = s < nrem ? perm[j0 + s] : 0;
     pk[r] = s < nrem ? (j0 + s < pivot_end ? -1 : -3) : -2;
   }
   for (int h = 0; h < W / CW; h++) {
     const int cb = j0 + h * CW;
     const int npv = h * CW;
+    // every slot loads (a slot with no row reads row phys = 0 and is never used): loads
+    // outside branches are waited for once, not one row at a time
     T v[ROWS][CW];
 #pragma unroll
     for (int r = 0; r < ROWS; r++) {
       const T* row = A + (size_t)phys[r] * lda + cb;
 #pragma unroll
-      for (int c = 0; c < CW; c += 4) {
-        if (pk[r] != -2) Vec4<T>::load(row + c, v[r] + c);
-        else v[r][c] = v[r][c + 1] = v[r][c + 2] = v[r][c + 3] = T(0);
-      }
+      for (int c = 0; c < CW; c += 4) Vec4<T>::load(row + c, v[r] + c);
     }
     if (npv > 0) {
       // (a)
@@ -148,7 +149,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
 #pragma unroll
           for (int c = 0; c < CW; c++) sm.stg[pk[r] * CW + c] = v[r][c];
       __syncthreads();
-      for (int e = tid; e < npv * CW; e += kLuThreads) {
+      for (int e = tid; e < npv * CW; e += NT) {
         const int k = e / CW, c = e - k * CW;
         T s = T(0);
         for (int i = 0; i <= k; i++) s += sm.M[k * 65 + i] * sm.stg[i * CW + c];
@@ -182,7 +183,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
         if (pk[r] == -1) {
           T a = fabs(v[r][c]);
           if (a != a) a = T(INFINITY);  // a NaN is taken as the pivot and flagged below
-          const int s = tid + kLuThreads * r;
+          const int s = tid + NT * r;
           if (a > best || (a == best && s < bslot)) { best = a; bslot = s; }
         }
       }
@@ -195,12 +196,12 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
       const int buf = c & 1;
       if (bslot == 0x7fffffff) {
         if (lane == 0) { sm.wval[buf][wave] = T(-1); sm.wslot[buf][wave] = bslot; }
-      } else if ((bslot & (kLuThreads - 1)) == tid) {
+      } else if ((bslot & (NT - 1)) == tid) {
         sm.wval[buf][wave] = best;
         sm.wslot[buf][wave] = bslot;
 #pragma unroll
         for (int r = 0; r < ROWS; r++)
-          if (r == bslot / kLuThreads)
+          if (r == bslot / NT)
 #pragma unroll
             for (int cc = 0; cc < CW; cc++) sm.wrow[buf][wave][cc] = v[r][cc];
       }
@@ -209,16 +210,16 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
       best = sm.wval[buf][0];
       bslot = sm.wslot[buf][0];
 #pragma unroll
-      for (int w = 1; w < kLuWaves; w++) {
+      for (int w = 1; w < (NT / 64); w++) {
         const T ob = sm.wval[buf][w];
         const int os = sm.wslot[buf][w];
         if (ob > best || (ob == best && os < bslot)) { best = ob; bslot = os; wbest = w; }
       }
       const T* pr = sm.wrow[buf][wbest];
-      if ((bslot & (kLuThreads - 1)) == tid) {
+      if ((bslot & (NT - 1)) == tid) {
 #pragma unroll
         for (int r = 0; r < ROWS; r++)
-          if (r == bslot / kLuThreads) {
+          if (r == bslot / NT) {
             pk[r] = npv + c;
             sm.pphys[npv + c] = phys[r];
           }
@@ -248,18 +249,18 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
     }
     __syncthreads();
     // (e) M <- [[M, 0], [-Lq^{-1} lq M, Lq^{-1}]],  Nn <- [[Nn, -Nn ub Uq^{-1}], [0, Uq^{-1}]]
-    for (int e = tid; e < CW * npv; e += kLuThreads) {
+    for (int e = tid; e < CW * npv; e += NT) {
       const int i = e / npv, k = e - i * npv;
       sm.lq[i * 64 + k] = A[(size_t)sm.pphys[npv + i] * lda + j0 + k];
     }
     __syncthreads();
-    for (int e = tid; e < CW * npv; e += kLuThreads) {
+    for (int e = tid; e < CW * npv; e += NT) {
       const int i = e / npv, j = e - i * npv;
       T s = T(0);
       for (int k = j; k < npv; k++) s += sm.lq[i * 64 + k] * sm.M[k * 65 + j];
       sm.t1[i * 64 + j] = s;
     }
-    for (int e = tid; e < npv * CW; e += kLuThreads) {
+    for (int e = tid; e < npv * CW; e += NT) {
       const int r = e / CW, c = e - r * CW;
       T s = T(0);
       for (int i = r; i < npv; i++) s += sm.Nn[r * 65 + i] * sm.ub[i * CW + c];
@@ -291,7 +292,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
       for (int i = 0; i < CW; i++) sm.uq[i * CW + j] = i <= j ? y[i] : T(0);
     }
     __syncthreads();
-    for (int e = tid; e < (npv + CW) * CW; e += kLuThreads) {
+    for (int e = tid; e < (npv + CW) * CW; e += NT) {
       const int r = e / CW, j = e - r * CW;
       T s;
       if (r < npv) {
@@ -312,7 +313,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
   for (int r = 0; r < ROWS; r++) {
     const unsigned long long mask = __ballot(pk[r] == -1 || pk[r] == -3);
     pre[r] = __popcll(mask & lt);
-    if (lane == 0) sm.cnt[r * kLuWaves + wave] = __popcll(mask);
+    if (lane == 0) sm.cnt[r * (NT / 64) + wave] = __popcll(mask);
   }
   __syncthreads();
   int base = j0 + W;
@@ -320,8 +321,8 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
   for (int r = 0; r < ROWS; r++) {
     int before = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kLuWaves; w++) {
-      const int cw = sm.cnt[r * kLuWaves + w];
+    for (int w = 0; w < (NT / 64); w++) {
+      const int cw = sm.cnt[r * (NT / 64) + w];
       tot += cw;
       if (w < wave) before += cw;
     }
@@ -331,7 +332,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
   if (tid < W) perm[j0 + tid] = sm.pphys[tid];
   T* Linv = dinv_panel;
   T* Uinv = dinv_panel + 64 * 64;
-  for (int e = tid; e < W * W; e += kLuThreads) {
+  for (int e = tid; e < W * W; e += NT) {
     const int i = e / W, k = e - i * W;
     Linv[i * 64 + k] = i > k ? sm.M[i * 65 + k] : (i == k ? T(1) : T(0));
     Uinv[i * 64 + k] = i <= k ? sm.Nn[i * 65 + k] : T(0);
@@ -365,10 +366,11 @@ __global__ void lu_init_kernel(int N, int* perm_all, int* info, int nbox) {
   if (blockIdx.x == 0 && threadIdx.x == 0) info[box] = 0;
 }
 
-template <typename T, int ROWS, int CW, int W>
-__global__ __launch_bounds__(kLuThreads, 2) void lu_panel_kernel(Geom g, T* A_all, int* perm_all, T* dinv_all,
-                                                                  int* info_all, int nbox, int c0, int pivot_end) {
-  __shared__ LuSmem<T, CW> sm;
+template <typename T, int ROWS, int CW, int W, int NT>
+__global__ __launch_bounds__(NT, NT >= 1024 ? 1 : 2) void lu_panel_kernel(Geom g, T* A_all, int* perm_all, T* dinv_all,
+                                                                           int* info_all, int nbox, int c0,
+                                                                           int pivot_end) {
+  __shared__ LuSmem<T, CW, NT / 64> sm;
   const int box = blockIdx.x;
   if (box >= nbox) return;
   const int N = g.n_pad;
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(kLuThreads, 2) void lu_panel_kernel(Geom g, T* A_al
   int* perm = perm_all + (size_t)box * N;
   T* dp = dinv_all + (size_t)box * g.npanel * 2 * 64 * 64 + (size_t)(c0 / kPanel) * 2 * 64 * 64;
   int info = 0;
-  lu_panel<T, ROWS, CW, W>(g, A, perm, c0, pivot_end, sm, info, dp);
+  lu_panel<T, ROWS, CW, W, NT>(g, A, perm, c0, pivot_end, sm, info, dp);
   if (threadIdx.x == 0 && info != 0 && info_all[box] == 0) info_all[box] = info;
 }
 
@@ -1012,20 +1014,20 @@ static hipError_t launch_gemm(const Geom& g, const T* F, const int* perm, T* X, 
 }
 
 
-template <typename T, int ROWS>
+template <typename T, int ROWS, int NT>
 static hipError_t launch_panel(const Geom& g, T* A, int* perm, T* dinv, int* info, int nbox, int c0, int w,
                                int pivot_end, hipStream_t st) {
-  constexpr int CW = PanelChunk<T, ROWS>::CW;
+  constexpr int CW = PanelChunk<T, ROWS, NT>::CW;
   if (w == 64)
-    hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, CW, 64>), dim3(nbox), dim3(kLuThreads), 0, st, g, A, perm, dinv,
-                       info, nbox, c0, pivot_end);
+    hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, CW, 64, NT>), dim3(nbox), dim3(NT), 0, st, g, A, perm, dinv, info,
+                       nbox, c0, pivot_end);
   else
-    hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, (CW < 32 ? CW : 32), 32>), dim3(nbox), dim3(kLuThreads), 0, st, g,
-                       A, perm, dinv, info, nbox, c0, pivot_end);
+    hipLaunchKernelGGL((lu_panel_kernel<T, ROWS, (CW < 32 ? CW : 32), 32, NT>), dim3(nbox), dim3(NT), 0, st, g, A,
+                       perm, dinv, info, nbox, c0, pivot_end);
   return hipGetLastError();
 }
 
-template <typename T, int ROWS>
+template <typename T, int ROWS, int NT = kLuThreads>
 static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
                          hipStream_t st, Profiler* prof, int pivot_end) {
   const int N = g.n_pad;
@@ -1035,7 +1037,7 @@ static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* 
     const int* op = ops.data() + q;
     if (op[0] == kOpPanel) {
       ProfScope ps(prof, Profiler::kLuPanel, 0.0, st);
-      e = launch_panel<T, ROWS>(g, A, perm, dinv, info, nbox, op[1], op[2], pivot_end, st);
+      e = launch_panel<T, ROWS, NT>(g, A, perm, dinv, info, nbox, op[1], op[2], pivot_end, st);
     } else if (op[0] == kOpRows) {
       const int r0 = op[1], r1 = op[2], cA = op[3], cB = op[4], ntn = (cB - cA + 63) / 64;
       for (int s = r0; s < r1 && e == hipSuccess; s += kPanel) {
@@ -1055,9 +1057,14 @@ static hipError_t run_lu(const Geom& g, const std::vector<int>& ops, T* A, int* 
 
 template <typename T>
 hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm, T* dinv, int* info, int nbox,
-                     hipStream_t st, Profiler* prof, int pivot_end) {
+                     hipStream_t st, Profiler* prof, int pivot_end, int panel_threads) {
   const int rows = (g.n_pad + kLuThreads - 1) / kLuThreads;
   const int pe = pivot_end < 0 ? g.n_pad : pivot_end;
+  // 1024-thread panels (four waves per SIMD to hide the latency of each pivot step): FP32,
+  // 2049..3072 rows (three rows per thread); bitwise the 512-thread result
+  if constexpr (sizeof(T) == 4)
+    if (panel_threads == 1024 && g.n_pad > 2048 && g.n_pad <= 3072)
+      return run_lu<T, 3, 1024>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
   if (rows <= 1) return run_lu<T, 1>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
   if (rows <= 2) return run_lu<T, 2>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
   if (rows <= 4) return run_lu<T, 4>(g, ops, A, perm, dinv, info, nbox, st, prof, pe);
@@ -1148,9 +1155,9 @@ hipError_t getrs_run(const Geom& g, const T* F, const int* perm, const T* dinv, 
   return e;
 }
 template hipError_t getrf_run<float>(const Geom&, const std::vector<int>&, float*, int*, float*, int*, int, hipStream_t,
-                                     Profiler*, int);
+                                     Profiler*, int, int);
 template hipError_t getrf_run<double>(const Geom&, const std::vector<int>&, double*, int*, double*, int*, int,
-                                      hipStream_t, Profiler*, int);
+                                      hipStream_t, Profiler*, int, int);
 template hipError_t getrs_run<float>(const Geom&, const float*,
                                      const int*, const float*, const float*, float*, int, const int*, hipStream_t,
                                      Profiler*, double*, int, int, int, const int*, int, const float*,

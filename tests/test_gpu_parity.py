@@ -449,3 +449,14 @@ def test_mixed_refinement_steps(gpu):
             assert full["iters"][k] == it[k]
         for key in ("X", "T", "g"):
             assert np.array_equal(mixed[key][k], ref[key][k]), (k, key)
+
+
+def test_panel_threads_1024_bitwise(gpu):
+    # the 1024-thread panel factorization (three rows per thread) at p = 16 chooses the same
+    # pivots and computes every row with the same operations as the 512-thread one: LU
+    # factors, pivot order and the whole reduction agree bitwise
+    prob = W.multi_bump((2, 2, 2), 16, 6.0, 30, gaussian_source=True, name="panel1024_p16")
+    runs = [gpu_leaf_boxes(prob, range(3), "fp32_ir", tuning={"panel_threads": nt}) for nt in (512, 1024)]
+    assert runs[0]["plan"].info.n_pad > 2048
+    for key in ("LU", "perm", "X", "T", "g", "info", "iters"):
+        assert np.array_equal(runs[0][key], runs[1][key]), key
