@@ -295,6 +295,16 @@ hps_status hps_front_factor(hps_front_plan plan, int32_t nfront, double* F, int3
 hps_status hps_front_solve(hps_front_plan plan, int32_t nfront, const double* F, const int32_t* perm,
                            const double* dinv, double* vec, int32_t mode, hipStream_t stream);
 
+/* Device workspace, in bytes, that one call needs for `nbox` boxes (the `ws`
+ * argument; caller-owned, any alignment of at least 256 bytes):
+ *   HPS_CALL_DTN             hps_leaf_dtn: nbox * hps_plan_info.ws_bytes
+ *   HPS_CALL_INTERIOR_SOLVE  hps_leaf_interior_solve: 8 nbox (n_i + 3)
+ *   HPS_CALL_ADJOINT_SOLVE   hps_leaf_adjoint_solve: 16 nbox n_pad
+ * HPS_EINVAL for an unknown call, nbox < 0 or bytes == NULL; *bytes is set only
+ * on success. */
+typedef enum { HPS_CALL_DTN = 0, HPS_CALL_INTERIOR_SOLVE = 1, HPS_CALL_ADJOINT_SOLVE = 2 } hps_call;
+hps_status hps_leaf_workspace_bytes(hps_plan plan, int32_t call, int32_t nbox, size_t* bytes);
+
 /* Run-time tuning of a plan.  A knob changes how the work is scheduled, never
  * what is computed: every setting gives bitwise the same results.
  *   HPS_TUNE_TRSM_SCHEDULE: the interior solves of hps_leaf_dtn (Alg. 1, the

@@ -18,8 +18,11 @@ EXPORTS = (
     "hps_leaf_interior_solve", "hps_leaf_flux", "hps_plan_set_tuning", "hps_plan_get_tuning",
     "hps_leaf_interior_solve_noalloc", "hps_front_plan_create", "hps_front_plan_destroy", "hps_front_dinv_elems",
     "hps_front_init", "hps_front_block_add", "hps_front_segments", "hps_front_factor", "hps_front_solve",
-    "hps_leaf_cn_rhs",
+    "hps_leaf_cn_rhs", "hps_leaf_workspace_bytes",
 )
+
+# hps_call: the calls whose workspace hps_leaf_workspace_bytes sizes
+CALLS = {"dtn": 0, "interior_solve": 1, "adjoint_solve": 2}
 
 # HPS_NOALLOC_SCRATCH_BYTES: the fixed scratch of hps_leaf_interior_solve_noalloc
 NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -84,6 +87,7 @@ def load() -> C.CDLL:
         "hps_plan_profile_read": [P, C.POINTER(Profile)],
         "hps_plan_set_tuning": [P, I32, I32],
         "hps_plan_get_tuning": [P, I32, C.POINTER(C.c_int32)],
+        "hps_leaf_workspace_bytes": [P, I32, I32, C.POINTER(SZ)],
         "hps_leaf_cn_rhs": [P, I32, P, D, P, P, P, P],
         "hps_front_plan_create": [C.POINTER(P), I32, I32],
         "hps_front_plan_destroy": [P],

@@ -590,6 +590,18 @@ hps_status hps_leaf_adjoint_solve(hps_plan pl, int32_t nbox, const void* LU, con
   return HPS_OK;
 }
 
+hps_status hps_leaf_workspace_bytes(hps_plan pl, int32_t call, int32_t nbox, size_t* bytes) {
+  if (bad_plan(pl) || nbox < 0 || !bytes) return HPS_EINVAL;
+  const Geom& g = pl->g;
+  const size_t nb = (size_t)nbox;
+  switch (call) {
+    case HPS_CALL_DTN: *bytes = nb * sizes_of(pl).ws; return HPS_OK;
+    case HPS_CALL_INTERIOR_SOLVE: *bytes = 8 * nb * ((size_t)g.n + 3); return HPS_OK;
+    case HPS_CALL_ADJOINT_SOLVE: *bytes = 16 * nb * (size_t)g.n_pad; return HPS_OK;
+    default: return HPS_EINVAL;
+  }
+}
+
 hps_status hps_plan_set_tuning(hps_plan pl, int32_t key, int32_t value) {
   if (bad_plan(pl)) return HPS_EINVAL;
   if (key == HPS_TUNE_TRSM_SCHEDULE && (value == hps::kTrsmRows || value == hps::kTrsmSweep)) {

@@ -101,6 +101,12 @@ class LeafPlan:
     def hps_plan_set_tuning(self, key: str, value: int) -> None:
         check(self.lib.hps_plan_set_tuning(self.handle, _lib.TUNING_KEYS[key], int(value)), "hps_plan_set_tuning")
 
+    def hps_leaf_workspace_bytes(self, call: str, nbox: int) -> int:
+        v = C.c_size_t(0)
+        check(self.lib.hps_leaf_workspace_bytes(self.handle, _lib.CALLS[call], int(nbox), C.byref(v)),
+              "hps_leaf_workspace_bytes")
+        return int(v.value)
+
     def hps_plan_get_tuning(self, key: str) -> int:
         v = C.c_int32(0)
         check(self.lib.hps_plan_get_tuning(self.handle, _lib.TUNING_KEYS[key], C.byref(v)), "hps_plan_get_tuning")
@@ -169,7 +175,7 @@ class LeafPlan:
             _ptr(slot_map, torch.int32, nbox * 36, "slot_map"), _ptr(T_vals, torch.float64, 1, "T_vals"),
             _ptr(g, torch.float64, nbox * i.n_b, "g"), _ptr(X, torch.float64, nbox * i.n_pad * i.ldx, "X"),
             _ptr(ir_iters, torch.int32, nbox, "ir_iters"), _ptr(berr, torch.float64, nbox, "berr"),
-            _ptr(ws, torch.uint8, nbox * i.ws_bytes, "ws"), _stream()), "hps_leaf_dtn")
+            _ptr(ws, torch.uint8, self.hps_leaf_workspace_bytes("dtn", nbox), "ws"), _stream()), "hps_leaf_dtn")
 
     def hps_leaf_reconstruct(self, nbox: int, X, u_b, u_i):
         i = self.info
@@ -188,10 +194,10 @@ class LeafPlan:
                 _ptr(u_i, torch.float64, nbox * i.n_i, "u_i"))
 
     def hps_leaf_interior_solve(self, nbox: int, LU, perm, dinv, b, anorm, f, u_b, u_i, steps: int, berr, ws):
-        i = self.info
         check(self.lib.hps_leaf_interior_solve(
             *self._interior_args(nbox, LU, perm, dinv, b, anorm, f, u_b, u_i, berr), int(steps),
-            _ptr(berr, torch.float64, nbox, "berr"), _ptr(ws, torch.uint8, 8 * nbox * (i.n_i + 3), "ws"),
+            _ptr(berr, torch.float64, nbox, "berr"),
+            _ptr(ws, torch.uint8, self.hps_leaf_workspace_bytes("interior_solve", nbox), "ws"),
             _stream()), "hps_leaf_interior_solve")
 
     def hps_leaf_interior_solve_noalloc(self, nbox: int, LU, perm, dinv, b, anorm, f, u_b, u_i, steps: int,
@@ -222,7 +228,8 @@ class LeafPlan:
             _ptr(dinv, self.elem, nbox * i.dinv_bytes // i.elem_bytes, "dinv"),
             _ptr(b, torch.float64, nbox * i.n_i, "b"), _ptr(w_i, torch.float64, nbox * i.n_i, "w_i"),
             _ptr(lam_b, torch.float64, nbox * i.n_b, "lam_b"), _ptr(z, torch.float64, nbox * i.n_i, "z"),
-            _ptr(y_b, torch.float64, nbox * i.n_b, "y_b"), _ptr(ws, torch.uint8, nbox * i.ws_bytes, "ws"),
+            _ptr(y_b, torch.float64, nbox * i.n_b, "y_b"),
+            _ptr(ws, torch.uint8, self.hps_leaf_workspace_bytes("adjoint_solve", nbox), "ws"),
             _stream()), "hps_leaf_adjoint_solve")
 
     def hps_leaf_adjoint_grad(self, nbox: int, lam_i, u_i, grad):

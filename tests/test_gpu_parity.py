@@ -460,3 +460,26 @@ def test_panel_threads_1024_bitwise(gpu):
     assert runs[0]["plan"].info.n_pad > 2048
     for key in ("LU", "perm", "X", "T", "g", "info", "iters"):
         assert np.array_equal(runs[0][key], runs[1][key]), key
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_workspace_bytes(gpu, precision):
+    # hps_leaf_workspace_bytes states each call's workspace: the DtN's per-box figure of
+    # hps_plan_get_info, one FP64 vector and three scalars per box for the interior solve,
+    # two padded FP64 vectors per box for the adjoint solve; bad arguments are rejected
+    from paper_2503_04033_amd._lib import HpsError, check
+    from paper_2503_04033_amd.leaf import LeafPlan
+    plan = LeafPlan(12, (0.5, 0.5, 0.5), 10.0, precision)
+    i = plan.info
+    for nb in (0, 1, 37):
+        assert plan.hps_leaf_workspace_bytes("dtn", nb) == nb * i.ws_bytes
+        assert plan.hps_leaf_workspace_bytes("interior_solve", nb) == 8 * nb * (i.n_i + 3)
+        assert plan.hps_leaf_workspace_bytes("adjoint_solve", nb) == 16 * nb * i.n_pad
+    assert plan.hps_leaf_workspace_bytes("interior_solve", 1) <= i.ws_bytes
+    import ctypes as C
+    v = C.c_size_t(7)
+    with pytest.raises(HpsError):
+        check(plan.lib.hps_leaf_workspace_bytes(plan.handle, 3, 1, C.byref(v)), "bad call")
+    assert v.value == 7
+    with pytest.raises(HpsError):
+        plan.hps_leaf_workspace_bytes("dtn", -1)
