@@ -329,7 +329,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nbox", type=int, default=0, help="time only the first N boxes (profiling)")
-    ap.add_argument("--chunk", type=int, default=1024)
+    ap.add_argument("--chunk", type=int, default=2048,
+                    help="boxes per launch of the FP32+IR headline (the FP64 leg takes at most 1024: its "
+                         "buffers are twice as large)")
     ap.add_argument("--streams", type=int, default=1,
                     help="chunks interleaved over this many HIP streams (each with its own buffers); more "
                          "than one overlaps kernels, so per-kernel event times then include the overlap")
@@ -490,7 +492,7 @@ def main():
         del fp32
         torch.cuda.empty_cache()
         # FP64 buffers are ~1.4x larger per box: the same streams, chunks of chunk/streams
-        fp64 = Runner(prob, "fp64", nbox, max(1, a.chunk // a.streams), streams=a.streams)
+        fp64 = Runner(prob, "fp64", nbox, max(1, min(a.chunk, 1024) // a.streams), streams=a.streams)
         fp64.step(b, g_dir)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
