@@ -201,6 +201,13 @@ class BatchedLeafReduction:
 TRSM_KNOBS = ({"trsm_schedule": 0, "trsm_waves": 4}, {"trsm_schedule": 0, "trsm_waves": 6},
               {"trsm_schedule": 0, "trsm_waves": 8}, {"trsm_schedule": 1, "trsm_waves": 4})
 RESIDUAL_KNOBS = ({"residual_cols": 8}, {"residual_cols": 4})
+# the panel's thread count matters only where a 1024-thread panel exists (FP32 factors of
+# 2049..3072 rows); the stage is skipped elsewhere
+PANEL_KNOBS = ({"panel_threads": 1024}, {"panel_threads": 512})
+
+
+def _panel_knob_applies(info, precision) -> bool:
+    return precision == "fp32_ir" and 2048 < info.n_pad <= 3072
 
 
 def _time_build(pr, precision, hbm_budget, chunk, knobs, reps):
@@ -222,12 +229,13 @@ def _time_build(pr, precision, hbm_budget, chunk, knobs, reps):
 
 
 def autotune(problems, precision="fp32_ir", candidates=(128, 256, 512, 1024), hbm_budget=64e9, cache=None,
-             reps=1, knob_stages=(TRSM_KNOBS, RESIDUAL_KNOBS)):
+             reps=1, knob_stages=(TRSM_KNOBS, RESIDUAL_KNOBS, PANEL_KNOBS)):
     """Pick, per problem, the chunk size and the plan knobs by timing the build stage.
 
-    One stage per group of knobs (solve schedule and occupancy, then the residual's
-    column blocking), each timed at the largest chunk that fits hbm_budget on top of the
-    choices of the earlier stages; then every candidate chunk with the chosen knobs.
+    One stage per group of knobs (solve schedule and occupancy, the residual's column
+    blocking, the panel's thread count where it applies), each timed at the largest chunk
+    that fits hbm_budget on top of the choices of the earlier stages; then every candidate
+    chunk with the chosen knobs.
     Returns a list of {"chunk": c, "tuning": {knob: value}}; results are cached as JSON
     under the key (GPU name, p, nbox, precision).
     """
@@ -243,13 +251,16 @@ def autotune(problems, precision="fp32_ir", candidates=(128, 256, 512, 1024), hb
         if key in table:
             out.append({"chunk": int(table[key]["chunk"]), "tuning": dict(table[key]["tuning"])})
             continue
-        per_box = bytes_per_box(LeafPlan(pr.p, pr.h, pr.kappa, precision).info)
+        pinfo = LeafPlan(pr.p, pr.h, pr.kappa, precision).info
+        per_box = bytes_per_box(pinfo)
         fits = [min(c, nbox) for c in candidates if per_box * min(c, nbox) <= hbm_budget]
         if not fits:
             raise ValueError(f"no candidate chunk of p={pr.p} fits {hbm_budget:.3g} bytes")
         c0 = max(fits)
         best_kn, ktrials = {}, []
         for stage in knob_stages:
+            if stage is PANEL_KNOBS and not _panel_knob_applies(pinfo, precision):
+                continue
             trials = [(dict(best_kn, **kn), _time_build(pr, precision, hbm_budget, c0, dict(best_kn, **kn), reps))
                       for kn in stage]
             best_kn = min(trials, key=lambda t: t[1])[0]

@@ -116,16 +116,20 @@ def test_three_problem_batch(gpu):
 
 
 def test_autotune_config4(gpu, tmp_path):
-    # the autotuner's choices (chunk, solve schedule, occupancy, residual blocking) per size group: valid,
+    # the autotuner's choices (chunk, solve schedule, occupancy, residual blocking, panel threads) per size group: valid,
     # cached, and bitwise the same results as the untuned run
-    from paper_2503_04033_amd.batch import RESIDUAL_KNOBS, TRSM_KNOBS, BatchedLeafReduction, autotune
+    from paper_2503_04033_amd.batch import PANEL_KNOBS, RESIDUAL_KNOBS, TRSM_KNOBS, BatchedLeafReduction, autotune
     probs = W.config4()
     cache = str(tmp_path / "tune.json")
     tuned = autotune(probs, "fp32_ir", candidates=(256, 4096), hbm_budget=24e9, cache=cache)
     for pr, t in zip(probs, tuned):
         say(f"  autotune p={pr.p} nbox={pr.nbox}: chunk {t['chunk']}, {t['tuning']}")
         assert t["chunk"] in (256, min(4096, pr.nbox))
-        assert set(t["tuning"]) == {"trsm_schedule", "trsm_waves", "residual_cols"}
+        # the panel's thread count is tuned only for the p = 16 group (2744 rows)
+        assert set(t["tuning"]) == {"trsm_schedule", "trsm_waves", "residual_cols"} | (
+            {"panel_threads"} if pr.p == 16 else set())
+        if pr.p == 16:
+            assert {"panel_threads": t["tuning"]["panel_threads"]} in PANEL_KNOBS
         assert {k: t["tuning"][k] for k in ("trsm_schedule", "trsm_waves")} in TRSM_KNOBS
         assert {"residual_cols": t["tuning"]["residual_cols"]} in RESIDUAL_KNOBS
     assert autotune(probs, "fp32_ir", candidates=(256, 4096), hbm_budget=24e9, cache=cache) == tuned
