@@ -317,7 +317,8 @@ hps_status hps_leaf_workspace_bytes(hps_plan plan, int32_t call, int32_t nbox, s
  *     at 4; the value is accepted and ignored there.
  *   HPS_TUNE_RESIDUAL_COLS: the FP64 refinement residual of FP32_IR plans (the
  *     Alg. 1 solves, refined), 6 <= p <= 18: right-hand-side columns per workgroup,
- *     4 (512 threads, two workgroups per CU, default) or 8 (1024 threads).  Other p
+ *     4 (512 threads, two workgroups per CU, default), 8 (1024 threads) or 2 (256
+ *     threads, four workgroups per CU).  Other p
  *     use one kernel and ignore the value.
  *   HPS_TUNE_PANEL_THREADS: FP32_IR plans whose padded interior size is 2049..3072
  *     (p = 15, 16): threads of the pivoted panel factorization of hps_leaf_factor,

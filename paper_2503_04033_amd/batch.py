@@ -200,7 +200,7 @@ class BatchedLeafReduction:
 
 TRSM_KNOBS = ({"trsm_schedule": 0, "trsm_waves": 4}, {"trsm_schedule": 0, "trsm_waves": 6},
               {"trsm_schedule": 0, "trsm_waves": 8}, {"trsm_schedule": 1, "trsm_waves": 4})
-RESIDUAL_KNOBS = ({"residual_cols": 8}, {"residual_cols": 4})
+RESIDUAL_KNOBS = ({"residual_cols": 8}, {"residual_cols": 4}, {"residual_cols": 2})
 # the panel's thread count matters only where a 1024-thread panel exists (FP32 factors of
 # 2049..3072 rows); the stage is skipped elsewhere
 PANEL_KNOBS = ({"panel_threads": 1024}, {"panel_threads": 512})

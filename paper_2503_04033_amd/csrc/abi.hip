@@ -612,7 +612,7 @@ hps_status hps_plan_set_tuning(hps_plan pl, int32_t key, int32_t value) {
     pl->trsm_waves = value;
     return HPS_OK;
   }
-  if (key == HPS_TUNE_RESIDUAL_COLS && (value == 4 || value == 8)) {
+  if (key == HPS_TUNE_RESIDUAL_COLS && (value == 2 || value == 4 || value == 8)) {
     pl->res_cols = value;
     return HPS_OK;
   }

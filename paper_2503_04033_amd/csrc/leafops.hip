@@ -440,7 +440,7 @@ __device__ inline double wave_uniform(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int M, int NW, int CB, typename TX>
+template <int M, int NW, int CB, typename TX, bool HASF>
 __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, int nbox, int ncb, const double* b,
                                                                        const double* f, const TX* X_all,
                                                                        float* R32_all, const int* pos_all,
@@ -461,12 +461,22 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
   static_assert(4 * mm * CB <= 2 * BUF * 2, "output staging must fit the slab buffers");
   using V = TX __attribute__((ext_vector_type(VX)));
   __shared__ double sm[2 * BUF];
-  __shared__ double sb[M * M * M];   // kappa^2 b of the box
-  __shared__ double sf[M * M * M];   // f of the box (the block with the load column only)
-  __shared__ double te[2 * 16];      // D2[i+1][0] and D2[i+1][p-1]
-  __shared__ int spos[M * M * M];    // R32 row of each node (pos, or the node itself)
+  __shared__ double sb[M * M * M];             // kappa^2 b of the box
+  __shared__ double sf[HASF ? M * M * M : 1];  // f of the box (the launch of the load column's block)
+  __shared__ double te[2 * 16];                // D2[i+1][0] and D2[i+1][p-1]
+  // Two launches: every column block except, when f is given, the one that holds the load
+  // column; then that block alone (one workgroup per box, f staged in LDS), so the first
+  // launch needs no LDS for f and more of its workgroups fit on a CU.
   int box, cb;
-  if (!map_box_chunk(nbox, ncb, box, cb)) return;
+  const int fcb = rhs_icol(g, g.nb) / CB;
+  if constexpr (HASF) {
+    box = blockIdx.x;
+    cb = fcb;
+    if (box >= nbox) return;
+  } else {
+    if (!map_box_chunk(nbox, ncb, box, cb)) return;
+    if (f && cb == fcb) return;
+  }
   const int p = g.p, ldx = g.ldx;
   // the wave index in a scalar register: everything derived from it (column, run of slabs,
   // the column's face) stays scalar and its branches are scalar branches
@@ -479,7 +489,6 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
   const TX* X = X_all + (size_t)box * g.n_pad * ldx + (sizeof(TX) == 4 ? c0 : rhs_ncol(g, c0));
   const int* pos = pos_all ? pos_all + (size_t)box * g.n_pad : nullptr;
   const double* bb = b + (size_t)box * g.n;
-  const bool fblock = f && rhs_icol(g, g.nb) / CB == cb;
   // (the column-map loads above and this one are in flight together)
   if (active && active[box] == 0) return;
   // Load task t = threadIdx.x + s * threads (t < NX) of a slab: row t / XT, elements
@@ -508,22 +517,17 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
 #pragma unroll
       for (int e = 0; e < VX; e++) sm[buf * BUF + lo[s] + e * kRmTile] = (double)pf[slot][s][e];
   };
-  // The global loads of b, f, the R32 row positions and the operator tables are issued
-  // together and branch-free (one wait, not one per loop trip), ahead of the slab loads;
-  // their values go to LDS after the slab loads are on their way.
+  // The global loads of b, f and the operator tables are issued together and branch-free
+  // (one wait, not one per loop trip), ahead of the slab loads; their values go to LDS
+  // after the slab loads are on their way.
   constexpr int NB = (M * M * M + kRmThreads - 1) / kRmThreads;
   static_assert(2 * M <= kRmThreads, "one table entry per thread");
-  const double* fsrc = fblock ? f + (size_t)box * g.n : bb;  // (b: a valid, cached stand-in)
-  const int* psrc = pos ? pos : g.coords;
-  double rb[NB], rf[NB];
-  int rp[NB];
+  double rb[NB], rf[HASF ? NB : 1];
 #pragma unroll
   for (int k = 0; k < NB; k++) {
     const int e = threadIdx.x + k * kRmThreads, ec = e < m * mm ? e : 0;
     rb[k] = bb[ec];
-    rf[k] = fsrc[ec];
-    const int pv = psrc[ec];
-    rp[k] = pos ? pv : ec;
+    if constexpr (HASF) rf[k] = f[(size_t)box * g.n + ec];
   }
   const int e0 = threadIdx.x;
   const double re = g.D2[e0 < 2 * m ? (e0 % m + 1) * p + (e0 < m ? 0 : p - 1) : 0];
@@ -549,8 +553,7 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
     const int e = threadIdx.x + k * kRmThreads;
     if (e < m * mm) {
       sb[e] = g.kappa2 * rb[k];
-      sf[e] = rf[k];
-      spos[e] = rp[k];
+      if constexpr (HASF) sf[e] = rf[k];
     }
   }
   if (e0 < 2 * m) te[e0] = re;
@@ -565,7 +568,7 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
     la = qq % m;
     lb = qq / m;
   }
-  const bool fcol = (col == g.nb) && f;
+  const bool fcol = HASF && col == g.nb;
   int emask = 0, inb = 0;  // inb: bit i marks node (lr + 4i, lc) inside the m x m slab
 #pragma unroll
   for (int i = 0; i < 4; i++) {
@@ -618,10 +621,12 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
           const int node = q * mm + ((inb >> i) & 1 ? lr + 4 * i + m * lc : 0);
           a[i] += sb[node] * bx[i];
         }
-        if (fcol) {
+        if constexpr (HASF) {
+          if (fcol) {
 #pragma unroll
-          for (int i = 0; i < 4; i++)
-            if ((inb >> i) & 1) a[i] += sf[q * mm + lr + 4 * i + m * lc];
+            for (int i = 0; i < 4; i++)
+              if ((inb >> i) & 1) a[i] += sf[q * mm + lr + 4 * i + m * lc];
+          }
         }
         acc[q - pt * H] = a;
 #pragma unroll
@@ -688,12 +693,27 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
         }
       }
       __syncthreads();
-      constexpr int V4 = CB / 4;  // float4 per row segment
+      // row segments of OV floats; the R32 rows (pos) come from L2, issued together
+      constexpr int OV = CB < 4 ? CB : 4;
+      constexpr int VO = CB / OV;
+      constexpr int NR = (4 * mm * VO + kRmThreads - 1) / kRmThreads;
+      using FO = float __attribute__((ext_vector_type(OV)));
       const int nk = (m - k0) < 4 ? (m - k0) : 4;
-      for (int t = threadIdx.x; t < nk * mm * V4; t += kRmThreads) {
-        const int row = t / V4, h = t % V4;  // row = (slab - k0) * m^2 + r
-        const f4 v = *reinterpret_cast<const f4*>(O + row * CB + 4 * h);
-        *reinterpret_cast<f4*>(R32 + (size_t)spos[k0 * mm + row] * ldx + 4 * h) = v;
+      int prow[NR];
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        const int t = threadIdx.x + j * kRmThreads, row = t / VO;
+        const int node = k0 * mm + (t < nk * mm * VO ? row : 0);
+        prow[j] = pos ? pos[node] : node;
+      }
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        const int t = threadIdx.x + j * kRmThreads;
+        if (t < nk * mm * VO) {
+          const int row = t / VO, h = t % VO;  // row = (slab - k0) * m^2 + r
+          const FO v = *reinterpret_cast<const FO*>(O + row * CB + OV * h);
+          *reinterpret_cast<FO*>(R32 + (size_t)prow[j] * ldx + OV * h) = v;
+        }
       }
     }
   }
@@ -726,14 +746,17 @@ static hipError_t launch_residual_mfma(const Geom& g, int nbox, int grid_boxes, 
                                        const int* active, hipStream_t st) {
   // column blocks run over the internal order's 16-column groups that hold natural columns
   // 0..nb (they come first); later groups hold zeros in X and in R32 (left as the caller
-  // wrote them)
+  // wrote them).  With f, the load column's block runs in a second launch.
   const int ncb = 16 * ((g.nb + 1 + 15) / 16) / CB;
-  const dim3 grid(grid_boxes * ncb), block(64 * CB * NW);
+  const dim3 grid(grid_boxes * ncb), gridf(grid_boxes), block(64 * CB * NW);
   switch (g.m) {
-#define HPS_RES_CASE(M)                                                                                        \
-  case M:                                                                                                      \
-    hipLaunchKernelGGL((residual_mfma_kernel<M, NW, CB, TX>), grid, block, 0, st, g, nbox, ncb, b, f, X, R32,  \
-                       pos, maxr, maxx, active);                                                               \
+#define HPS_RES_CASE(M)                                                                                          \
+  case M:                                                                                                        \
+    hipLaunchKernelGGL((residual_mfma_kernel<M, NW, CB, TX, false>), grid, block, 0, st, g, nbox, ncb, b, f, X,  \
+                       R32, pos, maxr, maxx, active);                                                            \
+    if (f)                                                                                                       \
+      hipLaunchKernelGGL((residual_mfma_kernel<M, NW, CB, TX, true>), gridf, block, 0, st, g, nbox, ncb, b, f,   \
+                         X, R32, pos, maxr, maxx, active);                                                       \
     break;
     HPS_RES_CASE(4) HPS_RES_CASE(5) HPS_RES_CASE(6) HPS_RES_CASE(7) HPS_RES_CASE(8) HPS_RES_CASE(9)
     HPS_RES_CASE(10) HPS_RES_CASE(11) HPS_RES_CASE(12) HPS_RES_CASE(13) HPS_RES_CASE(14) HPS_RES_CASE(15)
@@ -753,7 +776,8 @@ hipError_t launch_residual(const Geom& g, int nbox, const double* b, const doubl
   if (e != hipSuccess) return e;
   const int grid_boxes = 8 * ((nbox + 7) / 8);
   if (g.m >= 4 && g.m <= 16) {
-    // two waves per column; 8 columns (1024 threads) or 4 columns (512 threads) per workgroup
+    // two waves per column; 8 columns (1024 threads), 4 (512) or 2 (256) per workgroup
+    if (cols == 2) return launch_residual_mfma<2, 2>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st);
     if (cols == 4) return launch_residual_mfma<2, 4>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st);
     return launch_residual_mfma<2, 8>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st);
   } else if (((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double) <= 96 * 1024) {

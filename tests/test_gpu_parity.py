@@ -67,7 +67,7 @@ def test_trsm_schedules(gpu, precision, case):
         prob, boxes = W.config3_p20(), [5]
     tol = FP64_TOL if precision == "fp64" else IR_TOL
     sweep = _check_leaf(prob, boxes, precision, tol, tuning={"trsm_schedule": 1})
-    for waves, cols in ((4, 8), (6, 4), (8, 8)):
+    for waves, cols in ((4, 8), (6, 4), (8, 2)):
         rows = gpu_leaf_boxes(prob, boxes, precision,
                               tuning={"trsm_schedule": 0, "trsm_waves": waves, "residual_cols": cols})
         for k in ("X", "T", "g", "iters"):
@@ -79,6 +79,8 @@ def test_trsm_schedules(gpu, precision, case):
     with pytest.raises(HpsError):
         plan.hps_plan_set_tuning("trsm_waves", 5)
     assert plan.hps_plan_get_tuning("trsm_schedule") == 0 and plan.hps_plan_get_tuning("trsm_waves") == 8
+    with pytest.raises(HpsError):
+        plan.hps_plan_set_tuning("residual_cols", 16)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
