@@ -212,8 +212,9 @@ hps::SolveFlops solve_flops(const hps_plan_s* pl, int nbox, const int* kstart_de
     for (int tn = 0; tn < ntn; tn++) {
       const int k0 = ks[(size_t)b * ntn + tn];
       double t = 0.0;
-      for (int s = 0; s < N; s += br) {
-        const int w = std::min(br, N - s);
+      for (int q = 0; q < (N + br - 1) / br; q++) {
+        int s, w;
+        hps::sweep_block(N, br, false, q, s, w);
         if (s + w <= k0) continue;
         t += 2.0 * w * std::max(0, s - k0) + (double)w * w;
       }

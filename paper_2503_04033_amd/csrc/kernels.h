@@ -97,6 +97,23 @@ hipError_t getrf_run(const Geom& g, const std::vector<int>& ops, T* A, int* perm
 // panels per launch), 64 in FP64.
 template <typename T>
 constexpr int solve_block_rows() { return sizeof(T) == 4 ? 128 : 64; }
+
+// Block q (in sweep order) of the block rows of a triangular sweep over N rows in blocks of
+// BR: rows [s, s + w).  With 128-row blocks and N = 64 mod 128 the 64-row block is the first
+// one in either direction, where its product with the rows already solved is empty: the
+// forward sweep takes rows [0, 64) first and continues at 64 + 128 j (block rows stay made
+// of whole 64-row diagonal blocks of the factor), the backward sweep starts at the last 64
+// rows.  Otherwise the blocks start at multiples of BR.
+__host__ __device__ inline void sweep_block(int N, int BR, bool upper, int q, int& s, int& w) {
+  if (BR == 128 && !upper && N % 128 == 64) {
+    s = q == 0 ? 0 : 64 + 128 * (q - 1);
+    w = q == 0 ? 64 : 128;
+    return;
+  }
+  const int nblk = (N + BR - 1) / BR;
+  s = (upper ? nblk - 1 - q : q) * BR;
+  w = (N - s) < BR ? (N - s) : BR;
+}
 // Flops of one solve for the profiler (set by the caller when profiling is on): algorithmic
 // n_i^2 (n_b + 1) per active box and sweep, and what the kernels execute per sweep.
 struct SolveFlops {

@@ -982,8 +982,8 @@ __global__ __launch_bounds__(256, OCC) void trsm_sweep128_kernel(Geom g, const T
   const int ks = kstart ? kstart[(size_t)box * ntn + tn] : 0;
 #pragma unroll 1
   for (int q = 0; q < nblk; q++) {
-    const int jb = UPPER ? nblk - 1 - q : q;
-    const int s = jb * kBlockRows, w = (N - s) < kBlockRows ? (N - s) : kBlockRows;
+    int s, w;
+    sweep_block(N, kBlockRows, UPPER, q, s, w);
     const T* Inv0 = dinv + (size_t)(s / kPanel) * 2 * 64 * 64;
     solve_block_row128<T, UPPER, SEG>(g, F, perm, Inv0, Inv0 + 2 * 64 * 64, B, Y, Xb, xmode, s, w, tn * 64, ks,
                                       bdirect, Y0, smem);
@@ -1097,7 +1097,8 @@ static hipError_t launch_sweep(const Geom& g, const T* F, const int* perm, const
   constexpr int BR = solve_block_rows<T>();
   const int nblk = (N + BR - 1) / BR;
   for (int q = 0; q < nblk; q++) {
-    const int s = (UPPER ? nblk - 1 - q : q) * BR, w = (N - s) < BR ? (N - s) : BR;
+    int s, w;
+    sweep_block(N, BR, UPPER, q, s, w);
     if constexpr (R128)
       hipLaunchKernelGGL((trsm_row128_kernel<T, UPPER, SEG, OCC>), dim3(grid_for(nbox, ntn)), dim3(256), 0, st, g,
                          F, perm, dinv, B, Y, s, w, nbox, ntn, active, X, xmode, kstart, bdirect, Y0);

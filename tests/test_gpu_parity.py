@@ -56,13 +56,17 @@ def test_leaf_fp32_ir_small(gpu, p):
     assert np.all(out["iters"] >= 0)
 
 
-@pytest.mark.parametrize("precision,case", [("fp64", "p9"), ("fp32_ir", "p9"), ("fp32_ir", "p20")])
+@pytest.mark.parametrize("precision,case", [("fp64", "p9"), ("fp32_ir", "p9"), ("fp32_ir", "p14"),
+                                            ("fp32_ir", "p20")])
 def test_trsm_schedules(gpu, precision, case):
-    # every schedule and occupancy of the interior solves and both column blockings of the
+    # every schedule and occupancy of the interior solves and every column blocking of the
     # refinement residual: parity with the oracle, and bitwise the same results (same
-    # tiles, same order of every sum); p = 20 takes the segmented FP32 sums
+    # tiles, same order of every sum); p = 14 (1728 rows, 64 mod 128) takes the forward
+    # sweep whose 64-row block comes first; p = 20 takes the segmented FP32 sums
     if case == "p9":
         prob, boxes = W.multi_bump((2, 2, 2), 9, 6.0, 14, gaussian_source=True, name="sched_p9"), range(8)
+    elif case == "p14":
+        prob, boxes = W.multi_bump((2, 2, 2), 14, 6.0, 16, gaussian_source=True, name="sched_p14"), [0, 7]
     else:
         prob, boxes = W.config3_p20(), [5]
     tol = FP64_TOL if precision == "fp64" else IR_TOL
