@@ -136,7 +136,13 @@ hps_status hps_leaf_factor(hps_plan plan, int32_t nbox, void* A, int32_t* perm, 
  *   for that), the correction is solved in FP32 and added in FP64, until the
  *   backward error is <= ir_tol or ir_max_iter steps; ir_iters[box] = steps
  *   taken, or -1 - steps if still above ir_tol (a NaN counts as above);
- *   berr[box] = final backward error.
+ *   berr[box] = final backward error: the larger of
+ *     max|R| / (|A_ii|_inf max|X| + max|B|) over every column of [A_ib | f_i] and,
+ *     when f is given, the same over the load column alone (its entries are far
+ *     smaller than A_ib's, so the first figure alone would not see its error).
+ *   FP32_IR plans solve and refine the load column as f / s, s the power of two
+ *   with 1 <= max|f| / s < 2 per box (exact; berr is taken in that scale), so that
+ *   loads far below FP32's range are resolved like the other columns.
  *   T = A_bb - A_bi X_b: row block a / column block b of box t is written to
  *   T_vals + slot_map[t*36 + 6a + b] * m^4 (row-major m^2 x m^2 block) when the
  *   slot is >= 0; slot -1 drops the block (rows of boundary faces, columns of

@@ -125,6 +125,8 @@ struct WsLayout {
   float* Y32;
   double *maxb, *maxr, *maxx;
   int* active;
+  double* fst;  // [3][nbox]: the load column's max|f|, max|R|, max|X|
+  double* fsc;  // [nbox]: the load column's scale in the FP32 solves
   int* kstart;  // [nbox][ldx/64]
   int* pos;     // [nbox][n_pad]: inverse of perm
 };
@@ -141,6 +143,8 @@ WsLayout ws_layout(const hps_plan_s* pl, int nbox, void* ws) {
   L.maxr = L.maxb + nbox;
   L.maxx = L.maxr + nbox;
   L.active = reinterpret_cast<int*>(L.maxx + nbox);
+  L.fst = reinterpret_cast<double*>(p + 32 * (size_t)nbox);  // after active
+  L.fsc = L.fst + 3 * (size_t)nbox;                            // bytes 56..64 per box
   L.kstart = reinterpret_cast<int*>(p + 64 * (size_t)nbox);
   L.pos = L.kstart + round_up(g.ldx / 64, 16) * (size_t)nbox;
   return L;
@@ -407,7 +411,8 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
   const bool ir = pl->desc.precision == HPS_FP32_IR;
   if (!ir) {
     double* B = static_cast<double*>(L.B);
-    HPS_TRY(hps::launch_rhs<double>(g, nbox, f, B, L.maxb, st));
+    double* fst = f ? L.fst : nullptr;
+    HPS_TRY(hps::launch_rhs<double>(g, nbox, f, B, L.maxb, st, fst));
     HPS_TRY(hps::launch_rhs_first_row(g, nbox, perm, f != nullptr, L.kstart, nullptr, st));
     hps::SolveFlops sf{};
     if (pl->prof.on) sf = solve_flops(pl, nbox, L.kstart, nullptr, st);
@@ -419,15 +424,21 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
       HPS_TRY(hps::launch_fill_int(L.active, 1, nbox, st));
       hps::ProfScope ps(&pl->prof, hps::Profiler::kResidual, 0.0, st);
       HPS_TRY(hps::launch_residual<double>(g, nbox, b, f, X, nullptr, nullptr, L.maxr, L.maxx, nullptr, st,
-                                           pl->res_cols));
+                                           pl->res_cols, fst));
       HPS_TRY(hps::launch_ir_check(nbox, 0, 1, INFINITY, anorm, L.maxb, L.maxr, L.maxx, L.active, nullptr, berr,
-                                   st));
+                                   st, fst));
     }
   } else {
     float* B = static_cast<float*>(L.B);
     const float* LUf = static_cast<const float*>(LU);
     const float* Dinv = static_cast<const float*>(dinv);
-    HPS_TRY(hps::launch_rhs<float>(g, nbox, f, B, L.maxb, st));
+    // The load column is solved and refined as f / s (s a power of two per box), so that a
+    // load far below FP32's range is resolved like the other columns; X's load column is
+    // scaled back after the refinement.
+    double* fst = f ? L.fst : nullptr;
+    double* fsc = f ? L.fsc : nullptr;
+    if (fsc) HPS_TRY(hps::launch_fscale(g, nbox, f, fsc, st));
+    HPS_TRY(hps::launch_rhs<float>(g, nbox, f, B, L.maxb, st, fst, fsc));
     HPS_TRY(hps::launch_rhs_first_row(g, nbox, perm, f != nullptr, L.kstart, L.pos, st));
     // First solve into Y32 only: X0 = Y32 is exact in FP32 and is read from there.  The
     // residual writes R32 in the factor's row order, so each correction runs in place in
@@ -447,25 +458,26 @@ hps_status hps_leaf_dtn(hps_plan pl, int32_t nbox, const void* LU, const int32_t
         hps::ProfScope ps(&pl->prof, hps::Profiler::kResidual, 0.0, st);
         if (it == 0)
           HPS_TRY(hps::launch_residual<float>(g, nbox, b, f, L.Y32, B, L.pos, L.maxr, L.maxx, L.active, st,
-                                              pl->res_cols));
+                                              pl->res_cols, fst, fsc));
         else
           HPS_TRY(hps::launch_residual<double>(g, nbox, b, f, X, nullptr, nullptr, L.maxr, L.maxx, L.active, st,
-                                               pl->res_cols));
+                                               pl->res_cols, fst, fsc));
       }
       HPS_TRY(hps::launch_ir_check(nbox, it, last, tol, anorm, L.maxb, L.maxr, L.maxx, L.active, ir_iters, berr,
-                                   st));
+                                   st, fst));
       if (it == 0) HPS_TRY(hps::launch_x_from_y(g, nbox, L.Y32, X, L.active, st));  // boxes done after 0 steps
       if (last) break;
       if (it > 0) {
         hps::ProfScope ps(&pl->prof, hps::Profiler::kResidual, 0.0, st);
         HPS_TRY(hps::launch_residual<double>(g, nbox, b, f, X, B, L.pos, L.maxr, L.maxx, L.active, st,
-                                             pl->res_cols));
+                                             pl->res_cols, fst, fsc));
       }
       hps::SolveFlops sfc{};
       if (pl->prof.on) sfc = solve_flops(pl, nbox, nullptr, L.active, st);
       HPS_TRY(hps::getrs_run<float>(g, LUf, perm, Dinv, B, B, nbox, L.active, st, &pl->prof, X, it == 0 ? 3 : 2,
                                     pl->trsm_sched, pl->trsm_waves, nullptr, 1, L.Y32, &sfc));
     }
+    if (fsc) HPS_TRY(hps::launch_funscale(g, nbox, X, fsc, st));  // X's load column for f
   }
   hps::ProfScope ps(&pl->prof, hps::Profiler::kDtn, 0.0, st);
   // the right-hand-side region of the workspace (8 n_pad ldx bytes per box) is free again:

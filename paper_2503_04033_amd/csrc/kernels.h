@@ -135,7 +135,16 @@ hipError_t launch_nodes(const Geom& g, const double* t, const double* h, int nbo
 template <typename T>
 hipError_t launch_operators(const Geom& g, int nbox, const double* b, T* A, double* anorm, hipStream_t st);
 template <typename T>
-hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* maxb, hipStream_t st);
+// fst (may be null): the load column's own statistics, [3][nbox]: max|f| (written here),
+// max|R| and max|X| of that column (written by launch_residual); launch_ir_check then also
+// takes the load column's backward error on its own scale
+// fsc (may be null): the load column's per-box scale s (launch_fscale); B then carries f / s
+hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* maxb, hipStream_t st,
+                      double* fst = nullptr, const double* fsc = nullptr);
+// fsc[box] = the power of two s with 1 <= max|f| / s < 2 (1 for a zero load), and back:
+// X[:, nb] *= s for the load column of an X that was solved for f / s
+hipError_t launch_fscale(const Geom& g, int nbox, const double* f, double* fsc, hipStream_t st);
+hipError_t launch_funscale(const Geom& g, int nbox, double* X, const double* fsc, hipStream_t st);
 // kstart [nbox][ldx/64]: first pivoted row at which each 64-column tile of [A_ib | f]
 // can be nonzero, rounded down to 64 (for the forward sweep of the first solve)
 // and, if pos is given, the inverse permutation pos [nbox][n_pad] (pos[perm[k]] = k)
@@ -148,12 +157,12 @@ hipError_t residual_prepare(const Geom& g);
 template <typename TX>
 hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const TX* X, float* R32,
                            const int* pos, double* maxr, double* maxx, const int* active, hipStream_t st,
-                           int cols = 8);
+                           int cols = 8, double* fst = nullptr, const double* fsc = nullptr);
 // X = (double) Y (natural column order) for the boxes whose active flag is 0
 hipError_t launch_x_from_y(const Geom& g, int nbox, const float* Y, double* X, const int* active, hipStream_t st);
 hipError_t launch_ir_check(int nbox, int it, int last, double tol, const double* anorm, const double* maxb,
                            const double* maxr, const double* maxx, int* active, int* iters, double* berr,
-                           hipStream_t st);
+                           hipStream_t st, const double* fst = nullptr);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_fill_int(int* p, int value, size_t count, hipStream_t st);
 // a4: T and the lifted loads; part: scratch of dtn_part_bytes(g, nbox) bytes

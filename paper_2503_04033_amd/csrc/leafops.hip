@@ -204,7 +204,8 @@ __device__ inline double aib_entry(const Geom& g, int ii, int jj, int kk, int co
 // B has at most 7 nonzeros per row (A_ib: the two face nodes at the ends of each of the
 // node's three lines; the load f): zero rows with 16-byte stores, then the nonzeros.
 template <typename T>
-__global__ __launch_bounds__(256) void rhs_kernel(Geom g, int nbox, const double* f, T* B_all, double* maxb) {
+__global__ __launch_bounds__(256) void rhs_kernel(Geom g, int nbox, const double* f, T* B_all, double* maxb,
+                                                  double* maxbf, const double* fsc) {
   const int box = blockIdx.y;
   const int N = g.n_pad, ldx = g.ldx, n = g.n, m = g.m, mm = m * m, p = g.p;
   T* B = B_all + (size_t)box * N * ldx;
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(256) void rhs_kernel(Geom g, int nbox, const double
     Store4<T>::st(B + (size_t)(r0 + rr) * ldx + c, zero);
   }
   __syncthreads();
-  double mx = 0.0;
+  double mx = 0.0, mxf = 0.0;
   for (int e = threadIdx.x; e < nr * 7; e += blockDim.x) {
     const int rr = e / 7, t = e - rr * 7, r = r0 + rr;
     if (r >= n) continue;
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(256) void rhs_kernel(Geom g, int nbox, const double
     int col;
     if (t == 6) {
       if (!f) continue;
-      v = f[(size_t)box * n + r];
+      v = f[(size_t)box * n + r] * (fsc ? 1.0 / fsc[box] : 1.0);  // (a power of two: exact)
       col = g.nb;
     } else {
       const int cd = g.coords[r];
@@ -238,21 +239,69 @@ __global__ __launch_bounds__(256) void rhs_kernel(Geom g, int nbox, const double
     }
     B[(size_t)r * ldx + rhs_icol(g, col)] = (T)v;
     mx = fmax(mx, fabs(v));
+    if (t == 6) mxf = fmax(mxf, fabs(v));
   }
   mx = wave_max(mx);
-  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(maxb + box, mx);
+  mxf = wave_max(mxf);
+  if ((threadIdx.x & 63) == 0) {
+    atomic_max_nonneg(maxb + box, mx);
+    if (maxbf) atomic_max_nonneg(maxbf + box, mxf);
+  }
 }
 
 template <typename T>
-hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* maxb, hipStream_t st) {
+hipError_t launch_rhs(const Geom& g, int nbox, const double* f, T* B, double* maxb, hipStream_t st, double* fst,
+                      const double* fsc) {
   hipError_t e = launch_fill_zero(maxb, sizeof(double) * nbox, st);
+  if (e == hipSuccess && fst) e = launch_fill_zero(fst, sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((rhs_kernel<T>), dim3((g.n_pad + kOperatorRows - 1) / kOperatorRows, nbox), dim3(256), 0, st, g, nbox, f, B,
-                     maxb);
+                     maxb, fst, fsc);
   return hipGetLastError();
 }
-template hipError_t launch_rhs<float>(const Geom&, int, const double*, float*, double*, hipStream_t);
-template hipError_t launch_rhs<double>(const Geom&, int, const double*, double*, double*, hipStream_t);
+template hipError_t launch_rhs<float>(const Geom&, int, const double*, float*, double*, hipStream_t, double*,
+                                      const double*);
+template hipError_t launch_rhs<double>(const Geom&, int, const double*, double*, double*, hipStream_t, double*,
+                                       const double*);
+
+// Load-column scale of the FP32 solves: per box the power of two s with
+// 1 <= max|f| / s < 2 (1 when f is zero or not finite).  The FP32 right-hand side and the
+// refinement carry f / s, so a load far below FP32's range (a source's far field) is
+// resolved like any other column; dividing by a power of two is exact, so loads inside
+// the range give bitwise the same X.
+__global__ __launch_bounds__(256) void fscale_kernel(int n, int nbox, const double* f, double* fsc) {
+  __shared__ double wm[4];
+  const int box = blockIdx.x;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(f[(size_t)box * n + i]));
+  mx = wave_max(mx);
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+    int ex = 0;
+    (void)frexp(mx, &ex);
+    fsc[box] = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, ex - 1) : 1.0;
+  }
+}
+
+hipError_t launch_fscale(const Geom& g, int nbox, const double* f, double* fsc, hipStream_t st) {
+  hipLaunchKernelGGL(fscale_kernel, dim3(nbox), dim3(256), 0, st, g.n, nbox, f, fsc);
+  return hipGetLastError();
+}
+
+// X's load column (natural column nb) back from f / s to f: X[:, nb] *= s.
+__global__ __launch_bounds__(256) void funscale_kernel(Geom g, int nbox, double* X_all, const double* fsc) {
+  const int box = blockIdx.y;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= g.n_pad) return;
+  X_all[((size_t)box * g.n_pad + r) * g.ldx + g.nb] *= fsc[box];
+}
+
+hipError_t launch_funscale(const Geom& g, int nbox, double* X, const double* fsc, hipStream_t st) {
+  hipLaunchKernelGGL(funscale_kernel, dim3((g.n_pad + 255) / 256, nbox), dim3(256), 0, st, g, nbox, X, fsc);
+  return hipGetLastError();
+}
 
 // First pivoted row at which each 64-column tile of B = [A_ib | f] (columns in the
 // solves' internal order, see Geom) can be nonzero.
@@ -340,7 +389,8 @@ __device__ inline bool map_box_chunk(int nbox, int nchunk, int& box, int& chunk)
 template <int CW, typename TX>
 __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox, const double* b, const double* f,
                                                                const TX* X_all, float* R32_all, const int* pos_all,
-                                                               double* maxr, double* maxx, const int* active) {
+                                                               double* maxr, double* maxx, const int* active,
+                                                               double* fst, const double* fsc) {
   extern __shared__ double xs[];  // [n][CW] then D2 interior block [m][m] and its two boundary columns
   int box, chunk;
   if (!map_box_chunk(nbox, g.ldx / CW, box, chunk)) return;
@@ -397,18 +447,25 @@ __global__ __launch_bounds__(kResThreads) void residual_kernel(Geom g, int nbox,
     } else if (axis == 2) {
       if (ii + m * jj == qq) bv = -s2a * d2e[side * m + kk];
     } else if (fcol) {
-      bv = f[(size_t)box * n + node];
+      bv = f[(size_t)box * n + node] * (fsc ? 1.0 / fsc[box] : 1.0);
     }
     const double r = bv + g.s2[0] * ax + g.s2[1] * ay + g.s2[2] * az + g.kappa2 * bb[node] * xv;
     if (R32) R32[(size_t)(pos ? pos[node] : node) * ldx + rhs_icol(g, col)] = (float)r;
     mr = fmax(mr, fabs(r));
     mxv = fmax(mxv, fabs(xv));
   }
+  double mrf = fcol ? mr : 0.0, mxf = fcol ? mxv : 0.0;  // the load column alone
   mr = wave_max(mr);
   mxv = wave_max(mxv);
+  mrf = wave_max(mrf);
+  mxf = wave_max(mxf);
   if ((threadIdx.x & 63) == 0) {
     atomic_max_nonneg(maxr + box, mr);
     atomic_max_nonneg(maxx + box, mxv);
+    if (fst) {
+      atomic_max_nonneg(fst + nbox + box, mrf);
+      atomic_max_nonneg(fst + 2 * nbox + box, mxf);
+    }
   }
 }
 
@@ -445,7 +502,8 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
                                                                        const double* f, const TX* X_all,
                                                                        float* R32_all, const int* pos_all,
                                                                        double* maxr, double* maxx,
-                                                                       const int* active) {
+                                                                       const int* active, double* fst,
+                                                                       const double* fsc) {
   constexpr int m = M, mm = M * M;
   constexpr int kRmThreads = 64 * CB * NW;
   constexpr int H = (M + NW - 1) / NW;        // output slabs per wave
@@ -529,6 +587,7 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
     rb[k] = bb[ec];
     if constexpr (HASF) rf[k] = f[(size_t)box * g.n + ec];
   }
+  const double finv = (HASF && fsc) ? 1.0 / fsc[box] : 1.0;  // (a power of two: exact)
   const int e0 = threadIdx.x;
   const double re = g.D2[e0 < 2 * m ? (e0 % m + 1) * p + (e0 < m ? 0 : p - 1) : 0];
   // MFMA operand of both derivative terms, kept in registers: lane (lr, lc) holds, for k
@@ -553,7 +612,7 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
     const int e = threadIdx.x + k * kRmThreads;
     if (e < m * mm) {
       sb[e] = g.kappa2 * rb[k];
-      if constexpr (HASF) sf[e] = rf[k];
+      if constexpr (HASF) sf[e] = rf[k] * finv;
     }
   }
   if (e0 < 2 * m) te[e0] = re;
@@ -722,6 +781,12 @@ __global__ __launch_bounds__(64 * CB * NW, 4) void residual_mfma_kernel(Geom g, 
   if (lane == 0) {
     atomic_max_nonneg(maxr + box, mr);
     atomic_max_nonneg(maxx + box, mxv);
+    if constexpr (HASF) {
+      if (fcol && fst) {  // the load column alone (this wave's column)
+        atomic_max_nonneg(fst + nbox + box, mr);
+        atomic_max_nonneg(fst + 2 * nbox + box, mxv);
+      }
+    }
   }
 }
 
@@ -743,7 +808,7 @@ hipError_t residual_prepare(const Geom& g) {
 template <int NW, int CB, typename TX>
 static hipError_t launch_residual_mfma(const Geom& g, int nbox, int grid_boxes, const double* b, const double* f,
                                        const TX* X, float* R32, const int* pos, double* maxr, double* maxx,
-                                       const int* active, hipStream_t st) {
+                                       const int* active, hipStream_t st, double* fst, const double* fsc) {
   // column blocks run over the internal order's 16-column groups that hold natural columns
   // 0..nb (they come first); later groups hold zeros in X and in R32 (left as the caller
   // wrote them).  With f, the load column's block runs in a second launch.
@@ -753,10 +818,10 @@ static hipError_t launch_residual_mfma(const Geom& g, int nbox, int grid_boxes, 
 #define HPS_RES_CASE(M)                                                                                          \
   case M:                                                                                                        \
     hipLaunchKernelGGL((residual_mfma_kernel<M, NW, CB, TX, false>), grid, block, 0, st, g, nbox, ncb, b, f, X,  \
-                       R32, pos, maxr, maxx, active);                                                            \
+                       R32, pos, maxr, maxx, active, fst, fsc);                                                  \
     if (f)                                                                                                       \
       hipLaunchKernelGGL((residual_mfma_kernel<M, NW, CB, TX, true>), gridf, block, 0, st, g, nbox, ncb, b, f,   \
-                         X, R32, pos, maxr, maxx, active);                                                       \
+                         X, R32, pos, maxr, maxx, active, fst, fsc);                                             \
     break;
     HPS_RES_CASE(4) HPS_RES_CASE(5) HPS_RES_CASE(6) HPS_RES_CASE(7) HPS_RES_CASE(8) HPS_RES_CASE(9)
     HPS_RES_CASE(10) HPS_RES_CASE(11) HPS_RES_CASE(12) HPS_RES_CASE(13) HPS_RES_CASE(14) HPS_RES_CASE(15)
@@ -770,38 +835,51 @@ static hipError_t launch_residual_mfma(const Geom& g, int nbox, int grid_boxes, 
 
 template <typename TX>
 hipError_t launch_residual(const Geom& g, int nbox, const double* b, const double* f, const TX* X, float* R32,
-                           const int* pos, double* maxr, double* maxx, const int* active, hipStream_t st, int cols) {
+                           const int* pos, double* maxr, double* maxx, const int* active, hipStream_t st, int cols,
+                           double* fst, const double* fsc) {
+  if (!f) fst = nullptr;
   hipError_t e = launch_fill_zero(maxr, sizeof(double) * nbox, st);
   if (e == hipSuccess) e = launch_fill_zero(maxx, sizeof(double) * nbox, st);
+  if (e == hipSuccess && fst) e = launch_fill_zero(fst + nbox, 2 * sizeof(double) * nbox, st);
   if (e != hipSuccess) return e;
   const int grid_boxes = 8 * ((nbox + 7) / 8);
   if (g.m >= 4 && g.m <= 16) {
     // two waves per column; 8 columns (1024 threads), 4 (512) or 2 (256) per workgroup
-    if (cols == 2) return launch_residual_mfma<2, 2>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st);
-    if (cols == 4) return launch_residual_mfma<2, 4>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st);
-    return launch_residual_mfma<2, 8>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st);
+    if (cols == 2) return launch_residual_mfma<2, 2>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st,
+                                                      fst, fsc);
+    if (cols == 4) return launch_residual_mfma<2, 4>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st,
+                                                      fst, fsc);
+    return launch_residual_mfma<2, 8>(g, nbox, grid_boxes, b, f, X, R32, pos, maxr, maxx, active, st,
+                                                      fst, fsc);
   } else if (((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double) <= 96 * 1024) {
     const size_t shm = ((size_t)g.n * 4 + g.m * g.m + 2 * g.m) * sizeof(double);
     hipLaunchKernelGGL((residual_kernel<4, TX>), dim3(grid_boxes * (g.ldx / 4)), dim3(kResThreads), shm, st, g, nbox,
-                       b, f, X, R32, pos, maxr, maxx, active);
+                       b, f, X, R32, pos, maxr, maxx, active, fst, fsc);
   } else {
     const size_t shm = ((size_t)g.n * 2 + g.m * g.m + 2 * g.m) * sizeof(double);
     hipLaunchKernelGGL((residual_kernel<2, TX>), dim3(grid_boxes * (g.ldx / 2)), dim3(kResThreads), shm, st, g, nbox,
-                       b, f, X, R32, pos, maxr, maxx, active);
+                       b, f, X, R32, pos, maxr, maxx, active, fst, fsc);
   }
   return hipGetLastError();
 }
 template hipError_t launch_residual<double>(const Geom&, int, const double*, const double*, const double*, float*,
-                                            const int*, double*, double*, const int*, hipStream_t, int);
+                                            const int*, double*, double*, const int*, hipStream_t, int, double*,
+                                            const double*);
 template hipError_t launch_residual<float>(const Geom&, int, const double*, const double*, const float*, float*,
-                                           const int*, double*, double*, const int*, hipStream_t, int);
+                                           const int*, double*, double*, const int*, hipStream_t, int, double*,
+                                           const double*);
 
 // Backward error check of one refinement step; decides which boxes continue.
 __global__ void ir_check_kernel(int nbox, int it, int last, double tol, const double* anorm, const double* maxb,
-                                const double* maxr, const double* maxx, int* active, int* iters, double* berr) {
+                                const double* maxr, const double* maxx, int* active, int* iters, double* berr,
+                                const double* fst) {
   const int box = blockIdx.x * blockDim.x + threadIdx.x;
   if (box >= nbox || active[box] == 0) return;
-  const double be = maxr[box] / (anorm[box] * maxx[box] + maxb[box]);
+  double be = maxr[box] / (anorm[box] * maxx[box] + maxb[box]);
+  if (fst) {  // the load column on its own scale (its entries are far smaller than A_ib's)
+    const double bf = fst[nbox + box] / (anorm[box] * fst[2 * nbox + box] + fst[box]);
+    be = (bf > be || bf != bf) ? bf : be;  // (a NaN stays a NaN)
+  }
   if (berr) berr[box] = be;
   if (be <= tol) {
     active[box] = 0;
@@ -814,9 +892,9 @@ __global__ void ir_check_kernel(int nbox, int it, int last, double tol, const do
 
 hipError_t launch_ir_check(int nbox, int it, int last, double tol, const double* anorm, const double* maxb,
                            const double* maxr, const double* maxx, int* active, int* iters, double* berr,
-                           hipStream_t st) {
+                           hipStream_t st, const double* fst) {
   hipLaunchKernelGGL(ir_check_kernel, dim3((nbox + 255) / 256), dim3(256), 0, st, nbox, it, last, tol, anorm, maxb,
-                     maxr, maxx, active, iters, berr);
+                     maxr, maxx, active, iters, berr, fst);
   return hipGetLastError();
 }
 

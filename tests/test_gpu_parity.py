@@ -489,3 +489,32 @@ def test_workspace_bytes(gpu, precision):
     assert v.value == 7
     with pytest.raises(HpsError):
         plan.hps_leaf_workspace_bytes("dtn", -1)
+
+
+@pytest.mark.parametrize("ir_max_iter,ir_tol", [(0, 1e-30), (3, None)])
+def test_berr_includes_load_column(gpu, ir_max_iter, ir_tol):
+    # berr is the larger of the backward error over all columns of [A_ib | f] and that of
+    # the load column alone (whose entries are far smaller than A_ib's).  Both are formed
+    # here from the GPU's own X with the oracle's dense A_ii and compared with berr: after
+    # the first FP32 solve (no correction; both figures near 1e-7, far above rounding) and
+    # after refinement (below the tolerance)
+    from oracle import leaf as ol
+    prob = W.multi_bump((2, 2, 2), 8, 6.0, 12, gaussian_source=True, name="berr_p8")
+    out = gpu_leaf_boxes(prob, range(4), "fp32_ir", ir_max_iter=ir_max_iter, ir_tol=ir_tol, f_on=True)
+    for k in range(4):
+        blk = ol.local_blocks(prob.p, prob.h, prob.kappa, prob.b(out["xi"][k]))
+        A = blk.A_ii
+        B = np.concatenate([blk.A_ib, prob.f(out["xi"][k])[:, None]], axis=1)
+        X = out["X"][k]
+        R = B - A @ X
+        anorm = np.abs(A).sum(axis=1).max()
+        be_all = np.abs(R).max() / (anorm * np.abs(X).max() + np.abs(B).max())
+        be_f = np.abs(R[:, -1]).max() / (anorm * np.abs(X[:, -1]).max() + np.abs(B[:, -1]).max())
+        ref = max(be_all, be_f)
+        say(f"  box {k}: berr {out['berr'][k]:.3e}, host all-columns {be_all:.3e}, load column {be_f:.3e}")
+        if ir_max_iter == 0:
+            assert 0.5 * ref <= out["berr"][k] <= 2.0 * ref
+        else:
+            from paper_2503_04033_amd.leaf import default_ir_tol
+            assert out["berr"][k] <= default_ir_tol(prob.p)
+            assert be_f <= 1e-11
