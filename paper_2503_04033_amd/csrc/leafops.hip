@@ -877,7 +877,9 @@ __global__ void ir_check_kernel(int nbox, int it, int last, double tol, const do
   if (box >= nbox || active[box] == 0) return;
   double be = maxr[box] / (anorm[box] * maxx[box] + maxb[box]);
   if (fst) {  // the load column on its own scale (its entries are far smaller than A_ib's)
-    const double bf = fst[nbox + box] / (anorm[box] * fst[2 * nbox + box] + fst[box]);
+    const double num = fst[nbox + box], den = anorm[box] * fst[2 * nbox + box] + fst[box];
+    // a zero load with a zero solution has nothing to refine (0 / 0 counts as 0)
+    const double bf = num != num ? num : (den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0));
     be = (bf > be || bf != bf) ? bf : be;  // (a NaN stays a NaN)
   }
   if (berr) berr[box] = be;

@@ -491,6 +491,19 @@ def test_workspace_bytes(gpu, precision):
         plan.hps_leaf_workspace_bytes("dtn", -1)
 
 
+def test_zero_load_passed_converges(gpu):
+    # a load that is passed but exactly zero: its column's backward error is 0 / 0, which
+    # counts as converged (every box stops after its usual correction, bitwise the run
+    # without a load)
+    prob = W.multi_bump((2, 2, 2), 8, 6.0, 12, name="zero_load_p8")
+    assert not np.any(prob.f(np.random.default_rng(0).random((5, 3))))
+    withf = gpu_leaf_boxes(prob, range(8), "fp32_ir", f_on=True)
+    nof = gpu_leaf_boxes(prob, range(8), "fp32_ir", f_on=False)
+    assert np.all(withf["iters"] >= 0)
+    for key in ("X", "T", "g", "iters"):
+        assert np.array_equal(withf[key], nof[key]), key
+
+
 @pytest.mark.parametrize("ir_max_iter,ir_tol", [(0, 1e-30), (3, None)])
 def test_berr_includes_load_column(gpu, ir_max_iter, ir_tol):
     # berr is the larger of the backward error over all columns of [A_ib | f] and that of
