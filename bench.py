@@ -420,7 +420,7 @@ def main():
     tot_flops = lu_alg + solve_alg
     KNAMES = {"solve_fwd": "trsm_row128_kernel<float, false, false, 4>", "solve_bwd": "trsm_row128_kernel<float, true, false, 4>",
               "lu_gemm": "gemm_op_kernel<float, true>", "lu_panel": "lu_panel_kernel<float, 3, 16, 64, 1024>",
-              "residual": "residual_mfma_kernel<14, 2, 4, double>"}
+              "residual": "residual_mfma_kernel<14, 2, 4, double, false>"}
     # the LU/TRSM phase: device time of the factorization and solve kernels (events around
     # each launch) against the LU and solve flops of the step, algorithmic and as executed
     # (the first forward sweep skips the structurally zero leading rows of A_ib's columns)
