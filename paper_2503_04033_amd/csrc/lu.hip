@@ -81,6 +81,60 @@ struct LuSmem {
   int cnt[24 * NWV];  // per (row slot r < 24, wave): rows that stay candidates
 };
 
+// DPP lane moves (GFX9 encodings: row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143).  A lane whose source lies outside its row of 16, or whose row
+// ROWS leaves out, gets `id`.
+template <int CTRL, int ROWS = 0xf>
+__device__ inline int dpp_move(int id, int v) {
+  return __builtin_amdgcn_update_dpp(id, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ inline float dpp_move(float id, float v) {
+  return __int_as_float(dpp_move<CTRL, ROWS>(__float_as_int(id), __float_as_int(v)));
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ inline double dpp_move(double id, double v) {
+  const long long a = __double_as_longlong(id), b = __double_as_longlong(v);
+  const int lo = dpp_move<CTRL, ROWS>((int)a, (int)b);
+  const int hi = dpp_move<CTRL, ROWS>((int)(a >> 32), (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Reduction with an associative, commutative op (identity id) over the first row of 16
+// lanes (WAVE false) or over the whole wave, returned in every lane.  Every lane must be
+// active.
+template <bool WAVE, typename V, typename Op>
+__device__ inline V dpp_reduce(V v, V id, Op op) {
+  v = op(v, dpp_move<0x111>(id, v));
+  v = op(v, dpp_move<0x112>(id, v));
+  v = op(v, dpp_move<0x114>(id, v));
+  v = op(v, dpp_move<0x118>(id, v));  // lane 15 of each row: the row's result
+  if constexpr (WAVE) {
+    v = op(v, dpp_move<0x142, 0xa>(id, v));  // lanes 31 and 63: two rows each
+    v = op(v, dpp_move<0x143, 0xc>(id, v));  // lane 63: all four rows
+  }
+  return lane_value(v, WAVE ? 63 : 15);
+}
+
+// The pivot candidate of the lanes (of row 0, or of the wave): the largest modulus, the
+// lowest slot among the lanes that hold it (an empty candidate has modulus -1 and slot
+// 0x7fffffff).  Returned in every lane.
+template <bool WAVE, typename T>
+__device__ inline void argmax_lanes(T& best, int& slot) {
+  // (fmax: the moduli hold no NaN, a NaN entry having been taken as infinity)
+  const T m = dpp_reduce<WAVE>(best, T(-INFINITY), [](T a, T b) { return fmax(a, b); });
+  slot = dpp_reduce<WAVE>(best == m ? slot : 0x7fffffff, 0x7fffffff, [](int a, int b) { return a < b ? a : b; });
+  best = m;
+}
+
 template <typename T> struct Store4;
 template <> struct Store4<float> {
   __device__ static inline void store(float* p, const float* v) {
@@ -187,12 +241,7 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
           if (a > best || (a == best && s < bslot)) { best = a; bslot = s; }
         }
       }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const T ob = __shfl_xor(best, off);
-        const int os = __shfl_xor(bslot, off);
-        if (ob > best || (ob == best && os < bslot)) { best = ob; bslot = os; }
-      }
+      argmax_lanes<true>(best, bslot);  // the wave's candidate, in every lane
       const int buf = c & 1;
       if (bslot == 0x7fffffff) {
         if (lane == 0) { sm.wval[buf][wave] = T(-1); sm.wslot[buf][wave] = bslot; }
@@ -206,15 +255,12 @@ __device__ __attribute__((always_inline)) inline void lu_panel(const Geom& g, T*
             for (int cc = 0; cc < CW; cc++) sm.wrow[buf][wave][cc] = v[r][cc];
       }
       __syncthreads();
-      int wbest = 0;
-      best = sm.wval[buf][0];
-      bslot = sm.wslot[buf][0];
-#pragma unroll
-      for (int w = 1; w < (NT / 64); w++) {
-        const T ob = sm.wval[buf][w];
-        const int os = sm.wslot[buf][w];
-        if (ob > best || (ob == best && os < bslot)) { best = ob; bslot = os; wbest = w; }
-      }
+      // the waves' candidates: lane l of each row reads wave l % (NT / 64), one LDS round trip
+      static_assert(16 % (NT / 64) == 0, "a row of 16 lanes holds every wave's candidate");
+      best = sm.wval[buf][lane % (NT / 64)];
+      bslot = sm.wslot[buf][lane % (NT / 64)];
+      argmax_lanes<false>(best, bslot);
+      const int wbest = bslot == 0x7fffffff ? 0 : (bslot & (NT - 1)) >> 6;  // the winner's wave
       const T* pr = sm.wrow[buf][wbest];
       if ((bslot & (NT - 1)) == tid) {
 #pragma unroll

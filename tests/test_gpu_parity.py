@@ -531,3 +531,81 @@ def test_berr_includes_load_column(gpu, ir_max_iter, ir_tol):
             from paper_2503_04033_amd.leaf import default_ir_tol
             assert out["berr"][k] <= default_ir_tol(prob.p)
             assert be_f <= 1e-11
+
+
+def _lu_rule(A):
+    """Partial pivoting as hps_leaf_factor documents it: in column k the row of largest
+    modulus among the rows not yet pivoted, the lowest current position on ties; the
+    chosen row takes position k and the rows it passes keep their order.  Returns
+    (order, B, ties): order[i] = the row at position i, B[i] = row i of L (below the
+    diagonal) and U, ties = the steps where more than one row had the largest modulus."""
+    B = A.copy()
+    n = len(B)
+    order = np.arange(n)
+    ties = 0
+    for k in range(n):
+        col = np.abs(B[k:, k])
+        j = k + int(np.argmax(col))  # (the first maximum: lowest position)
+        ties += int(np.count_nonzero(col == col[j - k]) > 1)
+        if j != k:
+            B[k:j + 1] = np.roll(B[k:j + 1], 1, axis=0)
+            order[k:j + 1] = np.roll(order[k:j + 1], 1)
+        lk = B[k + 1:, k] / B[k, k]
+        B[k + 1:, k] = lk
+        B[k + 1:, k + 1:] -= np.outer(lk, B[k, k + 1:])
+    return order, B, ties
+
+
+_TIE_REF = {}
+
+
+def _tie_matrix(n, seed):
+    # rows of diag(H_64 (x) I_q, H_32) (H_64 and H_32 the Sylvester-Hadamard matrices, H_32
+    # only where n = 64 q + 32), in a seeded order
+    H = [np.ones((1, 1))]
+    for _ in range(6):
+        H.append(np.block([[H[-1], H[-1]], [H[-1], -H[-1]]]))
+    q, rem = divmod(n, 64)
+    assert rem in (0, 32)
+    A = np.zeros((n, n))
+    A[:64 * q, :64 * q] = np.kron(H[6], np.eye(q))
+    if rem:
+        A[64 * q:, 64 * q:] = H[5]
+    A = A[np.random.default_rng(seed).permutation(n)]
+    if (n, seed) not in _TIE_REF:
+        _TIE_REF[(n, seed)] = _lu_rule(A)
+    return A, _TIE_REF[(n, seed)]
+
+
+@pytest.mark.parametrize("precision,p,threads", [("fp32_ir", 8, None), ("fp64", 8, None), ("fp32_ir", 15, 1024),
+                                                 ("fp32_ir", 15, 512), ("fp64", 15, None)])
+def test_pivot_ties_exact(gpu, precision, p, threads):
+    # A matrix with a tie in modulus at nearly every elimination step whose factors are exact
+    # in any summation order (every entry of L is 0 or +-1, of U an integer up to 64, every
+    # partial sum of products below 2^9 in modulus): the pivot order and the factors must be the rule's
+    # exactly (p = 15: n_pad 2240, the 1024- and 512-thread FP32 panels)
+    from paper_2503_04033_amd.leaf import LeafPlan
+    plan = LeafPlan(p, (0.5, 0.5, 0.5), 5.0, precision)
+    if threads:
+        plan.hps_plan_set_tuning("panel_threads", threads)
+    i = plan.info
+    n, nb = i.n_pad, 2 if p == 8 else 1
+    say(f"case pivot ties p={p} n_pad={n} {precision} panel_threads={threads}")
+    dev = torch.device("cuda")
+    bufs = plan.alloc(nb, dev)
+    mats = [_tie_matrix(n, 7 + k) for k in range(nb)]
+    A = bufs["A"].view(nb, n, n)
+    for k, (Ak, _) in enumerate(mats):
+        A[k].copy_(torch.tensor(Ak, dtype=A.dtype))
+    plan.hps_leaf_factor(nb, bufs["A"], bufs["perm"], bufs["dinv"], bufs["info"])
+    torch.cuda.synchronize()
+    perm = bufs["perm"].view(nb, n).cpu().numpy()
+    LU = A.cpu().numpy().astype(np.float64)
+    assert np.all(bufs["info"].cpu().numpy() == 0)
+    for k, (Ak, (order, B, ties)) in enumerate(mats):
+        say(f"  box {k}: ties at {ties} of {n} steps; pivots equal {np.array_equal(perm[k], order)}, "
+            f"factors equal {np.array_equal(LU[k][perm[k]], B)}")
+        assert ties > 0.9 * n
+        assert np.abs(B).max() <= 64 and np.array_equal(B, np.round(B))  # integer factors
+        assert np.array_equal(perm[k], order)
+        assert np.array_equal(LU[k][perm[k]], B)
