@@ -918,12 +918,41 @@ constexpr int kDtnLd = kDtnCols + 1;       // LDS row stride (doubles)
 
 struct DtnCtx {
   Geom g;
-  const double* gdir;
-  const int* smap;  // this box's 36 slots
   double* T_vals;
   int c, box_nb;    // this lane's column (c < nb + 1 valid), n_b
   bool valid;
+  // fixed per lane, loaded once (no dependent loads behind the line sums): the column's
+  // face is a Dirichlet face (its entries move to the load, times gd); slot[a] = the
+  // block (face a, the column's face) where T is stored, -1 where it is not; qc = the
+  // column's node on its face; dend[side][e] = D[side ? p-1 : 0][e ? p-1 : 0]
+  bool dir_col;
+  double gd;
+  int slot[6], qc;
+  double dend[2][2];
 };
+
+__device__ inline void dtn_ctx_init(DtnCtx& k, const Geom& g, const double* gdir, const int* smap, double* T_vals,
+                                    int c, int mm) {
+  const int nb = g.nb, p = g.p;
+  k.g = g;
+  k.T_vals = T_vals;
+  k.c = c;
+  k.box_nb = nb;
+  k.valid = c <= nb;
+  const int cc = c < nb ? c : 0, b = cc / mm;  // (other lanes read column 0's entries, unused)
+  k.qc = cc - b * mm;
+  k.dir_col = smap[b * 6 + b] < 0;
+  k.gd = gdir ? gdir[cc] : 0.0;
+#pragma unroll
+  for (int a = 0; a < 6; a++) {
+    const int sa = smap[a * 6 + a], sl = smap[a * 6 + b];
+    k.slot[a] = sa >= 0 ? sl : -1;
+  }
+  k.dend[0][0] = g.D[0];
+  k.dend[0][1] = g.D[p - 1];
+  k.dend[1][0] = g.D[(size_t)(p - 1) * p];
+  k.dend[1][1] = g.D[(size_t)(p - 1) * p + p - 1];
+}
 
 // Value of face row (face a, tangential q) at this lane's column from the line sum
 // xs_ = sum_l D[end][l+1] X[line node l][c]; returns the lane's contribution to the
@@ -931,24 +960,17 @@ struct DtnCtx {
 __device__ inline double dtn_entry(const DtnCtx& k, int a, int q, double xs_, int mm) {
   if (!k.valid) return 0.0;
   const Geom& g = k.g;
-  const int axis = a >> 1, side = a & 1, p = g.p;
+  const int axis = a >> 1, side = a & 1;
   const double s1 = g.s1[axis];
-  const double* Dend = g.D + (size_t)(side ? p - 1 : 0) * p;
   const int row_m = 2 * axis * mm + q, row_p = row_m + mm;
   if (k.c == k.box_nb) return side ? -s1 * xs_ : s1 * xs_;  // g = -A_bi v
   double t = side ? -s1 * xs_ : s1 * xs_;                   // -A_bi X_b
   const double sg = side ? s1 : -s1;                        // A_bb: outward derivative ends
-  if (k.c == row_m) t += sg * Dend[0];
-  if (k.c == row_p) t += sg * Dend[p - 1];
-  const int b = k.c / mm, qc = k.c - b * mm;
-  if (k.smap[b * 6 + b] < 0) {  // Dirichlet column: moves to the load
-    const double gd = k.gdir ? k.gdir[k.c] : 0.0;
-    return -t * gd;
-  }
-  if (k.smap[a * 6 + a] >= 0) {
-    const int sl = k.smap[a * 6 + b];
-    if (sl >= 0) k.T_vals[(size_t)sl * mm * mm + (size_t)q * mm + qc] = t;
-  }
+  if (k.c == row_m) t += sg * k.dend[side][0];
+  if (k.c == row_p) t += sg * k.dend[side][1];
+  if (k.dir_col) return -t * k.gd;  // Dirichlet column: moves to the load
+  const int sl = k.slot[a];
+  if (sl >= 0) k.T_vals[(size_t)sl * mm * mm + (size_t)q * mm + k.qc] = t;
   return 0.0;
 }
 
@@ -970,13 +992,7 @@ __global__ __launch_bounds__(256) void dtn_kernel(Geom g, int nbox, int ncb, con
   const int p = g.p, nb = g.nb, ldx = g.ldx;
   const int cl = threadIdx.x & 15, sub = threadIdx.x >> 4;  // column lane, row group
   DtnCtx k;
-  k.g = g;
-  k.gdir = gdir ? gdir + (size_t)box * nb : nullptr;
-  k.smap = slot_map + box * 36;
-  k.T_vals = T_vals;
-  k.c = cb * kDtnCols + cl;
-  k.box_nb = nb;
-  k.valid = k.c <= nb;
+  dtn_ctx_init(k, g, gdir ? gdir + (size_t)box * nb : nullptr, slot_map + box * 36, T_vals, cb * kDtnCols + cl, mm);
   // column c < ldx for every lane (ncb * 16 <= ldx), so loads need no guard; rows past
   // the plane reread its last row
   const double* X = X_all + (size_t)box * g.n_pad * ldx + cb * kDtnCols + cl;
