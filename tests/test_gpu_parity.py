@@ -607,5 +607,6 @@ def test_pivot_ties_exact(gpu, precision, p, threads):
             f"factors equal {np.array_equal(LU[k][perm[k]], B)}")
         assert ties > 0.9 * n
         assert np.abs(B).max() <= 64 and np.array_equal(B, np.round(B))  # integer factors
+        assert np.array_equal((np.tril(B, -1) + np.eye(n)) @ np.triu(B), Ak[order])  # exact
         assert np.array_equal(perm[k], order)
         assert np.array_equal(LU[k][perm[k]], B)

@@ -174,3 +174,24 @@ def test_interface_solver_dense_and_sparse_agree():
         xd, xs = dense.solve(rhs, trans=trans), sparse.solve(rhs, trans=trans)
         assert np.allclose(M @ xd, rhs, atol=1e-10)
         assert np.allclose(xd, xs, atol=1e-10)
+
+
+def test_pivot_rule_reference():
+    # the host elimination that the GPU pivot-rule test compares against: on a matrix without
+    # ties it chooses LAPACK's partial-pivoting rows, and its factors reproduce the matrix
+    import scipy.linalg as sl
+    from tests.test_gpu_parity import _lu_rule, _tie_matrix
+    n = 40
+    A = np.random.default_rng(3).standard_normal((n, n))
+    order, B, ties = _lu_rule(A)
+    assert ties == 0
+    P, L, U = sl.lu(A)  # A = P L U: position i holds row argmax(P[:, i])
+    assert np.array_equal(order, np.argmax(P, axis=0))
+    assert np.allclose(np.tril(B, -1), np.tril(L, -1), atol=1e-12) and np.allclose(np.triu(B), U, atol=1e-12)
+    # and the tie matrix (as at p = 8): ties at nearly every step, exact integer factors, and
+    # the first maximum is taken (the lowest current position)
+    A, (order, B, ties) = _tie_matrix(224, 7)
+    assert ties > 0.9 * 224
+    assert np.array_equal((np.tril(B, -1) + np.eye(224)) @ np.triu(B), A[order])
+    first = np.abs(A[:, 0]) == np.abs(A[:, 0]).max()
+    assert order[0] == np.flatnonzero(first)[0]
